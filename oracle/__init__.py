@@ -1,0 +1,228 @@
+"""ctypes front-end of the plain C oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke``
+and the CPU-baseline leg of ``bench.py``; never by the product package.
+
+Every function takes numpy arrays and the camera / parameter records produced
+by the ``scenes`` input generators and returns numpy arrays.  ``prec`` selects
+the FP32 build (the parity reference) or the FP64 build (finite differences,
+rounding bounds).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class OrcCamera(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class OrcSplatParams(C.Structure):
+    _fields_ = [("sigma_px", C.c_float), ("band_rel", C.c_float), ("z_min", C.c_float),
+                ("r_max_px", C.c_float)]
+
+
+class OrcTsdfParams(C.Structure):
+    _fields_ = [("z_near", C.c_float), ("z_far", C.c_float), ("num_bins", C.c_int32),
+                ("trunc", C.c_float), ("trunc_in_bins", C.c_int32),
+                ("conf_tau", C.c_float), ("conf_scale", C.c_float), ("conf_window", C.c_int32),
+                ("decay", C.c_float), ("weight_cap", C.c_float)]
+
+
+_libs = {}
+
+
+def lib(prec=32):
+    if prec not in _libs:
+        _build.ensure_built()
+        L = C.CDLL(os.path.join(HERE, f"liboracle{prec}.so"))
+        _libs[prec] = L
+    return _libs[prec]
+
+
+def cam(c) -> OrcCamera:
+    p = c.packed()
+    o = OrcCamera()
+    o.fx, o.fy, o.cx, o.cy = (float(v) for v in p[:4])
+    o.R[:] = [float(v) for v in p[4:13]]
+    o.t[:] = [float(v) for v in p[13:16]]
+    o.width, o.height = int(c.width), int(c.height)
+    return o
+
+
+def cams(cs):
+    arr = (OrcCamera * len(cs))()
+    for i, c in enumerate(cs):
+        arr[i] = cam(c)
+    return arr
+
+
+def splat_params(d) -> OrcSplatParams:
+    return OrcSplatParams(d["sigma_px"], d["band_rel"], d["z_min"], d["r_max_px"])
+
+
+def tsdf_params(d) -> OrcTsdfParams:
+    return OrcTsdfParams(d["z_near"], d["z_far"], int(d["num_bins"]), d["trunc"],
+                         int(d["trunc_in_bins"]), d["conf_tau"], d["conf_scale"],
+                         int(d["conf_window"]), d["decay"], d["weight_cap"])
+
+
+def _rt(prec):
+    return np.float32 if prec == 32 else np.float64
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def relproj(a, b):
+    """FP32 (H, c) of the relative projection a -> b."""
+    H = np.zeros(9, np.float32)
+    c = np.zeros(3, np.float32)
+    ca, cb = cam(a), cam(b)
+    lib(32).orc_relproj(C.byref(ca), C.byref(cb), _p(H), _p(c))
+    return H.reshape(3, 3), c
+
+
+def relproj64(a, b):
+    H = np.zeros(9, np.float64)
+    c = np.zeros(3, np.float64)
+    ca, cb = cam(a), cam(b)
+    lib(32).orc_relproj_d(C.byref(ca), C.byref(cb), _p(H), _p(c))
+    return H.reshape(3, 3), c
+
+
+def confidence(depth, tsdf, prec=32):
+    """Per-pixel fusion weight omega of one (H, W) or a stack (K, H, W)."""
+    d = _f32(depth)
+    out = np.zeros(d.shape, _rt(prec))
+    prm = tsdf_params(tsdf)
+    flat = d.reshape(-1, d.shape[-2], d.shape[-1])
+    o = out.reshape(flat.shape)
+    for k in range(flat.shape[0]):
+        lib(prec).orc_confidence(_p(flat[k]), flat.shape[2], flat.shape[1], C.byref(prm), _p(o[k]))
+    return out
+
+
+def bins(tsdf, prec=32):
+    D = int(tsdf["num_bins"])
+    z = np.zeros(D, _rt(prec))
+    tau = np.zeros(D, _rt(prec))
+    lib(prec).orc_bins(C.byref(tsdf_params(tsdf)), _p(z), _p(tau))
+    return z, tau
+
+
+def integrate(src, depth, tgt, tsdf, mask=None, F_prev=None, W_prev=None, pixels=None,
+              conf=None, prec=32):
+    """Fused volume (F, W), shape (npix, D) (all target pixels row-major when
+    ``pixels`` is None)."""
+    rt = _rt(prec)
+    K = len(src)
+    D = int(tsdf["num_bins"])
+    npix = tgt.width * tgt.height if pixels is None else len(pixels)
+    F = np.zeros((npix, D), rt)
+    W = np.zeros((npix, D), rt)
+    d = _f32(depth)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
+    Fp = None if F_prev is None else np.ascontiguousarray(F_prev, rt).reshape(npix, D)
+    Wp = None if W_prev is None else np.ascontiguousarray(W_prev, rt).reshape(npix, D)
+    if (Fp is None) != (Wp is None):
+        raise ValueError("F_prev and W_prev go together")
+    cf = None if conf is None else np.ascontiguousarray(conf, rt)
+    m = None if mask is None else _f32(mask)
+    tc = cam(tgt)
+    rc = lib(prec).orc_integrate(cams(src), K, _p(d), _p(cf), C.byref(tc),
+                                 C.byref(tsdf_params(tsdf)), _p(m), _p(Fp), _p(Wp), _p(F), _p(W),
+                                 _p(pix), 0 if pix is None else len(pix))
+    if rc != 0:
+        raise RuntimeError(f"orc_integrate failed: {rc}")
+    return F, W
+
+
+def extract(F, W, tsdf, prec=32):
+    rt = _rt(prec)
+    D = int(tsdf["num_bins"])
+    F = np.ascontiguousarray(F, rt).reshape(-1, D)
+    W = np.ascontiguousarray(W, rt).reshape(-1, D)
+    n = F.shape[0]
+    depth = np.zeros(n, rt)
+    b = np.zeros(n, np.int32)
+    lib(prec).orc_extract(C.byref(tsdf_params(tsdf)), _p(F), _p(W), n, _p(depth), _p(b))
+    return depth, b
+
+
+def splat(src, depth, rgb, tgt, sp, prec=32):
+    """Per-view splat outputs: win_idx (K,Ht,Wt) int32, depth, rgb (K,3,Ht,Wt),
+    alpha, tape (K,3,Ht,Wt)."""
+    rt = _rt(prec)
+    K = len(src)
+    Ht, Wt = tgt.height, tgt.width
+    win = np.zeros((K, Ht, Wt), np.int32)
+    od = np.zeros((K, Ht, Wt), rt)
+    orgb = np.zeros((K, 3, Ht, Wt), rt)
+    oa = np.zeros((K, Ht, Wt), rt)
+    tape = np.zeros((K, 3, Ht, Wt), rt)
+    d = _f32(depth)
+    c = np.ascontiguousarray(rgb, np.uint8)
+    tc = cam(tgt)
+    rc = lib(prec).orc_splat(cams(src), K, _p(d), _p(c), C.byref(tc), C.byref(splat_params(sp)),
+                             _p(win), _p(od), _p(orgb), _p(oa), _p(tape))
+    if rc != 0:
+        raise RuntimeError(f"orc_splat failed: {rc}")
+    return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=tape)
+
+
+def splat_backward(src, depth, rgb, tgt, sp, g_rgb, g_depth, g_alpha, prec=32):
+    rt = _rt(prec)
+    K = len(src)
+    d = _f32(depth)
+    c = np.ascontiguousarray(rgb, np.uint8)
+    gd = np.zeros(d.shape, rt)
+    gc = np.zeros(d.shape + (3,), rt)
+    tc = cam(tgt)
+    rc = lib(prec).orc_splat_backward(
+        cams(src), K, _p(d), _p(c), C.byref(tc), C.byref(splat_params(sp)),
+        _p(np.ascontiguousarray(g_rgb, rt)), _p(np.ascontiguousarray(g_depth, rt)),
+        _p(np.ascontiguousarray(g_alpha, rt)), _p(gd), _p(gc))
+    if rc != 0:
+        raise RuntimeError(f"orc_splat_backward failed: {rc}")
+    return gd, gc
+
+
+def tsdf_backward(src, depth, tgt, tsdf, g_out, mask=None, F_prev=None, W_prev=None, prec=32):
+    rt = _rt(prec)
+    K = len(src)
+    d = _f32(depth)
+    gd = np.zeros(d.shape, rt)
+    D = int(tsdf["num_bins"])
+    npix = tgt.width * tgt.height
+    Fp = None if F_prev is None else np.ascontiguousarray(F_prev, rt).reshape(npix, D)
+    Wp = None if W_prev is None else np.ascontiguousarray(W_prev, rt).reshape(npix, D)
+    m = None if mask is None else _f32(mask)
+    tc = cam(tgt)
+    rc = lib(prec).orc_tsdf_backward(cams(src), K, _p(d), C.byref(tc), C.byref(tsdf_params(tsdf)),
+                                     _p(m), _p(Fp), _p(Wp), _p(np.ascontiguousarray(g_out, rt)),
+                                     _p(gd))
+    if rc != 0:
+        raise RuntimeError(f"orc_tsdf_backward failed: {rc}")
+    return gd
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use in this process."""
+    import multiprocessing
+    env = os.environ.get("OMP_NUM_THREADS")
+    return int(env) if env else multiprocessing.cpu_count()

@@ -1,0 +1,77 @@
+"""The pins are strong enough: each plausible mistake planted in a copy of the
+oracle (a flipped sign, a dropped term, a transposed operand, a wrong index)
+makes at least one pin fail.  Mutants are built into a temporary directory on
+the CPU; the repository's oracle is never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (name, original text, mutated text, pin files expected to catch it)
+PINS = "tests/test_oracle_pins.py"
+GRADS = "tests/test_oracle_gradients.py"
+MUTANTS = [
+    ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
+     "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
+    ("no_occlusion_cut", "if (s < -tau) continue; /* occluded in view k */", "", PINS),
+    ("transposed_rotation", "(double)b->R[3 * r + 0] * (double)a->R[3 * k + 0]",
+     "(double)b->R[3 * r + 0] * (double)a->R[0 + k]", PINS),
+    ("pixel_corner_not_centre",
+     "ray_of(Hk[k], (real)x + (real)0.5, (real)y + (real)0.5, h[k]);",
+     "ray_of(Hk[k], (real)x, (real)y + (real)0.5, h[k]);", PINS),
+    ("window_divisor_dropped", "RSQRT(nu / n2)", "RSQRT(nu)", PINS),
+    ("hole_neighbour_free", "          } else {\n            term = tw2;",
+     "          } else {\n            term = 0;", PINS),
+    ("no_decay", "RMIN((decay * W_prev[o]) * m, cap)", "RMIN((W_prev[o]) * m, cap)", PINS),
+    ("no_cap", "RMIN((decay * W_prev[o]) * m, cap)", "((decay * W_prev[o]) * m)", PINS),
+    ("unnormalised_F", "F[o] = (Wn > 0) ? RFMA(wp, Fp, S) / Wn : (real)0;",
+     "F[o] = (Wn > 0) ? RFMA(wp, Fp, S) : (real)0;", PINS),
+    ("no_clamp", "const real cval = RMIN(s, tau);\n        const real w = conf[ns * k + q];\n        S",
+     "const real cval = s;\n        const real w = conf[ns * k + q];\n        S", PINS),
+    ("crossing_strict", "f[d] > 0 && f[d + 1] <= 0", "f[d] > 0 && f[d + 1] < 0", PINS),
+    ("interpolation_flipped", "depth[n] = zb[d] + (zb[d + 1] - zb[d]) * frac;",
+     "depth[n] = zb[d] + (zb[d + 1] - zb[d]) * (1 - frac);", PINS),
+    ("bin_step", "const real du = (un - uf) / (real)(D - 1);",
+     "const real du = (un - uf) / (real)(D);", PINS),
+    ("truncation_width", "((real)p->trunc * du) * (z[d] * z[d])", "((real)p->trunc * du) * (z[d])",
+     PINS),
+    ("coverage_radius", "g->R2 = RMIN((real)2 * g->s2, rmax2);", "g->R2 = RMIN(g->s2, rmax2);", PINS),
+    ("no_band", "if (!(g.z <= zwin[p] * band)) continue;", "if (!(g.z <= zwin[p])) continue;", PINS),
+    ("gaussian_scale", "const real G = REXP(((real)-0.5 * d2) / g.s2);\n            nrm[p]",
+     "const real G = REXP(((real)-1 * d2) / g.s2);\n            nrm[p]", PINS),
+    ("alpha_complement", "out_alpha[o] = (real)1 - prod[p];", "out_alpha[o] = prod[p];", PINS),
+    ("focal_ratio_dropped",
+     "(real)((double)sp->sigma_px * (double)tgt->fx / (double)src[k].fx);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    real *prgb",
+     "(real)((double)sp->sigma_px);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    real *prgb",
+     PINS),
+    ("grad_clamp_ignored", "if (s < tau) g_depth_in[ns * k + q] += gF[e] * w / Wn;",
+     "g_depth_in[ns * k + q] += gF[e] * w / Wn;", GRADS),
+    ("grad_neighbour_term", "g_depth_in[ns * k + n] -= gnu * (real)2 * dd;", "", GRADS),
+    ("grad_alpha_term", "dLdG += g_alpha[o] * others;", "", GRADS),
+    ("grad_footprint_term", "d2 * dsdD / (sig * g.s2)", "0", GRADS),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,mut,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, orig, mut, pins, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert src.count(orig) >= 1, "mutation site not found"
+    root = tmp_path / "root"
+    shutil.copytree(os.path.join(ROOT, "oracle"), root / "oracle",
+                    ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
+    (root / "oracle" / "oracle.c").write_text(src.replace(orig, mut, 1))
+    subprocess.run([sys.executable, str(root / "oracle" / "build.py")], check=True,
+                   capture_output=True)
+    os.symlink(os.path.join(ROOT, "scenes"), root / "scenes")
+    shutil.copytree(os.path.join(ROOT, "tests"), root / "tests",
+                    ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
+    env = dict(os.environ, PYTHONPATH=str(root), PYTHONDONTWRITEBYTECODE="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "-m", "not gpu", pins], cwd=root, env=env, capture_output=True, text=True)
+    assert r.returncode == 1, f"mutant {name} survived:\n{r.stdout[-2000:]}"
