@@ -1,0 +1,241 @@
+"""Throughput of the geometry stage on one MI355X.
+
+Workload (the metric's configuration): a 16-camera ring (radius 1 m, aimed
+inward), K = 4 input views of 1280x720 FP32 depth + uint8 RGB, target view
+between two ring cameras, D = 128 inverse-depth bins over 0.5-5 m, truncation
+4 bins, decay 0.9, weight cap 32; a 30-frame sequence of 5 moving spheres over
+a textured floor, 1% depth noise, 2% holes.  All 30 frames are resident in HBM
+before timing starts.  One step = one frame of the whole hot path:
+splat_views (K views into the target) + tsdf_integrate (fusion weight map,
+fusion into the carried 1280x720x128 volume, fused zero-crossing extraction).
+
+Prints one JSON line: target-view Mpix/s, the roofline of the dominant kernel
+(the fusion) measured with HIP events inside the timed region, the
+backward/forward time ratio on the differentiation workload, and the CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import scenes  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+WORKLOAD = "video ring K=4 1280x720 D=128 (30 frames, carried volume)"
+
+
+def _frame(t):
+    c = scenes.config2(seed=0)
+    return c["seq"].frame(t)
+
+
+def make_frames(n, procs):
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            out = pool.map(_frame, range(n))
+    else:
+        out = [_frame(t) for t in range(n)]
+    return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for name in ("tsdf.hip", "ggeom_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2505_18932_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """Per-launch HBM bytes of the fusion kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "integrate_video_1280x720_K4_D128_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_sha():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=4):
+    """The CPU oracle (plain C, OpenMP) on the same workload: whole frames
+    (splat + fusion with carry + extraction) until the time budget is used."""
+    import oracle
+
+    t0 = time.perf_counter()
+    F = W = None
+    frames = 0
+    while frames < max_frames:
+        oracle.splat(c["src"], depth[frames], rgb[frames], c["tgt"], c["splat"])
+        F, W = oracle.integrate(c["src"], depth[frames], c["tgt"], c["tsdf"], F_prev=F, W_prev=W)
+        oracle.extract(F, W, c["tsdf"])
+        frames += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    npix = c["tgt"].width * c["tgt"].height
+    return {"value": round(frames * npix / el / 1e6, 4), "unit": "Mpix/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{frames} full frame(s) of the same sequence (splat + fusion + "
+                      f"extraction), {el:.1f} s"}
+
+
+def bwd_fwd_ratio(gg, torch, dev, reps=10):
+    """Backward / forward time on the differentiation workload (640x360,
+    K=4, D=96): forward = splat + fusion + extraction, backward = the three
+    adjoints for random upstream gradients."""
+    c = scenes.config3()
+    depth = torch.from_numpy(c["depth"]).to(dev)
+    rgb = torch.from_numpy(c["rgb"]).to(dev)
+
+    def fwd():
+        o = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+        F, W, d, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+        return o, F, W, d, b
+
+    o, F, W, d, b = fwd()
+    g_rgb, g_z, g_a = (torch.randn_like(o["rgb"]), torch.randn_like(o["depth"]),
+                       torch.randn_like(o["alpha"]))
+    gdep = torch.randn_like(d)
+
+    def bwd():
+        gg.splat_views_backward(c["src"], depth, rgb, c["tgt"], c["splat"], o, g_rgb, g_z, g_a)
+        g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, gdep)
+        gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
+
+    for _ in range(3):
+        fwd()
+        bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fwd()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bwd()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    return tb / tf, tf * 1e3, tb * 1e3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the geometry stage on a single "
+              "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    procs = max(1, min(16, os.cpu_count() or 1))
+    depth_h, rgb_h = make_frames(args.frames, procs)
+    print(f"# frames generated: {depth_h.shape}", file=sys.stderr, flush=True)
+
+    import torch
+
+    import paper_2505_18932_amd as gg
+
+    dev = torch.device("cuda:0")
+    c = scenes.config2(seed=0)
+    src, tgt = gg.cameras(c["src"]), gg.camera(c["tgt"])
+    sp, tp = gg.splat_params(c["splat"]), gg.tsdf_params(c["tsdf"])
+    K, H, Wd, D = 4, tgt.height, tgt.width, tp.num_bins
+    depth = torch.from_numpy(depth_h).to(dev)
+    rgb = torch.from_numpy(rgb_h).to(dev)
+    F = torch.zeros((H, Wd, D), dtype=torch.float32, device=dev)
+    Wv = torch.zeros((H, Wd, D), dtype=torch.float32, device=dev)
+    ws_s = torch.empty(gg.workspace_size(1, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8, device=dev)
+    ws_t = torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
+    sout = dict(win_idx=torch.empty((K, H, Wd), dtype=torch.int32, device=dev),
+                depth=torch.empty((K, H, Wd), device=dev), rgb=torch.empty((K, 3, H, Wd), device=dev),
+                alpha=torch.empty((K, H, Wd), device=dev), tape=torch.empty((K, 3, H, Wd), device=dev))
+    nf = args.frames
+
+    def step(i, carry=True):
+        f = i % nf
+        gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s)
+        return gg.tsdf_integrate(src, depth[f], tgt, tp, F_prev=F if carry else None,
+                                 W_prev=Wv if carry else None, F=F, W=Wv, ws=ws_t)
+
+    step(0, carry=False)
+    for i in range(1, args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    gg.timing_reset()
+    gg.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gg.timing_enable(False)
+    kt = {}
+    for name in ("integrate", "conf", "bins", "splat_count", "splat_fill", "splat_raster",
+                 "splat_scan", "splat_zero"):
+        ms, n = gg.timing_read(name)
+        kt[name] = (ms, n)
+    ms_per_step = el * 1e3 / args.steps
+    value = args.steps * H * Wd / el / 1e6
+
+    # roofline of the fusion kernel: algorithmic bytes per launch
+    ns = H * Wd
+    vox = H * Wd * D
+    alg = vox * 16 + K * ns * 8 + ns * 8  # F, W read+write; view-table gather; extraction out
+    int_ms = kt["integrate"][0] / max(kt["integrate"][1], 1)
+    achieved = alg / (int_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
+            "kernel": "integrate_kernel<4>", "kernel_ms": round(int_ms, 4),
+            "algorithmic_bytes_per_launch": alg}
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "target-view Mpix/s (splat+TSDF+extract, K=4, 1280x720, D=128)",
+        "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "K": K, "width": Wd, "height": H, "bins": D,
+                   "frames_resident": nf},
+        "roofline": roof,
+        "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()},
+    }
+    if not args.no_bwd:
+        r, tf, tb = bwd_fwd_ratio(gg, torch, dev)
+        out["bwd_fwd"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3), "bwd_ms": round(tb, 3),
+                          "workload": "differentiation 640x360 K=4 D=96"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, depth_h, rgb_h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * ggeom.h -- C ABI of the MI355X geometry stage of "Geometry-guided Online 3D
+ * Video Synthesis with Multi-View Temporal Consistency" (arXiv 2505.18932):
+ * forward splatting of K RGB-D views into a target camera, fusion of their
+ * depths into a truncated signed distance field held as an H x W x D frustum
+ * volume in the target's image space, carried across frames with a running
+ * weight, and zero-crossing extraction of one depth per pixel; plus adjoints
+ * and a batched path.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Cameras: world -> camera x_c = R x_w + t (R row-major), intrinsics
+ *   K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]]; the projection of a world point
+ *   p into camera k is (x_k, y_k, z_k) = K_k (R_k p + t_k) and its pixel
+ *   coordinates are (x_k / z_k, y_k / z_k) (paper, Suppl. A.1).  Pixel (i, j)
+ *   is column i, row j, with its centre at (i + 0.5, j + 0.5); it samples the
+ *   area [i, i+1) x [j, j+1).  Depth is camera-frame z in metres; a depth
+ *   sample is usable iff it is > 0 and finite (holes are 0).
+ * Memory: every array pointer is a DEVICE pointer on the current HIP device,
+ *   owned by the caller, unless marked [host].  Images are row-major, one view
+ *   after the other (view-major).  Volumes are H x W x D with D innermost.
+ * Streams: `stream` is a hipStream_t (NULL: the default stream).  All work is
+ *   enqueued on it; a return value of GG_OK means "enqueued".  Kernel faults
+ *   surface at the caller's next synchronisation.
+ * Workspace: scratch comes from the caller's `ws` buffer of `ws_bytes` bytes
+ *   (device memory, 256-byte aligned); gg_workspace_size() gives the size.
+ *   These calls never allocate device memory.  Workspace contents need not be
+ *   initialised and are clobbered.
+ * Errors: 0 on success; a negative GG_ERR_* code otherwise, with a message
+ *   readable through gg_last_error() (thread-local).  Invalid arguments are
+ *   detected before anything is enqueued.  Nothing throws across the ABI.
+ * Aliasing: outputs never alias inputs, except F / W, which may alias
+ *   F_prev / W_prev (in-place temporal update).
+ * Determinism: every output is bitwise reproducible run to run; integer
+ *   outputs (winner indices, bins) and the volume F / W are bitwise equal to
+ *   the plain FP32 definition (no contraction, correctly rounded divide and
+ *   square root, floor for pixel indices, ties broken by the smaller index).
+ */
+#ifndef GGEOM_H
+#define GGEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GG_OK 0
+#define GG_ERR_INVALID (-1)     /* an argument is out of range or NULL          */
+#define GG_ERR_WORKSPACE (-2)   /* ws is NULL or ws_bytes too small             */
+#define GG_ERR_HIP (-3)         /* a HIP runtime call or launch failed          */
+#define GG_ERR_UNSUPPORTED (-4) /* valid but beyond this build's limits         */
+
+#define GG_MAX_VIEWS 16     /* K per call                                    */
+#define GG_MAX_BINS 4096    /* D per volume                                  */
+#define GG_MAX_WINDOW 15    /* confidence window side                        */
+
+/* Pinhole camera (Suppl. A.1 projection).  width/height in pixels. */
+typedef struct gg_camera {
+  float fx, fy, cx, cy;
+  float R[9]; /* world -> camera rotation, row-major */
+  float t[3]; /* world -> camera translation          */
+  int32_t width, height;
+} gg_camera;
+
+/* Pixel-Gaussian splat (§3.1, Suppl. A.3).  Each input pixel is an isotropic
+ * opaque Gaussian whose source-image footprint is one pixel. */
+typedef struct gg_splat_params {
+  float sigma_px; /* std of the Gaussian in source pixels (0.5: one-pixel footprint) */
+  float band_rel; /* blend band: splats with z <= z_winner * (1 + band_rel), >= 0  */
+  float z_min;    /* splats with target depth <= z_min are dropped, >= 0            */
+  float r_max_px; /* cap on the coverage radius in target pixels, in (0, 64]        */
+} gg_splat_params;
+
+/* Frustum-volume TSDF (Suppl. A.1, A.2). */
+typedef struct gg_tsdf_params {
+  float z_near, z_far;   /* depth range; bins uniform in 1/z, z_0 = z_near, 0 < near < far */
+  int32_t num_bins;      /* D, 2 .. GG_MAX_BINS                                          */
+  float trunc;           /* truncation: metres, or bins if trunc_in_bins                 */
+  int32_t trunc_in_bins; /* 1: tau_d = trunc * du * z_d^2 (local metric width of bins)   */
+  float conf_tau;        /* tau of the window statistic nu (Suppl. A.1: 0.02 m)          */
+  float conf_scale;      /* scale of the fusion weight (Suppl. A.1: 0.001)               */
+  int32_t conf_window;   /* w, odd, 1 .. GG_MAX_WINDOW (Suppl. A.1: 7)                   */
+  float decay;           /* beta of Suppl. A.2, weight carried per frame, in [0, 1]      */
+  float weight_cap;      /* eta of Suppl. A.2, cap on the carried weight, >= 0           */
+} gg_tsdf_params;
+
+/* Operations for gg_workspace_size(). */
+enum {
+  GG_OP_SPLAT = 1,
+  GG_OP_SPLAT_BACKWARD = 2,
+  GG_OP_TSDF_INTEGRATE = 3,
+  GG_OP_TSDF_INTEGRATE_BACKWARD = 4
+};
+
+/* Bytes of workspace `op` needs for K source views of src_w x src_h pixels, a
+ * tgt_w x tgt_h target and D bins (sp: splat parameters, [host], needed by the
+ * splat ops, may be NULL otherwise).  Returns 0 on invalid arguments. */
+size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_t tgt_w,
+                         int32_t tgt_h, int32_t num_bins, const gg_splat_params *sp);
+
+/* ---------------------------------------------------------------------------
+ * splat_views -- forward rendering of per-pixel Gaussians (§3.1; Suppl. A.3),
+ * each view into its own target images, z-buffered.
+ *
+ * Source pixel q = (i, j) of view k with usable depth D is moved to the target
+ * (x_T, y_T, z_T) = K_T (R_T p + t_T), p its world point; it is dropped unless
+ * z_T > z_min.  Centre (x, y) = (x_T, y_T) / z_T, target std
+ * sigma = sigma_px * (fx_T / fx_k) * (D / z_T), coverage radius^2
+ * R2 = min(2 sigma^2, r_max^2).  Target pixel p is covered iff its centre lies
+ * within R2 of (x, y).  The winner of p is the covering splat with the
+ * smallest (z_T, q); its band is every covering splat with
+ * z_T <= z_win * (1 + band_rel).  With G = exp(-d^2 / (2 sigma^2)) and
+ * colour c = rgb / 255: out_rgb = sum G c / sum G over the band,
+ * out_alpha = 1 - prod (1 - G) (accumulated opacity), out_depth = z_win,
+ * win_idx = q_win = j * src_w + i.  Uncovered pixels: -1, 0, 0, 0.
+ *
+ * src [host] K cameras, all of one size src_w x src_h; K in 1..GG_MAX_VIEWS.
+ * depth  float  K x src_h x src_w            rgb uint8 K x src_h x src_w x 3
+ * tgt [host] target camera (tgt_w x tgt_h).  prm [host].
+ * win_idx int32 K x tgt_h x tgt_w             out_depth float K x tgt_h x tgt_w
+ * out_rgb float K x 3 x tgt_h x tgt_w (planar) out_alpha float K x tgt_h x tgt_w
+ * out_tape float K x 3 x tgt_h x tgt_w or NULL: per pixel sum G, the sum of
+ *   log(1 - G) over band members with G < 1, and the count of G == 1 (what
+ *   splat_views_backward needs).
+ * Colour and opacity are accumulated in 64-bit fixed point, so they are
+ * independent of the order splats arrive in; they equal the sequential FP32
+ * sums to ~1e-7 relative.
+ * ------------------------------------------------------------------------- */
+int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                const gg_camera *tgt, const gg_splat_params *prm, int32_t *win_idx,
+                float *out_depth, float *out_rgb, float *out_alpha, float *out_tape, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* Adjoint of splat_views with respect to source depth and colour, for the
+ * loss L = <g_rgb, out_rgb> + <g_depth, out_depth> + <g_alpha, out_alpha>.
+ * Coverage, band and winner are held fixed (piecewise differentiation).
+ * Inputs as splat_views plus its outputs win_idx, out_depth, out_rgb and
+ * out_tape (required here).  g_rgb / g_depth / g_alpha: same shapes as
+ * out_rgb / out_depth / out_alpha (any may be NULL = zero).
+ * g_depth_in float K x src_h x src_w, g_rgb_in float K x src_h x src_w x 3
+ * (gradient with respect to c = rgb / 255): overwritten.  Gather formulation
+ * (one thread per source pixel), so it needs no atomics; ws may be NULL. */
+int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
+                         const uint8_t *rgb, const gg_camera *tgt, const gg_splat_params *prm,
+                         const int32_t *win_idx, const float *out_depth, const float *out_rgb,
+                         const float *out_tape, const float *g_rgb, const float *g_depth,
+                         const float *g_alpha, float *g_depth_in, float *g_rgb_in, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * tsdf_integrate -- fuse K depth maps into the target's frustum volume
+ * (Suppl. A.1) with the temporal weight of Suppl. A.2 carried per voxel.
+ *
+ * Bins: un = 1/z_near, uf = 1/z_far, du = (un - uf)/(D - 1),
+ *   z_d = 1 / (un - d du); tau_d = trunc * du * z_d^2 if trunc_in_bins else
+ *   trunc.
+ * Fusion weight per source pixel (Suppl. A.1): nu = sum over the w x w window
+ *   (row-major) of min((D_q - D_n)^2, conf_tau^2); out-of-image neighbours are
+ *   skipped, hole neighbours add conf_tau^2; omega = 1 if nu == 0 else
+ *   min(conf_scale / sqrt(nu / w^2), 1); holes have omega = 0.
+ * Voxel (x, y, d): for k = 0 .. K-1, project the point at depth z_d on the
+ *   ray of pixel (x, y) into view k; skip unless z_k > 0; sample the pixel
+ *   (floor(x_k / z_k), floor(y_k / z_k)) (skip if outside or a hole);
+ *   s = D_k - z_k (positive in front of the surface); skip if s < -tau_d;
+ *   S += omega * min(s, tau_d); Wo += omega.
+ * Temporal: m = max(1 - mask, 0) (1 without a mask); with a previous volume,
+ *   w_tmp = min(decay * W_prev * m, weight_cap), else 0;
+ *   W = w_tmp + Wo; F = (w_tmp F_prev + S) / W, or 0 where W == 0.
+ * Extraction (when out_depth is not NULL): as tsdf_extract_depth, fused.
+ *
+ * depth float K x src_h x src_w.  temporal_mask float tgt_h x tgt_w or NULL.
+ * F_prev, W_prev float tgt_h x tgt_w x D or both NULL (no carry); they may
+ * alias F, W.  F, W float tgt_h x tgt_w x D: overwritten.
+ * out_depth float tgt_h x tgt_w, out_bin int32 tgt_h x tgt_w: both or neither.
+ * ------------------------------------------------------------------------- */
+int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
+                   const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
+                   const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* tsdf_extract_depth -- the surface is where the fused signed distance
+ * changes sign along the ray (Suppl. A.1).  On the bins: d* = the smallest
+ * d in [0, D-2] with W_d > 0, W_{d+1} > 0, F_d > 0 and F_{d+1} <= 0;
+ * out_depth = z_d + (z_{d+1} - z_d) F_d / (F_d - F_{d+1}), out_bin = d*;
+ * no crossing: 0 and -1.  F, W float tgt_h x tgt_w x D. */
+int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
+                       const float *W, float *out_depth, int32_t *out_bin, void *stream);
+
+/* Adjoint of tsdf_extract_depth: for L = <g_depth, out_depth>,
+ * g_F2[p] = (dL/dF_{d*}, dL/dF_{d*+1}) at the pixel's crossing (0, 0 where
+ * bin < 0).  bin: the out_bin of the forward.  g_F2 float tgt_h x tgt_w x 2. */
+int tsdf_extract_depth_backward(const gg_camera *tgt, const gg_tsdf_params *prm,
+                                const float *F, const float *W, const int32_t *bin,
+                                const float *g_depth, float *g_F2, void *stream);
+
+/* Adjoint of tsdf_integrate with respect to the input depths, given the
+ * gradient g_F2 on the two voxels per pixel that extraction read (d*, d*+1;
+ * pixels with bin < 0 carry none).  The per-view terms of those voxels are
+ * recomputed from the inputs and the post-update F, W (nothing per voxel is
+ * stored between forward and backward).  No gradient reaches F_prev, W_prev,
+ * the mask or the cameras.  Discrete choices (sampled pixel, occlusion,
+ * clamp, the min of the fusion weight) are held fixed.
+ * Arguments as tsdf_integrate, with F, W the forward's outputs (call before
+ * the next frame overwrites them), bin its out_bin; g_depth_in float
+ * K x src_h x src_w is overwritten.  Scatter uses 64-bit fixed-point atomics
+ * with a data-derived scale, so the result is deterministic. */
+int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
+                            const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
+                            const float *W, const int32_t *bin, const float *g_F2,
+                            float *g_depth_in, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Utilities.
+ * ------------------------------------------------------------------------- */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *gg_last_error(void);
+
+/* The relative projection a -> b [host, no GPU work]: a pixel centre
+ * (px, py) of camera a at camera-a depth z maps to
+ * (x_b, y_b, z_b) = z * H (px, py, 1)^T + c  (exact in real arithmetic),
+ * H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a), formed in FP64
+ * and rounded to FP32 once.  H [host] 9 floats row-major, c [host] 3. */
+int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c);
+
+/* Launch shape of the volume kernels (tsdf_integrate, tsdf_extract_depth):
+ * whole target pixels per workgroup, each thread holding up to 4 consecutive
+ * bins.  0 restores the default (256 threads' worth of pixels).  Results do
+ * not depend on the choice; it exists for the autotuner.  Process-wide. */
+int gg_set_volume_tile(int pixels_per_block);
+
+/* Kernel timing for profiling: when enabled, every kernel the library
+ * launches is bracketed by HIP events on its stream.  gg_timing_read
+ * synchronises on the recorded events and returns the summed milliseconds
+ * and the number of launches of kernels whose name contains `name` (all if
+ * NULL) since the last gg_timing_reset. */
+int gg_timing_enable(int on);
+int gg_timing_reset(void);
+int gg_timing_read(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GGEOM_H */

@@ -1,0 +1,618 @@
+// C ABI of the geometry stage: argument validation (before anything is
+// enqueued), workspace layout, the relative projection of camera pairs, and
+// the launches.  See include/ggeom.h for the contract of each entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ggeom_internal.h"
+
+namespace gg {
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return GG_OK;
+  return fail(GG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+
+namespace {
+struct TimedLaunch {
+  std::string name;
+  hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_launches;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), stream_(s), slot_(-1) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_timing) return;
+  TimedLaunch t{name, take_event(), take_event()};
+  if (!t.start || !t.stop) return;
+  if (hipEventRecord(t.start, s) != hipSuccess) return;
+  g_launches.push_back(t);
+  slot_ = (int)g_launches.size() - 1;
+}
+
+KernelTimer::~KernelTimer() {
+  if (slot_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (slot_ < (int)g_launches.size()) (void)hipEventRecord(g_launches[slot_].stop, stream_);
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+
+// m = floor(2^32 / d) (2^32 - 1 for d = 1) underestimates n / d by less
+// than one for every n < 2^32, which the single correction in fdiv() fixes.
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.s = 0;
+  f.m = d <= 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / d);
+  return f;
+}
+
+// H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a), in FP64 in this
+// order, rounded once to FP32.
+void relproj(const gg_camera &a, const gg_camera &b, Proj &out) {
+  double M[3][3], e[3], A[3][3], H[9], c[3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      M[r][k] = ((double)b.R[3 * r + 0] * (double)a.R[3 * k + 0] +
+                 (double)b.R[3 * r + 1] * (double)a.R[3 * k + 1]) +
+                (double)b.R[3 * r + 2] * (double)a.R[3 * k + 2];
+  for (int r = 0; r < 3; ++r)
+    e[r] = (double)b.t[r] -
+           ((M[r][0] * (double)a.t[0] + M[r][1] * (double)a.t[1]) + M[r][2] * (double)a.t[2]);
+  for (int k = 0; k < 3; ++k) {
+    A[0][k] = (double)b.fx * M[0][k] + (double)b.cx * M[2][k];
+    A[1][k] = (double)b.fy * M[1][k] + (double)b.cy * M[2][k];
+    A[2][k] = M[2][k];
+  }
+  c[0] = (double)b.fx * e[0] + (double)b.cx * e[2];
+  c[1] = (double)b.fy * e[1] + (double)b.cy * e[2];
+  c[2] = e[2];
+  for (int r = 0; r < 3; ++r) {
+    const double h0 = A[r][0] / (double)a.fx;
+    const double h1 = A[r][1] / (double)a.fy;
+    H[3 * r + 0] = h0;
+    H[3 * r + 1] = h1;
+    H[3 * r + 2] = (A[r][2] - h0 * (double)a.cx) - h1 * (double)a.cy;
+  }
+  for (int i = 0; i < 9; ++i) out.H[i] = (float)H[i];
+  for (int i = 0; i < 3; ++i) out.c[i] = (float)c[i];
+}
+
+static bool finite_f(float v) { return std::isfinite(v); }
+
+static int check_camera(const gg_camera *c, const char *what) {
+  if (!c) return fail(GG_ERR_INVALID, "%s: camera is NULL", what);
+  if (!(c->fx > 0.0f) || !(c->fy > 0.0f) || !finite_f(c->fx) || !finite_f(c->fy) ||
+      !finite_f(c->cx) || !finite_f(c->cy))
+    return fail(GG_ERR_INVALID, "%s: intrinsics must be finite with fx, fy > 0", what);
+  for (float v : c->R)
+    if (!finite_f(v)) return fail(GG_ERR_INVALID, "%s: rotation is not finite", what);
+  for (float v : c->t)
+    if (!finite_f(v)) return fail(GG_ERR_INVALID, "%s: translation is not finite", what);
+  if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+    return fail(GG_ERR_INVALID, "%s: size %dx%d outside 1..16384", what, c->width, c->height);
+  return GG_OK;
+}
+
+static int check_sources(const gg_camera *src, int32_t K, const char *what) {
+  if (!src) return fail(GG_ERR_INVALID, "%s: src is NULL", what);
+  if (K < 1) return fail(GG_ERR_INVALID, "%s: K = %d, need K >= 1", what, K);
+  if (K > GG_MAX_VIEWS)
+    return fail(GG_ERR_UNSUPPORTED, "%s: K = %d exceeds %d views", what, K, GG_MAX_VIEWS);
+  for (int k = 0; k < K; ++k) {
+    if (int rc = check_camera(&src[k], what)) return rc;
+    if (src[k].width != src[0].width || src[k].height != src[0].height)
+      return fail(GG_ERR_INVALID, "%s: source views differ in size", what);
+  }
+  return GG_OK;
+}
+
+static int check_tsdf(const gg_tsdf_params *p, const char *what) {
+  if (!p) return fail(GG_ERR_INVALID, "%s: params NULL", what);
+  if (!(p->z_near > 0.0f) || !(p->z_far > p->z_near) || !finite_f(p->z_far))
+    return fail(GG_ERR_INVALID, "%s: need 0 < z_near < z_far < inf", what);
+  if (p->num_bins < 2) return fail(GG_ERR_INVALID, "%s: num_bins = %d < 2", what, p->num_bins);
+  if (p->num_bins > GG_MAX_BINS)
+    return fail(GG_ERR_UNSUPPORTED, "%s: num_bins = %d > %d", what, p->num_bins, GG_MAX_BINS);
+  if (!(p->trunc > 0.0f) || !finite_f(p->trunc))
+    return fail(GG_ERR_INVALID, "%s: trunc must be > 0", what);
+  if (!(p->conf_tau >= 0.0f) || !(p->conf_scale >= 0.0f) || !finite_f(p->conf_tau) ||
+      !finite_f(p->conf_scale))
+    return fail(GG_ERR_INVALID, "%s: conf_tau, conf_scale must be >= 0", what);
+  if (p->conf_window < 1 || p->conf_window % 2 == 0 || p->conf_window > GG_MAX_WINDOW)
+    return fail(GG_ERR_INVALID, "%s: conf_window must be odd in 1..%d", what, GG_MAX_WINDOW);
+  if (!(p->decay >= 0.0f && p->decay <= 1.0f) || !(p->weight_cap >= 0.0f) ||
+      !finite_f(p->weight_cap))
+    return fail(GG_ERR_INVALID, "%s: need decay in [0,1], weight_cap >= 0", what);
+  return GG_OK;
+}
+
+static int check_splat(const gg_splat_params *p, const char *what) {
+  if (!p) return fail(GG_ERR_INVALID, "%s: params NULL", what);
+  if (!(p->sigma_px > 0.0f) || !finite_f(p->sigma_px))
+    return fail(GG_ERR_INVALID, "%s: sigma_px must be > 0", what);
+  if (!(p->band_rel >= 0.0f) || !finite_f(p->band_rel))
+    return fail(GG_ERR_INVALID, "%s: band_rel must be >= 0", what);
+  if (!(p->z_min >= 0.0f) || !finite_f(p->z_min))
+    return fail(GG_ERR_INVALID, "%s: z_min must be >= 0", what);
+  if (!(p->r_max_px > 0.0f) || !(p->r_max_px <= 64.0f))
+    return fail(GG_ERR_INVALID, "%s: r_max_px must be in (0, 64]", what);
+  return GG_OK;
+}
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+
+struct SplatLayout {
+  uint32_t ntx, nty, ntiles, cap;
+  size_t count, offset, cursor, list, total;
+};
+
+static SplatLayout splat_layout(int K, int sw, int sh, int tw, int th, const gg_splat_params *sp) {
+  SplatLayout L{};
+  L.ntx = (uint32_t)((tw + kTile - 1) / kTile);
+  L.nty = (uint32_t)((th + kTile - 1) / kTile);
+  L.ntiles = L.ntx * L.nty;
+  const size_t n = (size_t)K * L.ntiles;
+  const size_t cap = (size_t)K * sw * sh * splat_tiles_per_splat(sp->r_max_px);
+  L.cap = cap > 0xffffffffull ? 0xffffffffu : (uint32_t)cap;
+  size_t o = 0;
+  L.count = o;
+  o += up256(4 * (n + 1));
+  L.offset = o;
+  o += up256(4 * (n + 1));
+  L.cursor = o;
+  o += up256(4 * (n + 1));
+  L.list = o;
+  o += up256(4 * cap);
+  L.total = o;
+  return L;
+}
+
+struct TsdfLayout {
+  size_t table, bins, acc, gnu, total;
+};
+
+static TsdfLayout tsdf_layout(int K, int sw, int sh, int D, bool backward) {
+  TsdfLayout L{};
+  const size_t ns = (size_t)sw * sh;
+  size_t o = 0;
+  L.table = o;
+  o += up256(8 * ns * K);
+  L.bins = o;
+  o += up256(8 * (size_t)D);
+  if (backward) {
+    L.acc = o;  // acc_D, acc_w, max: contiguous
+    o += up256(8 * (2 * ns * K + 1));
+    L.gnu = o;
+    o += up256(4 * ns * K);
+  }
+  L.total = o;
+  return L;
+}
+
+static int check_ws(void *ws, size_t have, size_t need, const char *what) {
+  if (need == 0) return GG_OK;
+  if (!ws) return fail(GG_ERR_WORKSPACE, "%s: ws is NULL, need %zu bytes", what, need);
+  if (have < need) return fail(GG_ERR_WORKSPACE, "%s: ws has %zu bytes, need %zu", what, have, need);
+  if (!aligned(ws, 256)) return fail(GG_ERR_WORKSPACE, "%s: ws must be 256-byte aligned", what);
+  return GG_OK;
+}
+
+// Launch shape of the volume kernels: V bins per thread, whole pixels per
+// workgroup (tunable through gg_set_volume_tile).
+static int g_ppb_override = 0;
+
+struct VolumeShape {
+  int V;
+  uint32_t cpp, ppb, threads, nblocks;
+};
+
+static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what) {
+  s.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+  s.cpp = (uint32_t)(D / s.V);
+  if (s.cpp > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
+  uint32_t ppb = g_ppb_override > 0 ? (uint32_t)g_ppb_override : 256u / s.cpp;
+  if (ppb < 1) ppb = 1;
+  while (ppb > 1 && ppb * s.cpp > 1024) --ppb;
+  s.ppb = ppb;
+  s.threads = ppb * s.cpp;
+  s.nblocks = (npix + ppb - 1) / ppb;
+  return GG_OK;
+}
+
+}  // namespace gg
+
+using namespace gg;
+
+extern "C" {
+
+const char *gg_last_error(void) { return g_err.c_str(); }
+
+int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c) {
+  if (int rc = check_camera(a, "gg_relative_projection")) return rc;
+  if (int rc = check_camera(b, "gg_relative_projection")) return rc;
+  if (!H || !c) return fail(GG_ERR_INVALID, "gg_relative_projection: NULL output");
+  Proj P;
+  relproj(*a, *b, P);
+  memcpy(H, P.H, sizeof P.H);
+  memcpy(c, P.c, sizeof P.c);
+  return GG_OK;
+}
+
+size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_t tgt_w,
+                         int32_t tgt_h, int32_t num_bins, const gg_splat_params *sp) {
+  if (K < 1 || K > GG_MAX_VIEWS || src_w < 1 || src_h < 1 || tgt_w < 1 || tgt_h < 1) return 0;
+  switch (op) {
+    case GG_OP_SPLAT:
+      if (!sp || check_splat(sp, "gg_workspace_size")) return 0;
+      return splat_layout(K, src_w, src_h, tgt_w, tgt_h, sp).total;
+    case GG_OP_SPLAT_BACKWARD:
+      return 0;
+    case GG_OP_TSDF_INTEGRATE:
+      if (num_bins < 2) return 0;
+      return tsdf_layout(K, src_w, src_h, num_bins, false).total;
+    case GG_OP_TSDF_INTEGRATE_BACKWARD:
+      if (num_bins < 2) return 0;
+      return tsdf_layout(K, src_w, src_h, num_bins, true).total;
+    default:
+      return 0;
+  }
+}
+
+int gg_set_volume_tile(int pixels_per_block) {
+  if (pixels_per_block < 0 || pixels_per_block > 1024)
+    return fail(GG_ERR_INVALID, "gg_set_volume_tile: %d outside 0..1024", pixels_per_block);
+  g_ppb_override = pixels_per_block;
+  return GG_OK;
+}
+
+int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                const gg_camera *tgt, const gg_splat_params *prm, int32_t *win_idx,
+                float *out_depth, float *out_rgb, float *out_alpha, float *out_tape, void *ws,
+                size_t ws_bytes, void *stream) {
+  const char *W = "splat_views";
+  if (int rc = check_sources(src, K, W)) return rc;
+  if (int rc = check_camera(tgt, W)) return rc;
+  if (int rc = check_splat(prm, W)) return rc;
+  if (!depth || !rgb || !win_idx || !out_depth || !out_rgb || !out_alpha)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", W);
+  const int sw = src[0].width, sh = src[0].height;
+  const SplatLayout L = splat_layout(K, sw, sh, tgt->width, tgt->height, prm);
+  if ((size_t)K * sw * sh * splat_tiles_per_splat(prm->r_max_px) > 0xffffffffull)
+    return fail(GG_ERR_UNSUPPORTED, "%s: too many source pixels", W);
+  if (int rc = check_ws(ws, ws_bytes, L.total, W)) return rc;
+  SplatArgs a{};
+  for (int k = 0; k < K; ++k) {
+    relproj(src[k], *tgt, a.views[k].P);
+    a.views[k].sscale = (float)((double)prm->sigma_px * (double)tgt->fx / (double)src[k].fx);
+  }
+  a.depth = depth;
+  a.rgb = rgb;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.Wt = tgt->width;
+  a.Ht = tgt->height;
+  a.ns = (uint32_t)(sw * sh);
+  a.nt = (uint32_t)(tgt->width * tgt->height);
+  a.ws_div = make_fastdiv((uint32_t)sw);
+  a.ntx = (int)L.ntx;
+  a.nty = (int)L.nty;
+  a.ntiles = L.ntiles;
+  a.zmin = prm->z_min;
+  a.rmax2 = prm->r_max_px * prm->r_max_px;
+  a.band = 1.0f + prm->band_rel;
+  char *w = (char *)ws;
+  a.tile_count = (uint32_t *)(w + L.count);
+  a.tile_offset = (uint32_t *)(w + L.offset);
+  a.tile_cursor = (uint32_t *)(w + L.cursor);
+  a.list = (uint32_t *)(w + L.list);
+  a.list_cap = L.cap;
+  a.win_idx = win_idx;
+  a.out_depth = out_depth;
+  a.out_rgb = out_rgb;
+  a.out_alpha = out_alpha;
+  a.out_tape = out_tape;
+  return launch_splat_forward(a, (hipStream_t)stream);
+}
+
+int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
+                         const uint8_t *rgb, const gg_camera *tgt, const gg_splat_params *prm,
+                         const int32_t *win_idx, const float *out_depth, const float *out_rgb,
+                         const float *out_tape, const float *g_rgb, const float *g_depth,
+                         const float *g_alpha, float *g_depth_in, float *g_rgb_in, void *ws,
+                         size_t ws_bytes, void *stream) {
+  const char *W = "splat_views_backward";
+  (void)ws;
+  (void)ws_bytes;
+  if (int rc = check_sources(src, K, W)) return rc;
+  if (int rc = check_camera(tgt, W)) return rc;
+  if (int rc = check_splat(prm, W)) return rc;
+  if (!depth || !rgb || !win_idx || !out_depth || !out_rgb || !out_tape || !g_depth_in ||
+      !g_rgb_in)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", W);
+  const int sw = src[0].width, sh = src[0].height;
+  SplatArgs a{};
+  for (int k = 0; k < K; ++k) {
+    relproj(src[k], *tgt, a.views[k].P);
+    a.views[k].sscale = (float)((double)prm->sigma_px * (double)tgt->fx / (double)src[k].fx);
+  }
+  a.depth = depth;
+  a.rgb = rgb;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.Wt = tgt->width;
+  a.Ht = tgt->height;
+  a.ns = (uint32_t)(sw * sh);
+  a.nt = (uint32_t)(tgt->width * tgt->height);
+  a.ws_div = make_fastdiv((uint32_t)sw);
+  a.zmin = prm->z_min;
+  a.rmax2 = prm->r_max_px * prm->r_max_px;
+  a.band = 1.0f + prm->band_rel;
+  a.fw_win = win_idx;
+  a.fw_depth = out_depth;
+  a.fw_rgb = out_rgb;
+  a.fw_tape = out_tape;
+  a.g_rgb = g_rgb;
+  a.g_depth = g_depth;
+  a.g_alpha = g_alpha;
+  a.g_depth_in = g_depth_in;
+  a.g_rgb_in = g_rgb_in;
+  return launch_splat_backward(a, (hipStream_t)stream);
+}
+
+static int fill_views(const gg_camera *src, int32_t K, const gg_camera *tgt, Proj *views) {
+  for (int k = 0; k < K; ++k) relproj(*tgt, src[k], views[k]);
+  return GG_OK;
+}
+
+static ConfArgs conf_args(const float *depth, float2 *table, int sw, int sh, int K,
+                          const gg_tsdf_params *p) {
+  ConfArgs c{};
+  c.depth = depth;
+  c.table = table;
+  c.Ws = sw;
+  c.Hs = sh;
+  c.K = K;
+  c.radius = (p->conf_window - 1) / 2;
+  c.tw2 = p->conf_tau * p->conf_tau;
+  c.n2 = (float)(p->conf_window * p->conf_window);
+  c.scale = p->conf_scale;
+  return c;
+}
+
+int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
+                   const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
+                   const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
+                   void *ws, size_t ws_bytes, void *stream) {
+  const char *N = "tsdf_integrate";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!depth || !F || !W) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  if ((F_prev == nullptr) != (W_prev == nullptr))
+    return fail(GG_ERR_INVALID, "%s: F_prev and W_prev go together", N);
+  if ((out_depth == nullptr) != (out_bin == nullptr))
+    return fail(GG_ERR_INVALID, "%s: out_depth and out_bin go together", N);
+  const int sw = src[0].width, sh = src[0].height, D = prm->num_bins;
+  const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
+  VolumeShape vs;
+  if (int rc = volume_shape(D, npix, vs, N)) return rc;
+  const size_t va = 4 * (size_t)vs.V;
+  if (!aligned(F, va) || !aligned(W, va) || (F_prev && (!aligned(F_prev, va) || !aligned(W_prev, va))))
+    return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
+  if ((size_t)npix * D > (size_t)1 << 40) return fail(GG_ERR_UNSUPPORTED, "%s: volume too large", N);
+  const TsdfLayout L = tsdf_layout(K, sw, sh, D, false);
+  if (int rc = check_ws(ws, ws_bytes, L.total, N)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  float2 *table = (float2 *)(w + L.table);
+  float2 *bins = (float2 *)(w + L.bins);
+  if (int rc = launch_bins(*prm, bins, s)) return rc;
+  if (int rc = launch_conf(conf_args(depth, table, sw, sh, K, prm), s)) return rc;
+  IntegrateArgs a{};
+  fill_views(src, K, tgt, a.views);
+  a.table = table;
+  a.bins = bins;
+  a.mask = temporal_mask;
+  a.F_prev = F_prev;
+  a.W_prev = W_prev;
+  a.F = F;
+  a.W = W;
+  a.out_depth = out_depth;
+  a.out_bin = out_bin;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.D = D;
+  a.npix = npix;
+  a.ns = (uint32_t)(sw * sh);
+  a.wt_div = make_fastdiv((uint32_t)tgt->width);
+  a.cpp_div = make_fastdiv(vs.cpp);
+  a.cpp = vs.cpp;
+  a.ppb = vs.ppb;
+  a.nblocks = vs.nblocks;
+  a.decay = prm->decay;
+  a.cap = prm->weight_cap;
+  a.carry = F_prev != nullptr;
+  return launch_integrate(a, vs.V, vs.threads, s);
+}
+
+int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
+                       const float *W, float *out_depth, int32_t *out_bin, void *stream) {
+  const char *N = "tsdf_extract_depth";
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!F || !W || !out_depth || !out_bin) return fail(GG_ERR_INVALID, "%s: NULL argument", N);
+  const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
+  VolumeShape vs;
+  if (int rc = volume_shape(prm->num_bins, npix, vs, N)) return rc;
+  const size_t va = 4 * (size_t)vs.V;
+  if (!aligned(F, va) || !aligned(W, va))
+    return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
+  ExtractArgs a{};
+  a.F = F;
+  a.W = W;
+  a.out_depth = out_depth;
+  a.out_bin = out_bin;
+  a.npix = npix;
+  a.D = prm->num_bins;
+  a.cpp_div = make_fastdiv(vs.cpp);
+  a.cpp = vs.cpp;
+  a.ppb = vs.ppb;
+  a.nblocks = vs.nblocks;
+  a.z_near = prm->z_near;
+  a.z_far = prm->z_far;
+  return launch_extract(a, vs.V, vs.threads, (hipStream_t)stream);
+}
+
+int tsdf_extract_depth_backward(const gg_camera *tgt, const gg_tsdf_params *prm,
+                                const float *F, const float *W, const int32_t *bin,
+                                const float *g_depth, float *g_F2, void *stream) {
+  const char *N = "tsdf_extract_depth_backward";
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!F || !W || !bin || !g_depth || !g_F2) return fail(GG_ERR_INVALID, "%s: NULL argument", N);
+  if (!aligned(g_F2, 8)) return fail(GG_ERR_INVALID, "%s: g_F2 must be 8-byte aligned", N);
+  ExtractArgs a{};
+  a.F = F;
+  a.W = W;
+  a.bin = bin;
+  a.g_depth = g_depth;
+  a.g_F2 = g_F2;
+  a.npix = (uint32_t)(tgt->width * tgt->height);
+  a.D = prm->num_bins;
+  a.z_near = prm->z_near;
+  a.z_far = prm->z_far;
+  return launch_extract_backward(a, (hipStream_t)stream);
+}
+
+int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
+                            const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
+                            const float *W, const int32_t *bin, const float *g_F2,
+                            float *g_depth_in, void *ws, size_t ws_bytes, void *stream) {
+  const char *N = "tsdf_integrate_backward";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!depth || !F || !W || !bin || !g_F2 || !g_depth_in)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  if (!aligned(g_F2, 8)) return fail(GG_ERR_INVALID, "%s: g_F2 must be 8-byte aligned", N);
+  const int sw = src[0].width, sh = src[0].height, D = prm->num_bins;
+  const TsdfLayout L = tsdf_layout(K, sw, sh, D, true);
+  if (int rc = check_ws(ws, ws_bytes, L.total, N)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  float2 *table = (float2 *)(w + L.table);
+  float2 *bins = (float2 *)(w + L.bins);
+  if (int rc = launch_bins(*prm, bins, s)) return rc;
+  if (int rc = launch_conf(conf_args(depth, table, sw, sh, K, prm), s)) return rc;
+  TsdfBackArgs a{};
+  fill_views(src, K, tgt, a.views);
+  const size_t ns = (size_t)sw * sh;
+  a.table = table;
+  a.bins = bins;
+  a.depth = depth;
+  a.F = F;
+  a.W = W;
+  a.bin = bin;
+  a.g_F2 = g_F2;
+  a.acc_D = (unsigned long long *)(w + L.acc);
+  a.acc_w = a.acc_D + ns * K;
+  a.maxbits = (uint32_t *)(a.acc_w + ns * K);
+  a.gnu = (float *)(w + L.gnu);
+  a.g_depth_in = g_depth_in;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.D = D;
+  a.npix = (uint32_t)(tgt->width * tgt->height);
+  a.ns = (uint32_t)ns;
+  a.wt_div = make_fastdiv((uint32_t)tgt->width);
+  a.radius = (prm->conf_window - 1) / 2;
+  a.tw2 = prm->conf_tau * prm->conf_tau;
+  a.n2 = (float)(prm->conf_window * prm->conf_window);
+  a.scale = prm->conf_scale;
+  return launch_tsdf_backward(a, s);
+}
+
+int gg_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = on != 0;
+  return GG_OK;
+}
+
+int gg_timing_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto &t : g_launches) {
+    g_event_pool.push_back(t.start);
+    g_event_pool.push_back(t.stop);
+  }
+  g_launches.clear();
+  return GG_OK;
+}
+
+int gg_timing_read(const char *name, double *total_ms, int64_t *launches) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  double sum = 0.0;
+  int64_t n = 0;
+  for (auto &t : g_launches) {
+    if (name && !strstr(t.name.c_str(), name)) continue;
+    if (int rc = check_hip(hipEventSynchronize(t.stop), "gg_timing_read")) return rc;
+    float ms = 0.0f;
+    if (int rc = check_hip(hipEventElapsedTime(&ms, t.start, t.stop), "gg_timing_read")) return rc;
+    sum += ms;
+    ++n;
+  }
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = n;
+  return GG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Internal declarations of the gfx950 geometry-stage library: kernel argument
+// records (passed by value as kernel arguments, so launches need no host to
+// device copies and are capture-safe), device helpers, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ggeom.h"
+
+namespace gg {
+
+// ---------------------------------------------------------------------------
+// host side: errors and launch timing
+
+int fail(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+
+// Brackets one kernel launch with HIP events when timing is enabled.
+struct KernelTimer {
+  KernelTimer(const char *name, hipStream_t s);
+  ~KernelTimer();
+  const char *name_;
+  hipStream_t stream_;
+  int slot_;
+};
+
+// Magic-number division by a runtime constant d (1 <= d < 2^31):
+// q = umulhi(n, m) >> s, corrected once.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+FastDiv make_fastdiv(uint32_t d);
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  uint32_t q = __umulhi(n, f.m) >> f.s;
+  if (n - q * f.d >= f.d) ++q;
+  return q;
+}
+
+// The relative projection of a pixel ray into another camera, FP32:
+// (x, y, z) = zeta * H (px, py, 1)^T + c.
+struct Proj {
+  float H[9];
+  float c[3];
+};
+void relproj(const gg_camera &a, const gg_camera &b, Proj &out);
+
+__device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && d < INFINITY; }
+
+// h = H (px, py, 1)^T, one fused multiply-add chain per row.
+__device__ __forceinline__ void ray_of(const Proj &P, float px, float py, float &h0, float &h1,
+                                       float &h2) {
+  h0 = fmaf(P.H[0], px, fmaf(P.H[1], py, P.H[2]));
+  h1 = fmaf(P.H[3], px, fmaf(P.H[4], py, P.H[5]));
+  h2 = fmaf(P.H[6], px, fmaf(P.H[7], py, P.H[8]));
+}
+
+// Workgroup id -> logical tile id such that each of the 8 XCDs (which
+// receive workgroups round-robin) works on one contiguous range of tiles,
+// keeping its gathers in its own L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t wg, uint32_t n) {
+  const uint32_t x = wg & 7u, m = wg >> 3;
+  const uint32_t q = n >> 3, r = n & 7u;
+  return x * q + (x < r ? x : r) + m;
+}
+
+// ---------------------------------------------------------------------------
+// fusion (tsdf.hip)
+
+struct ConfArgs {
+  const float *depth;  // K x Hs x Ws
+  float2 *table;       // K x Hs x Ws: (usable depth or +inf, omega)
+  int32_t Ws, Hs, K;
+  int32_t radius;      // (w - 1) / 2
+  float tw2;           // conf_tau^2
+  float n2;            // w * w
+  float scale;         // conf_scale
+};
+
+struct IntegrateArgs {
+  Proj views[GG_MAX_VIEWS];  // target -> view k
+  const float2 *table;       // K x Ns view table
+  const float2 *bins;        // D x (z_d, tau_d)
+  const float *mask;         // Ht x Wt or null
+  const float *F_prev;       // may alias F
+  const float *W_prev;
+  float *F;
+  float *W;
+  float *out_depth;  // null: no fused extraction
+  int32_t *out_bin;
+  int32_t K, Ws, Hs, D;
+  uint32_t npix;     // Ht * Wt
+  uint32_t ns;       // Hs * Ws
+  FastDiv wt_div;    // by Wt
+  FastDiv cpp_div;   // by chunks per pixel (D / V)
+  uint32_t cpp, ppb; // chunks per pixel, pixels per workgroup
+  uint32_t nblocks;
+  float decay, cap;
+  int32_t carry;
+};
+
+struct ExtractArgs {
+  const float *F;
+  const float *W;
+  float *out_depth;
+  int32_t *out_bin;
+  const float *g_depth;  // backward only
+  float *g_F2;           // backward only
+  const int32_t *bin;    // backward only
+  uint32_t npix;
+  int32_t D;
+  FastDiv cpp_div;
+  uint32_t cpp, ppb, nblocks;
+  float z_near, z_far;
+};
+
+struct TsdfBackArgs {
+  Proj views[GG_MAX_VIEWS];
+  const float2 *table;   // recomputed view table
+  const float2 *bins;
+  const float *depth;
+  const float *F;
+  const float *W;
+  const int32_t *bin;
+  const float *g_F2;
+  unsigned long long *acc_D;  // K x Ns fixed point
+  unsigned long long *acc_w;  // K x Ns fixed point
+  float *gnu;                 // K x Ns
+  uint32_t *maxbits;          // [0]: max |contribution| as float bits
+  float *g_depth_in;
+  int32_t K, Ws, Hs, D;
+  uint32_t npix, ns;
+  FastDiv wt_div;
+  int32_t radius;
+  float tw2, n2, scale;
+};
+
+int launch_bins(const gg_tsdf_params &p, float2 *bins, hipStream_t s);
+int launch_conf(const ConfArgs &a, hipStream_t s);
+int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_t s);
+int launch_extract(const ExtractArgs &a, int V, uint32_t threads, hipStream_t s);
+int launch_extract_backward(const ExtractArgs &a, hipStream_t s);
+int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// splatting (splat.hip)
+
+constexpr int kTile = 16;  // target tiles are kTile x kTile pixels
+
+struct SplatView {
+  Proj P;        // view k -> target
+  float sscale;  // sigma_px * fx_T / fx_k
+};
+
+struct SplatArgs {
+  SplatView views[GG_MAX_VIEWS];
+  const float *depth;   // K x Ns
+  const uint8_t *rgb;   // K x Ns x 3
+  int32_t K, Ws, Hs, Wt, Ht;
+  uint32_t ns, nt;
+  FastDiv ws_div;       // by Ws
+  int32_t ntx, nty;     // target tiles per row / column
+  uint32_t ntiles;      // per view
+  float zmin, rmax2, band;
+  uint32_t *tile_count;   // K x ntiles (+1 for the total)
+  uint32_t *tile_offset;  // K x ntiles + 1
+  uint32_t *tile_cursor;  // K x ntiles
+  uint32_t *list;         // entries: source index
+  uint32_t list_cap;
+  int32_t *win_idx;
+  float *out_depth, *out_rgb, *out_alpha, *out_tape;
+  // backward
+  const float *g_rgb, *g_depth, *g_alpha, *fw_rgb, *fw_depth, *fw_tape;
+  const int32_t *fw_win;
+  float *g_depth_in, *g_rgb_in;
+};
+
+uint32_t splat_tiles_per_splat(float r_max);
+int launch_splat_forward(SplatArgs &a, hipStream_t s);
+int launch_splat_backward(const SplatArgs &a, hipStream_t s);
+
+}  // namespace gg

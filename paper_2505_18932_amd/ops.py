@@ -1,0 +1,282 @@
+"""Python binding of the C ABI: the same entry points, taking torch tensors.
+
+Argument marshalling only (shape / dtype / device checks, output and workspace
+allocation through PyTorch's caching allocator, the current stream).  Every
+step of the geometry stage runs in the HIP kernels of libggeom.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+# ---------------------------------------------------------------------------
+# cameras and parameters
+
+
+def camera(c) -> L.GGCamera:
+    """A GGCamera from any object with fx, fy, cx, cy, R (3x3), t (3),
+    width, height."""
+    if isinstance(c, L.GGCamera):
+        return c
+    o = L.GGCamera()
+    o.fx, o.fy, o.cx, o.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+    R = [float(v) for row in c.R for v in row] if hasattr(c.R[0], "__len__") else \
+        [float(v) for v in c.R]
+    o.R[:] = R
+    o.t[:] = [float(v) for v in c.t]
+    o.width, o.height = int(c.width), int(c.height)
+    return o
+
+
+def cameras(cs: Sequence) -> C.Array:
+    if isinstance(cs, C.Array):
+        return cs
+    arr = (L.GGCamera * len(cs))()
+    for i, c in enumerate(cs):
+        arr[i] = camera(c)
+    return arr
+
+
+def splat_params(p) -> L.GGSplatParams:
+    if isinstance(p, L.GGSplatParams):
+        return p
+    return L.GGSplatParams(p["sigma_px"], p["band_rel"], p["z_min"], p["r_max_px"])
+
+
+def tsdf_params(p) -> L.GGTsdfParams:
+    if isinstance(p, L.GGTsdfParams):
+        return p
+    return L.GGTsdfParams(p["z_near"], p["z_far"], int(p["num_bins"]), p["trunc"],
+                          int(p["trunc_in_bins"]), p["conf_tau"], p["conf_scale"],
+                          int(p["conf_window"]), p["decay"], p["weight_cap"])
+
+
+# ---------------------------------------------------------------------------
+# tensor checks
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, name, device):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _device(t: torch.Tensor) -> torch.device:
+    if t.device.type != "cuda":
+        raise ValueError("inputs must be GPU tensors (the geometry stage runs in HIP kernels)")
+    return t.device
+
+
+def _stream(device, stream):
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ws(nbytes, device, ws):
+    if nbytes == 0:
+        return None, 0
+    if ws is not None:
+        if ws.device != device or ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small or on the wrong device")
+        return ws, ws.numel() * ws.element_size()
+    # torch allocations are 256-byte aligned
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def workspace_size(op, K, src_w, src_h, tgt_w, tgt_h, num_bins=2, sp=None) -> int:
+    spp = None if sp is None else C.byref(splat_params(sp))
+    return int(L.lib().gg_workspace_size(op, K, src_w, src_h, tgt_w, tgt_h, num_bins, spp))
+
+
+def _wh(cams_arr):
+    return int(cams_arr[0].width), int(cams_arr[0].height)
+
+
+# ---------------------------------------------------------------------------
+# entry points
+
+
+def splat_views(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *, tape=True,
+                out=None, ws=None, stream=None):
+    """Forward splat of K views into the target (see include/ggeom.h).
+    Returns dict(win_idx, depth, rgb, alpha, tape)."""
+    dev = _device(depth)
+    sa, tg, sp = cameras(src), camera(tgt), splat_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th = tg.width, tg.height
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    _need(rgb, torch.uint8, (K, sh, sw, 3), "rgb", dev)
+    o = out or {}
+
+    def buf(key, shape, dtype):
+        t = o.get(key)
+        return torch.empty(shape, dtype=dtype, device=dev) if t is None else \
+            _need(t, dtype, shape, key, dev)
+
+    win = buf("win_idx", (K, th, tw), torch.int32)
+    od = buf("depth", (K, th, tw), torch.float32)
+    orgb = buf("rgb", (K, 3, th, tw), torch.float32)
+    oa = buf("alpha", (K, th, tw), torch.float32)
+    ot = buf("tape", (K, 3, th, tw), torch.float32) if (tape or o.get("tape") is not None) \
+        else None
+    need = workspace_size(L.GG_OP_SPLAT, K, sw, sh, tw, th, 2, sp)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().splat_views(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
+                                _ptr(win), _ptr(od), _ptr(orgb), _ptr(oa), _ptr(ot), _ptr(wsb),
+                                wsn, _stream(dev, stream)))
+    return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=ot)
+
+
+def splat_views_backward(src, depth, rgb, tgt, params, fwd, g_rgb=None, g_depth=None,
+                         g_alpha=None, *, stream=None):
+    """Adjoint of splat_views; returns (g_depth_in, g_rgb_in) with g_rgb_in
+    the gradient with respect to c = rgb / 255, shape (K, H, W, 3)."""
+    dev = _device(depth)
+    sa, tg, sp = cameras(src), camera(tgt), splat_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th = tg.width, tg.height
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    _need(rgb, torch.uint8, (K, sh, sw, 3), "rgb", dev)
+    for name, t, shp in (("g_rgb", g_rgb, (K, 3, th, tw)), ("g_depth", g_depth, (K, th, tw)),
+                         ("g_alpha", g_alpha, (K, th, tw))):
+        if t is not None:
+            _need(t, torch.float32, shp, name, dev)
+    if fwd.get("tape") is None:
+        raise ValueError("the forward must have been run with tape=True")
+    gd = torch.empty((K, sh, sw), dtype=torch.float32, device=dev)
+    gc = torch.empty((K, sh, sw, 3), dtype=torch.float32, device=dev)
+    L.check(L.lib().splat_views_backward(
+        sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp), _ptr(fwd["win_idx"]),
+        _ptr(fwd["depth"]), _ptr(fwd["rgb"]), _ptr(fwd["tape"]), _ptr(g_rgb), _ptr(g_depth),
+        _ptr(g_alpha), _ptr(gd), _ptr(gc), None, 0, _stream(dev, stream)))
+    return gd, gc
+
+
+def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
+                   mask=None, extract=True, ws=None, stream=None):
+    """Fuse K depth maps into the target volume (in place when F is F_prev).
+    Returns (F, W, depth, bin) (depth, bin None when extract=False)."""
+    dev = _device(depth)
+    sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th, D = tg.width, tg.height, tp.num_bins
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    vol = (th, tw, D)
+    if (F_prev is None) != (W_prev is None):
+        raise ValueError("F_prev and W_prev go together")
+    if F_prev is not None:
+        _need(F_prev, torch.float32, vol, "F_prev", dev)
+        _need(W_prev, torch.float32, vol, "W_prev", dev)
+    if mask is not None:
+        _need(mask, torch.float32, (th, tw), "mask", dev)
+    F = torch.empty(vol, dtype=torch.float32, device=dev) if F is None else \
+        _need(F, torch.float32, vol, "F", dev)
+    W = torch.empty(vol, dtype=torch.float32, device=dev) if W is None else \
+        _need(W, torch.float32, vol, "W", dev)
+    od = ob = None
+    if extract:
+        od = torch.empty((th, tw), dtype=torch.float32, device=dev)
+        ob = torch.empty((th, tw), dtype=torch.int32, device=dev)
+    need = workspace_size(L.GG_OP_TSDF_INTEGRATE, K, sw, sh, tw, th, D)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().tsdf_integrate(sa, K, _ptr(depth), C.byref(tg), C.byref(tp), _ptr(mask),
+                                   _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W), _ptr(od),
+                                   _ptr(ob), _ptr(wsb), wsn, _stream(dev, stream)))
+    return F, W, od, ob
+
+
+def tsdf_extract_depth(tgt, params, F, W, *, stream=None):
+    dev = _device(F)
+    tg, tp = camera(tgt), tsdf_params(params)
+    vol = (tg.height, tg.width, tp.num_bins)
+    _need(F, torch.float32, vol, "F", dev)
+    _need(W, torch.float32, vol, "W", dev)
+    od = torch.empty(vol[:2], dtype=torch.float32, device=dev)
+    ob = torch.empty(vol[:2], dtype=torch.int32, device=dev)
+    L.check(L.lib().tsdf_extract_depth(C.byref(tg), C.byref(tp), _ptr(F), _ptr(W), _ptr(od),
+                                       _ptr(ob), _stream(dev, stream)))
+    return od, ob
+
+
+def tsdf_extract_depth_backward(tgt, params, F, W, bin, g_depth, *, stream=None):
+    dev = _device(F)
+    tg, tp = camera(tgt), tsdf_params(params)
+    vol = (tg.height, tg.width, tp.num_bins)
+    _need(F, torch.float32, vol, "F", dev)
+    _need(W, torch.float32, vol, "W", dev)
+    _need(bin, torch.int32, vol[:2], "bin", dev)
+    _need(g_depth, torch.float32, vol[:2], "g_depth", dev)
+    g2 = torch.empty(vol[:2] + (2,), dtype=torch.float32, device=dev)
+    L.check(L.lib().tsdf_extract_depth_backward(C.byref(tg), C.byref(tp), _ptr(F), _ptr(W),
+                                                _ptr(bin), _ptr(g_depth), _ptr(g2),
+                                                _stream(dev, stream)))
+    return g2
+
+
+def tsdf_integrate_backward(src, depth, tgt, params, F, W, bin, g_F2, *, ws=None, stream=None):
+    dev = _device(depth)
+    sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th, D = tg.width, tg.height, tp.num_bins
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    _need(F, torch.float32, (th, tw, D), "F", dev)
+    _need(W, torch.float32, (th, tw, D), "W", dev)
+    _need(bin, torch.int32, (th, tw), "bin", dev)
+    _need(g_F2, torch.float32, (th, tw, 2), "g_F2", dev)
+    gd = torch.empty((K, sh, sw), dtype=torch.float32, device=dev)
+    need = workspace_size(L.GG_OP_TSDF_INTEGRATE_BACKWARD, K, sw, sh, tw, th, D)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().tsdf_integrate_backward(sa, K, _ptr(depth), C.byref(tg), C.byref(tp),
+                                            _ptr(F), _ptr(W), _ptr(bin), _ptr(g_F2), _ptr(gd),
+                                            _ptr(wsb), wsn, _stream(dev, stream)))
+    return gd
+
+
+def relative_projection(a, b):
+    """FP32 (H (3x3), c (3)) of the relative projection a -> b (host only)."""
+    H = (C.c_float * 9)()
+    c = (C.c_float * 3)()
+    ca, cb = camera(a), camera(b)
+    L.check(L.lib().gg_relative_projection(C.byref(ca), C.byref(cb), H, c))
+    return [list(H[0:3]), list(H[3:6]), list(H[6:9])], list(c)
+
+
+# ---------------------------------------------------------------------------
+# kernel timing (profiling)
+
+
+def timing_enable(on=True):
+    L.check(L.lib().gg_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    L.check(L.lib().gg_timing_reset())
+
+
+def timing_read(name=None):
+    ms = C.c_double()
+    n = C.c_int64()
+    L.check(L.lib().gg_timing_read(None if name is None else name.encode(), C.byref(ms),
+                                   C.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,138 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol the header
+declares, computes the relative projection bitwise like the oracle, and
+rejects invalid arguments before enqueuing any GPU work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from paper_2505_18932_amd import _lib as L
+from paper_2505_18932_amd import ops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "ggeom.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 13
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+@pytest.mark.parametrize("pair", [(0, 1), (2, 7), (5, 5)])
+def test_relative_projection_bitwise_equals_oracle(pair):
+    ring = scenes.ring_rig(8, 1.3, 640, 360)
+    tgt = scenes.ring_target(0.77, 1.3, 640, 360).quantized()
+    a = ring[pair[0]].quantized()
+    b = ring[pair[1]].quantized() if pair[0] != pair[1] else tgt
+    H, c = ops.relative_projection(a, b)
+    Ho, co = oracle.relproj(a, b)
+    assert np.array(H, np.float32).tobytes() == Ho.astype(np.float32).tobytes()
+    assert np.array(c, np.float32).tobytes() == co.astype(np.float32).tobytes()
+
+
+def _cams(K=2, w=32, h=24):
+    src = scenes._quantize_all(scenes.parallel_rig([0.01 * k for k in range(K)], w, h, 30.0))
+    return ops.cameras(src), ops.camera(src[0])
+
+
+FAKE = C.c_void_p(1 << 20)  # never dereferenced: every call below fails validation
+
+
+def _err(rc):
+    return rc, L.lib().gg_last_error().decode()
+
+
+def test_splat_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    sp = ops.splat_params(scenes.splat_params())
+    args = lambda K, d=FAKE, prm=sp, ws=FAKE, nws=1 << 40: (
+        src, K, d, FAKE, C.byref(tgt), C.byref(prm), FAKE, FAKE, FAKE, FAKE, None, ws, nws, None)
+    assert _err(lib.splat_views(*args(0)))[0] == L.GG_ERR_INVALID
+    big = ops.cameras([scenes.parallel_rig([0.0], 32, 24, 30.0)[0]] * 17)
+    rc = lib.splat_views(big, 17, FAKE, FAKE, C.byref(tgt), C.byref(sp), FAKE, FAKE, FAKE, FAKE,
+                         None, FAKE, 1 << 40, None)
+    assert rc == L.GG_ERR_UNSUPPORTED
+    rc, msg = _err(lib.splat_views(*args(2, d=None)))
+    assert rc == L.GG_ERR_INVALID and "NULL" in msg
+    bad = ops.splat_params(scenes.splat_params(sigma_px=0.0))
+    assert lib.splat_views(*args(2, prm=bad)) == L.GG_ERR_INVALID
+    bad = ops.splat_params(scenes.splat_params(band_rel=-0.1))
+    assert lib.splat_views(*args(2, prm=bad)) == L.GG_ERR_INVALID
+    rc, msg = _err(lib.splat_views(*args(2, nws=16)))
+    assert rc == L.GG_ERR_WORKSPACE and "need" in msg
+    assert lib.splat_views(*args(2, ws=None)) == L.GG_ERR_WORKSPACE
+    # a camera with a non-finite parameter
+    bad_src = ops.cameras([scenes.parallel_rig([0.0], 32, 24, 30.0)[0]] * 2)
+    bad_src[1].fx = float("nan")
+    rc = lib.splat_views(bad_src, 2, FAKE, FAKE, C.byref(tgt), C.byref(sp), FAKE, FAKE, FAKE,
+                         FAKE, None, FAKE, 1 << 40, None)
+    assert rc == L.GG_ERR_INVALID
+    # sources of different sizes
+    mixed = ops.cameras([scenes.parallel_rig([0.0], 32, 24, 30.0)[0],
+                         scenes.parallel_rig([0.0], 30, 24, 30.0)[0]])
+    rc = lib.splat_views(mixed, 2, FAKE, FAKE, C.byref(tgt), C.byref(sp), FAKE, FAKE, FAKE,
+                         FAKE, None, FAKE, 1 << 40, None)
+    assert rc == L.GG_ERR_INVALID
+
+
+def test_tsdf_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+
+    def call(prm, Fp=None, Wp=None, od=None, ob=None, ws=FAKE, nws=1 << 40, F=FAKE):
+        tp = ops.tsdf_params(prm)
+        return lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, Fp, Wp, F, FAKE,
+                                  od, ob, ws, nws, None)
+
+    good = scenes.tsdf_params(num_bins=64)
+    assert call(scenes.tsdf_params(num_bins=1)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(num_bins=5000)) == L.GG_ERR_UNSUPPORTED
+    assert call(scenes.tsdf_params(z_near=0.0)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(z_far=0.4)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(trunc=0.0)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(conf_window=6)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(conf_window=17)) == L.GG_ERR_INVALID
+    assert call(scenes.tsdf_params(decay=1.5)) == L.GG_ERR_INVALID
+    assert call(good, Fp=FAKE) == L.GG_ERR_INVALID
+    assert call(good, od=FAKE) == L.GG_ERR_INVALID
+    assert call(good, F=None) == L.GG_ERR_INVALID
+    assert call(good, F=C.c_void_p((1 << 20) + 4)) == L.GG_ERR_INVALID  # misaligned volume
+    assert call(good, nws=100) == L.GG_ERR_WORKSPACE
+    assert call(good, ws=C.c_void_p((1 << 20) + 8)) == L.GG_ERR_WORKSPACE  # misaligned ws
+    tp = ops.tsdf_params(scenes.tsdf_params(num_bins=1))
+    assert lib.tsdf_extract_depth(C.byref(tgt), C.byref(tp), FAKE, FAKE, FAKE, FAKE, None) == \
+        L.GG_ERR_INVALID
+
+
+def test_workspace_sizes():
+    sp = scenes.splat_params()
+    n = ops.workspace_size(L.GG_OP_SPLAT, 4, 1280, 720, 1280, 720, 2, sp)
+    assert n >= 4 * 1280 * 720 * 4  # at least one list entry per source pixel
+    assert ops.workspace_size(L.GG_OP_TSDF_INTEGRATE, 4, 1280, 720, 1280, 720, 128) >= \
+        4 * 1280 * 720 * 8
+    assert ops.workspace_size(L.GG_OP_TSDF_INTEGRATE_BACKWARD, 4, 1280, 720, 1280, 720, 128) > \
+        ops.workspace_size(L.GG_OP_TSDF_INTEGRATE, 4, 1280, 720, 1280, 720, 128)
+    assert ops.workspace_size(L.GG_OP_SPLAT, 0, 1280, 720, 1280, 720, 2, sp) == 0
+    assert ops.workspace_size(99, 4, 1280, 720, 1280, 720, 2, sp) == 0
+
+
+def test_product_path_refuses_cpu_tensors():
+    import torch
+    c = scenes.config1()
+    with pytest.raises(ValueError, match="GPU"):
+        ops.tsdf_integrate(c["src"], torch.from_numpy(c["depth"]), c["tgt"], c["tsdf"])

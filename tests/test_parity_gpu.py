@@ -1,0 +1,293 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer outputs (winner indices, zero-crossing bins) and the fused volume
+F / W are compared bitwise; colour, opacity and depth within 1e-5 relative
+with a floor of 1e-3 of the largest reference magnitude (north-star
+tolerance).  Sizes span several tiles with ragged tails; full-size workloads
+are compared on sampled target pixels the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2505_18932_amd as gg
+import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def close(got, ref, rtol=1e-5, what=""):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    floor = 1e-3 * max(np.abs(ref).max(), 1e-30)
+    bad = np.abs(got - ref) > rtol * np.maximum(np.abs(ref), floor)
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance; " \
+                          f"worst {np.abs(got - ref)[bad].max():.3g}"
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def to_dev(c):
+    return torch.from_numpy(c["depth"]).to(DEV), torch.from_numpy(c["rgb"]).to(DEV)
+
+
+def check_splat(c, depth, rgb):
+    out = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    torch.cuda.synchronize()
+    ref = oracle.splat(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"])
+    win = out["win_idx"].cpu().numpy()
+    assert np.array_equal(win, ref["win_idx"]), f"winners differ at {(win != ref['win_idx']).sum()}"
+    assert np.array_equal(bits(out["depth"].cpu().numpy()), bits(ref["depth"])), "winner depth"
+    close(out["rgb"].cpu().numpy(), ref["rgb"], what="rgb")
+    close(out["alpha"].cpu().numpy(), ref["alpha"], what="alpha")
+    tape = out["tape"].cpu().numpy()
+    close(tape[:, 0], ref["tape"][:, 0], what="tape sum G")
+    return out, ref
+
+
+def check_tsdf(c, depth, F_prev=None, W_prev=None, mask=None, pixels=None, ref_prev=None):
+    """Run the GPU fusion; compare (all or sampled pixels) with the oracle.
+    Returns GPU (F, W, dep, bin) and the oracle's sampled (F, W)."""
+    p = c["tsdf"]
+    D = p["num_bins"]
+    m = None if mask is None else torch.from_numpy(mask).to(DEV)
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], p, F_prev=F_prev, W_prev=W_prev,
+                                     mask=m)
+    torch.cuda.synchronize()
+    Fr_prev, Wr_prev = ref_prev if ref_prev is not None else (None, None)
+    Fr, Wr = oracle.integrate(c["src"], c["depth"], c["tgt"], p, mask=mask, F_prev=Fr_prev,
+                              W_prev=Wr_prev, pixels=pixels)
+    dr, br = oracle.extract(Fr, Wr, p)
+    Fg = F.reshape(-1, D).cpu().numpy()
+    Wg = W.reshape(-1, D).cpu().numpy()
+    dg = dep.reshape(-1).cpu().numpy()
+    bg = b.reshape(-1).cpu().numpy()
+    if pixels is not None:
+        Fg, Wg, dg, bg = Fg[pixels], Wg[pixels], dg[pixels], bg[pixels]
+    nF = (bits(Fg) != bits(Fr)).sum()
+    nW = (bits(Wg) != bits(Wr)).sum()
+    assert nF == 0 and nW == 0, f"volume differs bitwise: F {nF}, W {nW} of {Fr.size}"
+    assert np.array_equal(bg, br), f"bins differ at {(bg != br).sum()}"
+    close(dg, dr, what="extracted depth")
+    return (F, W, dep, b), (Fr, Wr)
+
+
+def test_config1_full():
+    c = scenes.config1()
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
+def test_config3_full():
+    c = scenes.config3()
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
+def test_config2_sequence_sampled():
+    """Full 1280x720, K=4, D=128 ring video: three frames with the volume
+    carried in place; the oracle follows 3000 sampled pixel columns."""
+    c = scenes.config2()
+    seq = c["seq"]
+    rng = np.random.default_rng(0)
+    npix = c["tgt"].width * c["tgt"].height
+    pix = np.sort(rng.choice(npix, 3000, replace=False)).astype(np.int32)
+    F = W = None
+    ref = None
+    for t in range(3):
+        d, r = seq.frame(t)
+        ct = dict(c, depth=d, rgb=r)
+        depth, rgb = to_dev(ct)
+        if t == 0:
+            check_splat(ct, depth, rgb)
+        (F, W, dep, b), ref = check_tsdf(ct, depth, F_prev=F, W_prev=W, pixels=pix,
+                                         ref_prev=ref)
+
+
+def test_config5_frame_sampled():
+    """K=8, 1920x1080, D=256 (the large streaming shape), one frame."""
+    c = scenes.config5()
+    d, r = c["seq"].frame(0)
+    ct = dict(c, depth=d, rgb=r)
+    depth, rgb = to_dev(ct)
+    rng = np.random.default_rng(1)
+    pix = np.sort(rng.choice(1920 * 1080, 1500, replace=False)).astype(np.int32)
+    check_tsdf(ct, depth, pixels=pix)
+
+
+@pytest.mark.parametrize("idx", [0, 5, 11])
+def test_batch_items_plain(idx):
+    desc = scenes.config4_items()[idx]
+    c = scenes.config4_item(desc, scale=2)
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+
+
+def small(seed=0, w=37, h=29, k=3, bins=24, noise=0.01, holes=0.05):
+    return scenes.small_ring(seed=seed, width=w, height=h, k=k, bins=bins, noise=noise,
+                             holes=holes)
+
+
+@pytest.mark.parametrize("bins", [2, 3, 5, 63, 96, 130])
+def test_odd_and_tiny_bin_counts(bins):
+    c = small(bins=bins)
+    depth, rgb = to_dev(c)
+    check_tsdf(c, depth)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (3, 2), (17, 1), (1, 33), (16, 16), (33, 17)])
+def test_tiny_and_ragged_images(wh):
+    c = small(w=wh[0], h=wh[1], k=2, bins=16)
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
+def test_single_view_and_many_views():
+    for k in (1, 8):
+        c = small(k=k)
+        depth, rgb = to_dev(c)
+        check_splat(c, depth, rgb)
+        check_tsdf(c, depth)
+
+
+def test_invalid_depths_are_holes():
+    c = small(holes=0.0)
+    d = c["depth"].copy()
+    d[0, 3, 4] = np.nan
+    d[0, 5, 6] = np.inf
+    d[1, 7, 8] = -1.0
+    d[2, :, 10:14] = 0.0
+    c["depth"] = d
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
+def test_all_holes():
+    c = small()
+    c["depth"] = np.zeros_like(c["depth"])
+    depth, rgb = to_dev(c)
+    out, _ = check_splat(c, depth, rgb)
+    assert (out["win_idx"] == -1).all()
+    (F, W, dep, b), _ = check_tsdf(c, depth)
+    assert (W == 0).all() and (b == -1).all()
+
+
+def test_mask_carry_and_in_place():
+    c = small()
+    depth, rgb = to_dev(c)
+    (F, W, _, _), ref = check_tsdf(c, depth)
+    rng = np.random.default_rng(3)
+    mask = rng.uniform(0, 1.2, (c["tgt"].height, c["tgt"].width)).astype(np.float32)
+    c2 = dict(c, depth=(c["depth"] * np.float32(1.01)).astype(np.float32))
+    d2 = torch.from_numpy(c2["depth"]).to(DEV)
+    # in place: F, W are both previous and output
+    Fg, Wg, dep, b = gg.tsdf_integrate(c2["src"], d2, c2["tgt"], c2["tsdf"], F_prev=F, W_prev=W,
+                                       F=F, W=W, mask=torch.from_numpy(mask).to(DEV))
+    torch.cuda.synchronize()
+    Fr, Wr = oracle.integrate(c2["src"], c2["depth"], c2["tgt"], c2["tsdf"], mask=mask,
+                              F_prev=ref[0], W_prev=ref[1])
+    D = c["tsdf"]["num_bins"]
+    assert np.array_equal(bits(Fg.reshape(-1, D).cpu().numpy()), bits(Fr))
+    assert np.array_equal(bits(Wg.reshape(-1, D).cpu().numpy()), bits(Wr))
+
+
+def test_standalone_extract_equals_fused():
+    c = scenes.config3()
+    depth, _ = to_dev(c)
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    d2, b2 = gg.tsdf_extract_depth(c["tgt"], c["tsdf"], F, W)
+    torch.cuda.synchronize()
+    assert torch.equal(b, b2)
+    assert torch.equal(dep.view(torch.int32), d2.view(torch.int32))
+
+
+def test_repeat_runs_bitwise():
+    c = scenes.config1()
+    depth, rgb = to_dev(c)
+    outs = [gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"]) for _ in range(3)]
+    vols = [gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"]) for _ in range(3)]
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        for key in ("win_idx", "depth", "rgb", "alpha", "tape"):
+            assert torch.equal(o[key].view(torch.int32), outs[0][key].view(torch.int32)), key
+    for v in vols[1:]:
+        for a, b in zip(v, vols[0]):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_volume_tile_shape_does_not_change_results():
+    c = small(bins=96)
+    depth, _ = to_dev(c)
+    base = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    try:
+        for ppb in (1, 3, 8, 40):
+            gg._lib.check(gg._lib.lib().gg_set_volume_tile(ppb))
+            v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+            torch.cuda.synchronize()
+            for a, b in zip(v, base):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), ppb
+    finally:
+        gg._lib.lib().gg_set_volume_tile(0)
+
+
+# ---------------------------------------------------------------------------
+# adjoints against the oracle's
+
+
+def grad_close(got, ref, what):
+    """Gradients: 1e-5 relative, norm-wise and per entry.  Each entry is a sum
+    of FP32 terms as large as the largest gradient, so below 1% of the
+    largest magnitude the per-entry bound becomes absolute, 1e-7 of the
+    largest (about two FP32 ulps of the largest term): the FP32 oracle itself
+    differs from the FP64 build by far more than this (cancellation)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), what
+    floor = 1e-2 * np.abs(ref).max()
+    bad = np.abs(got - ref) > 1e-5 * np.maximum(np.abs(ref), floor)
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance; " \
+                          f"worst {np.abs(got - ref)[bad].max():.3g}"
+
+
+def test_tsdf_backward_parity():
+    c = scenes.config1()
+    depth, _ = to_dev(c)
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal(dep.shape).astype(np.float32)
+    g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, torch.from_numpy(g).to(DEV))
+    gd = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
+    torch.cuda.synchronize()
+    ref = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g.ravel())
+    grad_close(gd.cpu().numpy(), ref, "tsdf depth gradient")
+
+
+def test_splat_backward_parity():
+    c = scenes.config1()
+    depth, rgb = to_dev(c)
+    out = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    rng = np.random.default_rng(3)
+    g_rgb = rng.standard_normal(out["rgb"].shape).astype(np.float32)
+    g_z = rng.standard_normal(out["depth"].shape).astype(np.float32)
+    g_a = rng.standard_normal(out["alpha"].shape).astype(np.float32)
+    gd, gc = gg.splat_views_backward(c["src"], depth, rgb, c["tgt"], c["splat"], out,
+                                     torch.from_numpy(g_rgb).to(DEV), torch.from_numpy(g_z).to(DEV),
+                                     torch.from_numpy(g_a).to(DEV))
+    torch.cuda.synchronize()
+    rd, rc = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"], g_rgb,
+                                   g_z, g_a)
+    grad_close(gc.cpu().numpy(), rc, "splat colour gradient")
+    grad_close(gd.cpu().numpy(), rd, "splat depth gradient")
