@@ -132,6 +132,61 @@ def bwd_fwd_ratio(gg, torch, dev, reps=10):
     return tb / tf, tf * 1e3, tb * 1e3
 
 
+def _batch_item(desc):
+    c = scenes.config4_item(desc)
+    return c["depth"], c["rgb"]
+
+
+def batched_speedup(gg, torch, dev, procs, tune=True):
+    """Batching workload: 24 target views of uneven resolution, view count and
+    bin count.  One hipGraph launch of the batched plan against the 24 plain
+    sequences (splat_views + tsdf_integrate per item), same outputs."""
+    from paper_2505_18932_amd import autotune
+
+    descs = scenes.config4_items()
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            frames = pool.map(_batch_item, descs)
+    else:
+        frames = [_batch_item(d) for d in descs]
+    items = []
+    for desc, (d, r) in zip(descs, frames):
+        seq = scenes.RingSequence(4, desc["seed"], 16, 1.0, desc["width"], desc["height"],
+                                  desc["k"], scenes.MovingSpheres(desc["seed"], 4),
+                                  target_angle=desc["angle"])
+        items.append(dict(src=gg.cameras(seq.src), tgt=gg.camera(seq.tgt),
+                          depth=torch.from_numpy(d).to(dev), rgb=torch.from_numpy(r).to(dev),
+                          splat=gg.splat_params(scenes.splat_params()),
+                          tsdf=gg.tsdf_params(scenes.tsdf_params(num_bins=desc["d"], trunc=4.0))))
+    voxels = sum(it["tgt"].width * it["tgt"].height * it["tsdf"].num_bins for it in items)
+    pixels = sum(it["tgt"].width * it["tgt"].height for it in items)
+    tuning, ttimes = autotune.tune_batch(items) if tune else ((0, 0), {})
+    plan = gg.BatchPlan(items, *tuning)
+    outs = [dict(F=it["F"], W=it["W"]) for it in items]
+
+    def plain():
+        for it, o in zip(items, outs):
+            gg.splat_views(it["src"], it["depth"], it["rgb"], it["tgt"], it["splat"])
+            gg.tsdf_integrate(it["src"], it["depth"], it["tgt"], it["tsdf"], F=o["F"], W=o["W"])
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    tb = timed(plan.launch)
+    tp = timed(plain)
+    plan.close()
+    return {"items": len(items), "target_mpix": round(pixels / 1e6, 3),
+            "voxels_g": round(voxels / 1e9, 3), "graph_ms": round(tb, 3), "plain_ms": round(tp, 3),
+            "speedup": round(tp / tb, 3), "tuning": list(tuning),
+            "batched_mpix_s": round(pixels / tb / 1e3, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +195,9 @@ def main():
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--procs", type=int, default=0,
+                    help="input-generation worker processes (0: min(16, cores))")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -148,7 +206,7 @@ def main():
               "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    procs = max(1, min(16, os.cpu_count() or 1))
+    procs = args.procs or max(1, min(16, os.cpu_count() or 1))
     depth_h, rgb_h = make_frames(args.frames, procs)
     print(f"# frames generated: {depth_h.shape}", file=sys.stderr, flush=True)
 
@@ -232,6 +290,10 @@ def main():
         r, tf, tb = bwd_fwd_ratio(gg, torch, dev)
         out["bwd_fwd"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3), "bwd_ms": round(tb, 3),
                           "workload": "differentiation 640x360 K=4 D=96"}
+    if not args.no_batch:
+        del depth, rgb, F, Wv, ws_s, ws_t, sout
+        torch.cuda.empty_cache()
+        out["batched"] = batched_speedup(gg, torch, dev, procs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, depth_h, rgb_h)
     print(json.dumps(out), flush=True)

@@ -212,6 +212,52 @@ int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
                             float *g_depth_in, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched path: many target views of uneven resolution, view count and bin
+ * count (each with its own inputs, cameras, parameters, volume and outputs)
+ * fused by persistent kernels in one hipGraph launch.  Every output is
+ * bitwise identical to the plain calls (splat_views + tsdf_integrate with
+ * fused extraction) on the same item, for any tuning.
+ * ------------------------------------------------------------------------- */
+typedef struct gg_batch_item {
+  const gg_camera *src;         /* [host] K source cameras, one size per item        */
+  int32_t K;
+  const float *depth;           /* K x src_h x src_w                                 */
+  const uint8_t *rgb;           /* K x src_h x src_w x 3, or NULL: no splat          */
+  gg_camera tgt;
+  gg_splat_params splat;
+  gg_tsdf_params tsdf;
+  const float *temporal_mask;   /* tgt_h x tgt_w or NULL                             */
+  const float *F_prev, *W_prev; /* both or neither; may alias F, W                   */
+  float *F, *W;                 /* tgt_h x tgt_w x D                                 */
+  float *out_depth;             /* tgt_h x tgt_w or NULL (with out_bin)              */
+  int32_t *out_bin;
+  int32_t *win_idx;             /* splat outputs, as splat_views (required with rgb) */
+  float *sp_depth, *sp_rgb, *sp_alpha;
+  float *sp_tape;               /* or NULL                                           */
+} gg_batch_item;
+
+/* Launch shape chosen by the autotuner (0 = default). */
+typedef struct gg_batch_tuning {
+  int32_t volume_threads; /* threads per fusion workgroup, multiple of 64 in 64..1024 (256) */
+  int32_t blocks_per_cu;  /* persistent workgroups per compute unit, 1..64 (4)              */
+} gg_batch_tuning;
+
+typedef struct gg_batch gg_batch;
+
+/* Validates every item (as the plain calls do), allocates the plan's device
+ * memory (descriptors, work lists, workspaces: gg_batch_device_bytes),
+ * uploads descriptors and captures the phases into a graph.  The plan binds
+ * the items' device pointers: refill those buffers between launches.  This
+ * call allocates and synchronises; gg_batch_launch does neither. */
+int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tuning,
+                    gg_batch **plan);
+/* One graph launch running the whole batch on `stream`. */
+int gg_batch_launch(gg_batch *plan, void *stream);
+size_t gg_batch_device_bytes(const gg_batch *plan);
+/* Frees the plan (call after its last launch has completed). */
+int gg_batch_destroy(gg_batch *plan);
+
+/* ---------------------------------------------------------------------------
  * Utilities.
  * ------------------------------------------------------------------------- */
 
@@ -226,10 +272,25 @@ const char *gg_last_error(void);
 int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c);
 
 /* Launch shape of the volume kernels (tsdf_integrate, tsdf_extract_depth):
- * whole target pixels per workgroup, each thread holding up to 4 consecutive
- * bins.  0 restores the default (256 threads' worth of pixels).  Results do
- * not depend on the choice; it exists for the autotuner.  Process-wide. */
-int gg_set_volume_tile(int pixels_per_block);
+ * whole target pixels per workgroup (each thread holding up to 4 consecutive
+ * bins of one pixel) and the number of neighbouring pixels interleaved in a
+ * wavefront row of tsdf_integrate (a power of two dividing the former; the
+ * largest such <= pixels_per_row is used).  0 restores the defaults (256
+ * threads' worth of pixels; up to 8 per row).  Results do not depend on the
+ * choice; it exists for the autotuner.  Process-wide. */
+int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
+
+/* Self-check of the correctly rounded reciprocal the fusion kernels use for
+ * 1/z: for every FP32 value with biased exponent in [e_lo, e_hi] (all 2^23
+ * significands of each), compares it bitwise with IEEE division on the
+ * device and adds the number of mismatches to *mismatches (a device
+ * counter the caller zeroes).  For the test suite. */
+int gg_selftest_reciprocal(int32_t e_lo, int32_t e_hi, unsigned long long *mismatches,
+                           void *stream);
+
+/* The kernels' reciprocal 1/z (z > 0) of n device floats, for comparison
+ * with a host reference.  For the test suite. */
+int gg_fast_reciprocal(const float *in, float *out, int64_t n, void *stream);
 
 /* Kernel timing for profiling: when enabled, every kernel the library
  * launches is bracketed by HIP events on its stream.  gg_timing_read

@@ -3,13 +3,13 @@
 fusion with a running temporal weight, zero-crossing extraction, adjoints and
 a batched path, as hand-written HIP kernels behind a C ABI (include/ggeom.h).
 """
-from . import _lib
-from .ops import (camera, cameras, relative_projection, splat_params, splat_views,
+from . import _lib, autograd
+from .ops import (BatchPlan, camera, cameras, relative_projection, splat_params, splat_views,
                   splat_views_backward, timing_enable, timing_read, timing_reset,
                   tsdf_extract_depth, tsdf_extract_depth_backward, tsdf_integrate,
                   tsdf_integrate_backward, tsdf_params, workspace_size)
 
-__all__ = ["camera", "cameras", "relative_projection", "splat_params", "splat_views",
+__all__ = ["BatchPlan", "camera", "cameras", "relative_projection", "splat_params", "splat_views",
            "splat_views_backward", "timing_enable", "timing_read", "timing_reset",
            "tsdf_extract_depth", "tsdf_extract_depth_backward", "tsdf_integrate",
-           "tsdf_integrate_backward", "tsdf_params", "workspace_size", "_lib"]
+           "tsdf_integrate_backward", "tsdf_params", "workspace_size", "_lib", "autograd"]

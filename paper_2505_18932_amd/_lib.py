@@ -41,6 +41,20 @@ class GGTsdfParams(C.Structure):
                 ("decay", C.c_float), ("weight_cap", C.c_float)]
 
 
+class GGBatchItem(C.Structure):
+    _fields_ = [("src", C.POINTER(GGCamera)), ("K", C.c_int32), ("depth", C.c_void_p),
+                ("rgb", C.c_void_p), ("tgt", GGCamera), ("splat", GGSplatParams),
+                ("tsdf", GGTsdfParams), ("temporal_mask", C.c_void_p), ("F_prev", C.c_void_p),
+                ("W_prev", C.c_void_p), ("F", C.c_void_p), ("W", C.c_void_p),
+                ("out_depth", C.c_void_p), ("out_bin", C.c_void_p), ("win_idx", C.c_void_p),
+                ("sp_depth", C.c_void_p), ("sp_rgb", C.c_void_p), ("sp_alpha", C.c_void_p),
+                ("sp_tape", C.c_void_p)]
+
+
+class GGBatchTuning(C.Structure):
+    _fields_ = [("volume_threads", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
 P = C.c_void_p
 CAM = C.POINTER(GGCamera)
 SPP = C.POINTER(GGSplatParams)
@@ -63,7 +77,14 @@ SIGNATURES = {
     "gg_timing_enable": (C.c_int, [C.c_int]),
     "gg_timing_reset": (C.c_int, []),
     "gg_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
-    "gg_set_volume_tile": (C.c_int, [C.c_int]),
+    "gg_set_volume_tile": (C.c_int, [C.c_int, C.c_int]),
+    "gg_selftest_reciprocal": (C.c_int, [I32, I32, P, P]),
+    "gg_batch_create": (C.c_int, [C.POINTER(GGBatchItem), I32, C.POINTER(GGBatchTuning),
+                                  C.POINTER(C.c_void_p)]),
+    "gg_batch_launch": (C.c_int, [P, P]),
+    "gg_batch_device_bytes": (SZ, [P]),
+    "gg_batch_destroy": (C.c_int, [P]),
+    "gg_fast_reciprocal": (C.c_int, [P, P, C.c_int64, P]),
 }
 
 _lib = None

@@ -1,0 +1,120 @@
+"""Autotuner of the volume kernels' launch shapes.
+
+Results never depend on the tile shape (the tests check it bitwise); only
+the time does.  The tuner times candidates on the device with HIP events and
+caches the winner per GPU architecture and workload class in a JSON file
+next to this module (``tuning_cache.json``):
+
+* plain path: pixels per workgroup and per wavefront row of the fusion for a
+  (K, D, width, height) class, applied through ``gg_set_volume_tile``;
+* batched path: (threads per fusion workgroup, persistent workgroups per
+  compute unit) for a batch signature.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import _lib as L
+from . import ops
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning_cache.json")
+
+# (pixels per workgroup, pixels per wavefront row); (0, 0) = defaults
+PLAIN_CANDIDATES = [(0, 0), (0, 1), (4, 4), (8, 1), (8, 8), (16, 8), (16, 16), (32, 8)]
+BATCH_CANDIDATES = [(128, 4), (256, 2), (256, 4), (256, 8), (512, 2), (512, 4), (1024, 1),
+                    (1024, 2)]
+
+
+def arch(device=None) -> str:
+    p = torch.cuda.get_device_properties(device or torch.device("cuda:0"))
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def _save(c):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def _time(fn, reps=5, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        best = min(best, s.elapsed_time(e))
+    return best
+
+
+def plain_key(K, D, width, height):
+    return f"plain/K{K}/D{D}/{width}x{height}"
+
+
+def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
+    """Best (pixels per workgroup, pixels per row) of tsdf_integrate for this
+    class; sets it process-wide and returns (best, {candidate: ms})."""
+    tg, tp = ops.camera(tgt), ops.tsdf_params(params)
+    key = plain_key(len(src), tp.num_bins, tg.width, tg.height)
+    cache = _load()
+    a = arch(depth.device)
+    if use_cache and key in cache.get(a, {}):
+        best = tuple(cache[a][key]["best"])
+        L.check(L.lib().gg_set_volume_tile(*best))
+        return best, cache[a][key]["times"]
+    F, W, _, _ = ops.tsdf_integrate(src, depth, tgt, params)
+    times = {}
+    for cand in PLAIN_CANDIDATES:
+        L.check(L.lib().gg_set_volume_tile(*cand))
+        times["%d,%d" % cand] = _time(lambda: ops.tsdf_integrate(src, depth, tgt, params, F_prev=F,
+                                                                   W_prev=W, F=F, W=W), reps)
+    best = tuple(int(v) for v in min(times, key=times.get).split(","))
+    L.check(L.lib().gg_set_volume_tile(*best))
+    cache.setdefault(a, {})[key] = {"best": list(best), "times": times, "when": time.time()}
+    _save(cache)
+    return best, times
+
+
+def batch_signature(items):
+    sig = sorted((len(it["src"]), ops.tsdf_params(it["tsdf"]).num_bins,
+                  ops.camera(it["tgt"]).width, ops.camera(it["tgt"]).height,
+                  it.get("rgb") is not None) for it in items)
+    return "batch/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
+
+
+def tune_batch(items, reps=3, use_cache=True):
+    """Best (volume_threads, blocks_per_cu) for this batch (one plan per
+    candidate over the same buffers, each closed before the next).
+    Returns (tuning, {candidate: ms})."""
+    key = batch_signature(items)
+    cache = _load()
+    a = arch(items[0]["depth"].device)
+    if use_cache and key in cache.get(a, {}):
+        return tuple(cache[a][key]["best"]), cache[a][key]["times"]
+    times = {}
+    for cand in BATCH_CANDIDATES:
+        plan = ops.BatchPlan(items, *cand)
+        times["%d,%d" % cand] = _time(plan.launch, reps)
+        plan.close()
+    best = min(times, key=times.get)
+    tun = tuple(int(v) for v in best.split(","))
+    cache.setdefault(a, {})[key] = {"best": list(tun), "times": times, "when": time.time()}
+    _save(cache)
+    return tun, times

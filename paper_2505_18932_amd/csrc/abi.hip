@@ -1,6 +1,7 @@
 // C ABI of the geometry stage: argument validation (before anything is
 // enqueued), workspace layout, the relative projection of camera pairs, and
 // the launches.  See include/ggeom.h for the contract of each entry point.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_internal.h"
 #include "ggeom_internal.h"
 
 namespace gg {
@@ -244,13 +246,22 @@ static int check_ws(void *ws, size_t have, size_t need, const char *what) {
 }
 
 // Launch shape of the volume kernels: V bins per thread, whole pixels per
-// workgroup (tunable through gg_set_volume_tile).
+// workgroup, neighbouring pixels per wavefront row (tunable through
+// gg_set_volume_tile).
 static int g_ppb_override = 0;
+static int g_pw_override = -1;
 
 struct VolumeShape {
   int V;
-  uint32_t cpp, ppb, threads, nblocks;
+  uint32_t cpp, ppb, threads, nblocks, pw_shift;
 };
+
+// Largest power of two <= cap (and <= 64) dividing ppb, as a shift.
+static uint32_t pick_pw_shift(uint32_t ppb, int cap) {
+  uint32_t sh = 0;
+  while ((2u << sh) <= (uint32_t)cap && (2u << sh) <= 64u && ppb % (2u << sh) == 0) ++sh;
+  return sh;
+}
 
 static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what) {
   s.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
@@ -262,6 +273,7 @@ static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what) 
   s.ppb = ppb;
   s.threads = ppb * s.cpp;
   s.nblocks = (npix + ppb - 1) / ppb;
+  s.pw_shift = pick_pw_shift(ppb, g_pw_override >= 0 ? g_pw_override : 8);
   return GG_OK;
 }
 
@@ -304,11 +316,50 @@ size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_
   }
 }
 
-int gg_set_volume_tile(int pixels_per_block) {
+int gg_set_volume_tile(int pixels_per_block, int pixels_per_row) {
   if (pixels_per_block < 0 || pixels_per_block > 1024)
     return fail(GG_ERR_INVALID, "gg_set_volume_tile: %d outside 0..1024", pixels_per_block);
+  if (pixels_per_row < 0 || pixels_per_row > 64)
+    return fail(GG_ERR_INVALID, "gg_set_volume_tile: pixels_per_row %d outside 0..64",
+                pixels_per_row);
   g_ppb_override = pixels_per_block;
+  g_pw_override = pixels_per_row == 0 ? -1 : pixels_per_row;
   return GG_OK;
+}
+
+// The splat kernels' arguments for K views of `src` into `tgt`, workspace
+// laid out by L from base pointer w (NULL: backward, no workspace).
+static void make_splat_args(SplatArgs &a, const gg_camera *src, int32_t K, const float *depth,
+                            const uint8_t *rgb, const gg_camera &tgt, const gg_splat_params &prm,
+                            const SplatLayout &L, char *w) {
+  for (int k = 0; k < K; ++k) {
+    relproj(src[k], tgt, a.views[k].P);
+    a.views[k].sscale = (float)((double)prm.sigma_px * (double)tgt.fx / (double)src[k].fx);
+  }
+  const int sw = src[0].width, sh = src[0].height;
+  a.depth = depth;
+  a.rgb = rgb;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.Wt = tgt.width;
+  a.Ht = tgt.height;
+  a.ns = (uint32_t)(sw * sh);
+  a.nt = (uint32_t)(tgt.width * tgt.height);
+  a.ws_div = make_fastdiv((uint32_t)sw);
+  a.ntx = (int)L.ntx;
+  a.nty = (int)L.nty;
+  a.ntiles = L.ntiles;
+  a.zmin = prm.z_min;
+  a.rmax2 = prm.r_max_px * prm.r_max_px;
+  a.band = 1.0f + prm.band_rel;
+  if (w) {
+    a.tile_count = (uint32_t *)(w + L.count);
+    a.tile_offset = (uint32_t *)(w + L.offset);
+    a.tile_cursor = (uint32_t *)(w + L.cursor);
+    a.list = (uint32_t *)(w + L.list);
+    a.list_cap = L.cap;
+  }
 }
 
 int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
@@ -327,32 +378,7 @@ int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8
     return fail(GG_ERR_UNSUPPORTED, "%s: too many source pixels", W);
   if (int rc = check_ws(ws, ws_bytes, L.total, W)) return rc;
   SplatArgs a{};
-  for (int k = 0; k < K; ++k) {
-    relproj(src[k], *tgt, a.views[k].P);
-    a.views[k].sscale = (float)((double)prm->sigma_px * (double)tgt->fx / (double)src[k].fx);
-  }
-  a.depth = depth;
-  a.rgb = rgb;
-  a.K = K;
-  a.Ws = sw;
-  a.Hs = sh;
-  a.Wt = tgt->width;
-  a.Ht = tgt->height;
-  a.ns = (uint32_t)(sw * sh);
-  a.nt = (uint32_t)(tgt->width * tgt->height);
-  a.ws_div = make_fastdiv((uint32_t)sw);
-  a.ntx = (int)L.ntx;
-  a.nty = (int)L.nty;
-  a.ntiles = L.ntiles;
-  a.zmin = prm->z_min;
-  a.rmax2 = prm->r_max_px * prm->r_max_px;
-  a.band = 1.0f + prm->band_rel;
-  char *w = (char *)ws;
-  a.tile_count = (uint32_t *)(w + L.count);
-  a.tile_offset = (uint32_t *)(w + L.offset);
-  a.tile_cursor = (uint32_t *)(w + L.cursor);
-  a.list = (uint32_t *)(w + L.list);
-  a.list_cap = L.cap;
+  make_splat_args(a, src, K, depth, rgb, *tgt, *prm, L, (char *)ws);
   a.win_idx = win_idx;
   a.out_depth = out_depth;
   a.out_rgb = out_rgb;
@@ -378,23 +404,8 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
     return fail(GG_ERR_INVALID, "%s: NULL array argument", W);
   const int sw = src[0].width, sh = src[0].height;
   SplatArgs a{};
-  for (int k = 0; k < K; ++k) {
-    relproj(src[k], *tgt, a.views[k].P);
-    a.views[k].sscale = (float)((double)prm->sigma_px * (double)tgt->fx / (double)src[k].fx);
-  }
-  a.depth = depth;
-  a.rgb = rgb;
-  a.K = K;
-  a.Ws = sw;
-  a.Hs = sh;
-  a.Wt = tgt->width;
-  a.Ht = tgt->height;
-  a.ns = (uint32_t)(sw * sh);
-  a.nt = (uint32_t)(tgt->width * tgt->height);
-  a.ws_div = make_fastdiv((uint32_t)sw);
-  a.zmin = prm->z_min;
-  a.rmax2 = prm->r_max_px * prm->r_max_px;
-  a.band = 1.0f + prm->band_rel;
+  const SplatLayout L = splat_layout(K, sw, sh, tgt->width, tgt->height, prm);
+  make_splat_args(a, src, K, depth, rgb, *tgt, *prm, L, nullptr);
   a.fw_win = win_idx;
   a.fw_depth = out_depth;
   a.fw_rgb = out_rgb;
@@ -412,6 +423,25 @@ static int fill_views(const gg_camera *src, int32_t K, const gg_camera *tgt, Pro
   return GG_OK;
 }
 
+// True when every sample's view depth z_k = z h2 + c2 (z <= z_far, pixel
+// centres inside the target) stays below 2^99, where the kernels' fast
+// reciprocal is exact; otherwise they take IEEE division throughout.
+static bool fast_reciprocal_safe(const Proj *views, int32_t K, const gg_camera &tgt,
+                                 float z_far) {
+  for (int k = 0; k < K; ++k) {
+    const Proj &P = views[k];
+    for (float v : P.H)
+      if (!std::isfinite(v)) return false;
+    for (float v : P.c)
+      if (!std::isfinite(v)) return false;
+    const double h2 = std::fabs((double)P.H[6]) * tgt.width + std::fabs((double)P.H[7]) * tgt.height +
+                      std::fabs((double)P.H[8]);
+    const double bound = (double)z_far * 1.01 * h2 + std::fabs((double)P.c[2]);
+    if (!(bound < std::ldexp(1.0, 99))) return false;
+  }
+  return true;
+}
+
 static ConfArgs conf_args(const float *depth, float2 *table, int sw, int sh, int K,
                           const gg_tsdf_params *p) {
   ConfArgs c{};
@@ -425,6 +455,40 @@ static ConfArgs conf_args(const float *depth, float2 *table, int sw, int sh, int
   c.n2 = (float)(p->conf_window * p->conf_window);
   c.scale = p->conf_scale;
   return c;
+}
+
+static void make_integrate_args(IntegrateArgs &a, const gg_camera *src, int32_t K,
+                                const gg_camera &tgt, const gg_tsdf_params &prm,
+                                const VolumeShape &vs, const float2 *table, const float2 *bins,
+                                const float *mask, const float *F_prev, const float *W_prev,
+                                float *F, float *W, float *out_depth, int32_t *out_bin) {
+  fill_views(src, K, &tgt, a.views);
+  const int sw = src[0].width, sh = src[0].height;
+  a.table = table;
+  a.bins = bins;
+  a.mask = mask;
+  a.F_prev = F_prev;
+  a.W_prev = W_prev;
+  a.F = F;
+  a.W = W;
+  a.out_depth = out_depth;
+  a.out_bin = out_bin;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.D = prm.num_bins;
+  a.npix = (uint32_t)(tgt.width * tgt.height);
+  a.ns = (uint32_t)(sw * sh);
+  a.wt_div = make_fastdiv((uint32_t)tgt.width);
+  a.cpp_div = make_fastdiv(vs.cpp);
+  a.cpp = vs.cpp;
+  a.ppb = vs.ppb;
+  a.pw_shift = vs.pw_shift;
+  a.nblocks = vs.nblocks;
+  a.decay = prm.decay;
+  a.cap = prm.weight_cap;
+  a.carry = F_prev != nullptr;
+  a.exact_only = fast_reciprocal_safe(a.views, K, tgt, prm.z_far) ? 0 : 1;
 }
 
 int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
@@ -457,30 +521,8 @@ int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg
   if (int rc = launch_bins(*prm, bins, s)) return rc;
   if (int rc = launch_conf(conf_args(depth, table, sw, sh, K, prm), s)) return rc;
   IntegrateArgs a{};
-  fill_views(src, K, tgt, a.views);
-  a.table = table;
-  a.bins = bins;
-  a.mask = temporal_mask;
-  a.F_prev = F_prev;
-  a.W_prev = W_prev;
-  a.F = F;
-  a.W = W;
-  a.out_depth = out_depth;
-  a.out_bin = out_bin;
-  a.K = K;
-  a.Ws = sw;
-  a.Hs = sh;
-  a.D = D;
-  a.npix = npix;
-  a.ns = (uint32_t)(sw * sh);
-  a.wt_div = make_fastdiv((uint32_t)tgt->width);
-  a.cpp_div = make_fastdiv(vs.cpp);
-  a.cpp = vs.cpp;
-  a.ppb = vs.ppb;
-  a.nblocks = vs.nblocks;
-  a.decay = prm->decay;
-  a.cap = prm->weight_cap;
-  a.carry = F_prev != nullptr;
+  make_integrate_args(a, src, K, *tgt, *prm, vs, table, bins, temporal_mask, F_prev, W_prev, F, W,
+                      out_depth, out_bin);
   return launch_integrate(a, vs.V, vs.threads, s);
 }
 
@@ -582,6 +624,20 @@ int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
   return launch_tsdf_backward(a, s);
 }
 
+int gg_selftest_reciprocal(int32_t e_lo, int32_t e_hi, unsigned long long *mismatches,
+                           void *stream) {
+  if (e_lo < 1 || e_hi > 254 || e_lo > e_hi || !mismatches)
+    return fail(GG_ERR_INVALID, "gg_selftest_reciprocal: need 1 <= e_lo <= e_hi <= 254");
+  return launch_recip_selftest((uint32_t)e_lo, (uint32_t)(e_hi - e_lo + 1), mismatches,
+                               (hipStream_t)stream);
+}
+
+int gg_fast_reciprocal(const float *in, float *out, int64_t n, void *stream) {
+  if (!in || !out || n < 0) return fail(GG_ERR_INVALID, "gg_fast_reciprocal: bad arguments");
+  if (n == 0) return GG_OK;
+  return launch_fast_recip(in, out, n, (hipStream_t)stream);
+}
+
 int gg_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
   g_timing = on != 0;
@@ -616,3 +672,225 @@ int gg_timing_read(const char *name, double *total_ms, int64_t *launches) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched path
+
+struct gg_batch {
+  BatchPlan P;
+  std::vector<char> keep;  // nothing host-side is needed after creation
+};
+
+static int check_item(const gg_batch_item &it, int i) {
+  char what[64];
+  snprintf(what, sizeof what, "gg_batch_create: item %d", i);
+  if (int rc = check_sources(it.src, it.K, what)) return rc;
+  if (int rc = check_camera(&it.tgt, what)) return rc;
+  if (int rc = check_tsdf(&it.tsdf, what)) return rc;
+  if (!it.depth || !it.F || !it.W) return fail(GG_ERR_INVALID, "%s: NULL array argument", what);
+  if ((it.F_prev == nullptr) != (it.W_prev == nullptr))
+    return fail(GG_ERR_INVALID, "%s: F_prev and W_prev go together", what);
+  if ((it.out_depth == nullptr) != (it.out_bin == nullptr))
+    return fail(GG_ERR_INVALID, "%s: out_depth and out_bin go together", what);
+  if (it.rgb) {
+    if (int rc = check_splat(&it.splat, what)) return rc;
+    if (!it.win_idx || !it.sp_depth || !it.sp_rgb || !it.sp_alpha)
+      return fail(GG_ERR_INVALID, "%s: splat outputs required with rgb", what);
+  }
+  const int D = it.tsdf.num_bins;
+  const int V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+  if (D / V > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
+  const size_t va = 4 * (size_t)V;
+  if (!aligned(it.F, va) || !aligned(it.W, va) ||
+      (it.F_prev && (!aligned(it.F_prev, va) || !aligned(it.W_prev, va))))
+    return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", what, va);
+  return GG_OK;
+}
+
+extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tune,
+                               gg_batch **out) {
+  const char *N = "gg_batch_create";
+  if (!items || !out || n < 1) return fail(GG_ERR_INVALID, "%s: need items, n >= 1, out", N);
+  if (n > 65535) return fail(GG_ERR_UNSUPPORTED, "%s: at most 65535 items", N);
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (int rc = check_item(items[i], i)) return rc;
+  int threads = (tune && tune->volume_threads) ? tune->volume_threads : 256;
+  int per_cu = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu : 4;
+  if (threads < 64 || threads > 1024 || threads % 64 || per_cu < 1 || per_cu > 64)
+    return fail(GG_ERR_INVALID, "%s: volume_threads in 64..1024 (multiple of 64), "
+                "blocks_per_cu in 1..64", N);
+  for (int i = 0; i < n; ++i) {
+    const int D = items[i].tsdf.num_bins;
+    const int V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+    while (threads < D / V) threads += 64;
+  }
+  int dev = 0, cus = 256;
+  if (int rc = check_hip(hipGetDevice(&dev), N)) return rc;
+  if (int rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), N))
+    return rc;
+
+  // host descriptors, work lists and the device-memory layout
+  std::vector<BatchItem> h(n);
+  std::vector<WorkItem> conf, bin, raster, integ[3];
+  std::vector<uint32_t> splat_items;
+  std::vector<VolumeShape> shapes(n);
+  std::vector<SplatLayout> sl(n);
+  size_t off = up256(sizeof(BatchItem) * n);
+  std::vector<size_t> o_table(n), o_bins(n), o_splat(n);
+  size_t count_words = 0;
+  std::vector<size_t> o_count(n);
+  for (int i = 0; i < n; ++i) {
+    const gg_batch_item &it = items[i];
+    const int sw = it.src[0].width, sh = it.src[0].height, K = it.K, D = it.tsdf.num_bins;
+    const uint32_t npix = (uint32_t)(it.tgt.width * it.tgt.height);
+    VolumeShape &vs = shapes[i];
+    vs.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+    vs.cpp = (uint32_t)(D / vs.V);
+    vs.ppb = std::max(1u, (uint32_t)threads / vs.cpp);
+    vs.threads = vs.ppb * vs.cpp;
+    vs.nblocks = (npix + vs.ppb - 1) / vs.ppb;
+    vs.pw_shift = pick_pw_shift(vs.ppb, 8);
+    o_table[i] = off;
+    off += up256(8 * (size_t)sw * sh * K);
+    o_bins[i] = off;
+    off += up256(8 * (size_t)D);
+    if (it.rgb) {
+      if ((size_t)K * sw * sh * splat_tiles_per_splat(it.splat.r_max_px) > 0xffffffffull)
+        return fail(GG_ERR_UNSUPPORTED, "%s: item %d has too many source pixels", N, i);
+      sl[i] = splat_layout(K, sw, sh, it.tgt.width, it.tgt.height, &it.splat);
+      o_splat[i] = off;
+      off += sl[i].total;
+      o_count[i] = count_words;
+      count_words += (size_t)K * sl[i].ntiles + 1;
+    }
+    const uint32_t ctx = (uint32_t)((sw + kConfTX - 1) / kConfTX),
+                   cty = (uint32_t)((sh + kConfTY - 1) / kConfTY);
+    if (ctx > 65535 || cty > 65535) return fail(GG_ERR_UNSUPPORTED, "%s: image too large", N);
+    for (int k = 0; k < K; ++k)
+      for (uint32_t y = 0; y < cty; ++y)
+        for (uint32_t x = 0; x < ctx; ++x)
+          conf.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)x, (uint16_t)y});
+    if (it.rgb) {
+      splat_items.push_back((uint32_t)i);
+      const uint32_t nb = ((uint32_t)(sw * sh) + 255u) / 256u;
+      for (int k = 0; k < K; ++k) {
+        for (uint32_t b = 0; b < nb; ++b)
+          bin.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)(b & 0xffff), (uint16_t)(b >> 16)});
+        for (uint32_t t = 0; t < sl[i].ntiles; ++t)
+          raster.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
+      }
+    }
+    const int g = vs.V == 4 ? 0 : (vs.V == 2 ? 1 : 2);
+    for (uint32_t t = 0; t < vs.nblocks; ++t)
+      integ[g].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
+  }
+  const size_t o_counts = off;
+  off += up256(4 * (count_words ? count_words : 1));
+  auto put = [&](size_t bytes) { const size_t o = off; off += up256(bytes ? bytes : 1); return o; };
+  const size_t o_conf = put(sizeof(WorkItem) * conf.size()), o_bin = put(sizeof(WorkItem) * bin.size()),
+               o_raster = put(sizeof(WorkItem) * raster.size());
+  size_t o_integ[3];
+  for (int g = 0; g < 3; ++g) o_integ[g] = put(sizeof(WorkItem) * integ[g].size());
+  const size_t o_sitems = put(4 * splat_items.size());
+
+  gg_batch *b = new gg_batch();
+  BatchPlan &P = b->P;
+  P.n_items = n;
+  P.cus = cus;
+  P.blocks_per_cu = per_cu;
+  P.integ_threads = (uint32_t)threads;
+  P.dev_bytes = off;
+  if (int rc = check_hip(hipMalloc(&P.dev, off), N)) {
+    delete b;
+    return rc;
+  }
+  char *dv = (char *)P.dev;
+  for (int i = 0; i < n; ++i) {
+    const gg_batch_item &it = items[i];
+    BatchItem &d = h[i];
+    const int sw = it.src[0].width, sh = it.src[0].height;
+    float2 *table = (float2 *)(dv + o_table[i]);
+    float2 *bins = (float2 *)(dv + o_bins[i]);
+    d.conf = conf_args(it.depth, table, sw, sh, it.K, &it.tsdf);
+    make_integrate_args(d.integ, it.src, it.K, it.tgt, it.tsdf, shapes[i], table, bins,
+                        it.temporal_mask, it.F_prev, it.W_prev, it.F, it.W, it.out_depth,
+                        it.out_bin);
+    if (it.rgb) {
+      make_splat_args(d.splat, it.src, it.K, it.depth, it.rgb, it.tgt, it.splat, sl[i],
+                      dv + o_splat[i]);
+      d.splat.tile_count = (uint32_t *)(dv + o_counts) + o_count[i];
+      d.splat.win_idx = it.win_idx;
+      d.splat.out_depth = it.sp_depth;
+      d.splat.out_rgb = it.sp_rgb;
+      d.splat.out_alpha = it.sp_alpha;
+      d.splat.out_tape = it.sp_tape;
+    }
+    d.bins = bins;
+    d.D = it.tsdf.num_bins;
+    d.z_near = it.tsdf.z_near;
+    d.z_far = it.tsdf.z_far;
+    d.trunc = it.tsdf.trunc;
+    d.trunc_in_bins = it.tsdf.trunc_in_bins;
+  }
+  P.d_items = (BatchItem *)dv;
+  P.d_conf = (WorkItem *)(dv + o_conf);
+  P.n_conf = (uint32_t)conf.size();
+  P.d_bin = (WorkItem *)(dv + o_bin);
+  P.n_bin = (uint32_t)bin.size();
+  P.d_raster = (WorkItem *)(dv + o_raster);
+  P.n_raster = (uint32_t)raster.size();
+  for (int g = 0; g < 3; ++g) {
+    P.d_integ[g] = (WorkItem *)(dv + o_integ[g]);
+    P.n_integ[g] = (uint32_t)integ[g].size();
+  }
+  P.d_splat_items = (uint32_t *)(dv + o_sitems);
+  P.n_splat_items = (uint32_t)splat_items.size();
+  P.zero_ptr = (uint32_t *)(dv + o_counts);
+  P.zero_words = count_words;
+  int rc = GG_OK;
+  auto cp = [&](size_t o, const void *src, size_t bytes) {
+    if (rc == GG_OK && bytes) rc = check_hip(hipMemcpy(dv + o, src, bytes, hipMemcpyHostToDevice), N);
+  };
+  cp(0, h.data(), sizeof(BatchItem) * n);
+  cp(o_conf, conf.data(), sizeof(WorkItem) * conf.size());
+  cp(o_bin, bin.data(), sizeof(WorkItem) * bin.size());
+  cp(o_raster, raster.data(), sizeof(WorkItem) * raster.size());
+  for (int g = 0; g < 3; ++g) cp(o_integ[g], integ[g].data(), sizeof(WorkItem) * integ[g].size());
+  cp(o_sitems, splat_items.data(), 4 * splat_items.size());
+  // capture every phase into one graph
+  hipStream_t cs = nullptr;
+  if (rc == GG_OK) rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), N);
+  if (rc == GG_OK) rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), N);
+  if (rc == GG_OK) {
+    const int rr = batch_record(P, cs);
+    const int re = check_hip(hipStreamEndCapture(cs, &P.graph), N);
+    rc = rr ? rr : re;
+  }
+  if (rc == GG_OK) rc = check_hip(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0), N);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc != GG_OK) {
+    gg_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return GG_OK;
+}
+
+extern "C" int gg_batch_launch(gg_batch *plan, void *stream) {
+  if (!plan || !plan->P.exec) return fail(GG_ERR_INVALID, "gg_batch_launch: no plan");
+  KernelTimer t("batch_graph", (hipStream_t)stream);
+  return check_hip(hipGraphLaunch(plan->P.exec, (hipStream_t)stream), "gg_batch_launch");
+}
+
+extern "C" size_t gg_batch_device_bytes(const gg_batch *plan) { return plan ? plan->P.dev_bytes : 0; }
+
+extern "C" int gg_batch_destroy(gg_batch *plan) {
+  if (!plan) return GG_OK;
+  BatchPlan &P = plan->P;
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  if (P.dev) (void)hipFree(P.dev);
+  delete plan;
+  return GG_OK;
+}

@@ -1,0 +1,170 @@
+// Batched path: many target views of uneven resolution, view count and bin
+// count fused by persistent kernels over per-phase work lists, the whole
+// batch captured once into a hipGraph and replayed with one launch.
+//
+// Each work item runs the same device function as the plain entry points
+// (conf_tile, splat_bin_block, tile_scan_block, raster_tile,
+// integrate_tile), so every output is bitwise identical to the
+// corresponding plain call.  Work lists are grouped by item and split into
+// contiguous ranges per workgroup; workgroups are numbered XCD-aware so
+// each XCD walks a contiguous part of the list.
+#include <cstring>
+#include <vector>
+
+#include "batch_internal.h"
+
+namespace gg {
+
+// ---------------------------------------------------------------------------
+// device phases
+
+__global__ void batch_zero_kernel(uint32_t *p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void batch_bins_kernel(const BatchItem *__restrict__ items) {
+  const BatchItem &it = items[blockIdx.x];
+  for (int d = threadIdx.x; d < it.D; d += blockDim.x) {
+    const float un = 1.0f / it.z_near;
+    const float uf = 1.0f / it.z_far;
+    const float du = (un - uf) / (float)(it.D - 1);
+    const float u = un - (float)d * du;
+    const float z = 1.0f / u;
+    it.bins[d] = make_float2(z, it.trunc_in_bins ? (it.trunc * du) * (z * z) : it.trunc);
+  }
+}
+
+// The contiguous range of work this workgroup owns.
+__device__ __forceinline__ void my_range(uint32_t n, uint32_t &b, uint32_t &e) {
+  const uint32_t g = gridDim.x;
+  const uint32_t per = (n + g - 1) / g;
+  const uint32_t lb = xcd_tile(blockIdx.x, g);
+  b = min(lb * per, n);
+  e = min(b + per, n);
+}
+
+__global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__restrict__ items,
+                                                         const WorkItem *__restrict__ work,
+                                                         uint32_t n) {
+  __shared__ float tile[kConfTileFloats];
+  uint32_t b, e;
+  my_range(n, b, e);
+  for (uint32_t w = b; w < e; ++w) {
+    const WorkItem wi = work[w];
+    conf_tile(items[wi.item].conf, wi.k, wi.x, wi.y, tile);
+  }
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(256) void batch_bin_kernel(const BatchItem *__restrict__ items,
+                                                        const WorkItem *__restrict__ work,
+                                                        uint32_t n) {
+  uint32_t b, e;
+  my_range(n, b, e);
+  for (uint32_t w = b; w < e; ++w) {
+    const WorkItem wi = work[w];
+    splat_bin_block<kFill>(items[wi.item].splat, wi.k, work_tile(wi));
+  }
+}
+
+__global__ __launch_bounds__(1024) void batch_scan_kernel(const BatchItem *__restrict__ items,
+                                                          const uint32_t *__restrict__ list) {
+  __shared__ uint32_t s[1024];
+  const SplatArgs &a = items[list[blockIdx.x]].splat;
+  tile_scan_block(a.tile_count, a.tile_offset, a.tile_cursor, (uint32_t)a.K * a.ntiles, s);
+}
+
+__global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__restrict__ items,
+                                                           const WorkItem *__restrict__ work,
+                                                           uint32_t n) {
+  __shared__ RasterLds lds;
+  uint32_t b, e;
+  my_range(n, b, e);
+  for (uint32_t w = b; w < e; ++w) {
+    const WorkItem wi = work[w];
+    raster_tile(items[wi.item].splat, wi.k, work_tile(wi), lds);
+  }
+}
+
+// Fusion: one workgroup tile of one item per work entry; the view count
+// selects a specialisation (same operation order as the plain kernel).
+template <int V>
+__device__ __forceinline__ void batch_integrate_one(const IntegrateArgs &a, uint32_t tile,
+                                                    float *smem) {
+  if (a.exact_only) {
+    integrate_tile<V, 0, true>(a, tile, smem);
+    return;
+  }
+  switch (a.K) {
+    case 2: integrate_tile<V, 2, false>(a, tile, smem); break;
+    case 3: integrate_tile<V, 3, false>(a, tile, smem); break;
+    case 4: integrate_tile<V, 4, false>(a, tile, smem); break;
+    case 6: integrate_tile<V, 6, false>(a, tile, smem); break;
+    case 8: integrate_tile<V, 8, false>(a, tile, smem); break;
+    default: integrate_tile<V, 0, false>(a, tile, smem); break;
+  }
+}
+
+template <int V>
+__global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
+                                                               const WorkItem *__restrict__ work,
+                                                               uint32_t n) {
+  extern __shared__ float smem[];
+  uint32_t b, e;
+  my_range(n, b, e);
+  for (uint32_t w = b; w < e; ++w) {
+    const WorkItem wi = work[w];
+    batch_integrate_one<V>(items[wi.item].integ, work_tile(wi), smem);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan
+
+static int persistent_grid(uint32_t n, int per_cu, int cus) {
+  const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+  return (int)(n < g ? (n ? n : 1) : g);
+}
+
+int batch_record(BatchPlan &P, hipStream_t s) {
+  const int cus = P.cus, per = P.blocks_per_cu;
+  if (P.zero_words) {
+    hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
+  }
+  hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
+  if (P.n_conf)
+    hipLaunchKernelGGL(batch_conf_kernel, dim3(persistent_grid(P.n_conf, per, cus)), dim3(256), 0,
+                       s, P.d_items, P.d_conf, P.n_conf);
+  if (P.n_bin) {
+    hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(persistent_grid(P.n_bin, per, cus)),
+                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
+                       P.d_splat_items);
+    hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(persistent_grid(P.n_bin, per, cus)),
+                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin);
+    hipLaunchKernelGGL(batch_raster_kernel, dim3(persistent_grid(P.n_raster, per, cus)),
+                       dim3(256), 0, s, P.d_items, P.d_raster, P.n_raster);
+  }
+  for (int g = 0; g < 3; ++g) {
+    const uint32_t n = P.n_integ[g];
+    if (!n) continue;
+    const int V = g == 0 ? 4 : (g == 1 ? 2 : 1);
+    const uint32_t threads = P.integ_threads;
+    const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * threads;
+    const dim3 grid(persistent_grid(n, per, cus));
+    if (V == 4)
+      hipLaunchKernelGGL(batch_integrate_kernel<4>, grid, dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n);
+    else if (V == 2)
+      hipLaunchKernelGGL(batch_integrate_kernel<2>, grid, dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n);
+    else
+      hipLaunchKernelGGL(batch_integrate_kernel<1>, grid, dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n);
+  }
+  return check_hip(hipGetLastError(), "batch phases");
+}
+
+}  // namespace gg

@@ -50,6 +50,34 @@ void relproj(const gg_camera &a, const gg_camera &b, Proj &out);
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && d < INFINITY; }
 
+// Range in which recip_rn() is the correctly rounded reciprocal.
+constexpr float kRecipLo = 0x1p-100f, kRecipHi = 0x1p100f;
+
+// Correctly rounded 1/z for kRecipLo < z < kRecipHi: the hardware
+// approximation (v_rcp_f32, about 1 ulp) refined by one Newton-Raphson step
+// with fused multiply-adds, e = 1 - z y, y' = y + y e (Markstein's
+// correction).  The test suite compares it bitwise with IEEE division for
+// every FP32 significand over that exponent range.
+__device__ __forceinline__ float recip_rn(float z) {
+  const float y = __builtin_amdgcn_rcpf(z);
+  const float e = fmaf(-z, y, 1.0f);
+  return fmaf(y, e, y);
+}
+
+// 1/z, correctly rounded for every z > 0: the fast path above, else the
+// compiler's IEEE division (rare: depths below 2^-100 or above 2^100).
+__device__ __forceinline__ float recip_pos(float z) {
+  if (__builtin_expect(z > kRecipLo && z < kRecipHi, 1)) return recip_rn(z);
+  return 1.0f / z;
+}
+
+// floor(x) converted to int32 in one instruction (saturating; x finite).
+__device__ __forceinline__ int32_t floor_i32(float x) {
+  int32_t r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // h = H (px, py, 1)^T, one fused multiply-add chain per row.
 __device__ __forceinline__ void ray_of(const Proj &P, float px, float py, float &h0, float &h1,
                                        float &h2) {
@@ -97,9 +125,11 @@ struct IntegrateArgs {
   FastDiv wt_div;    // by Wt
   FastDiv cpp_div;   // by chunks per pixel (D / V)
   uint32_t cpp, ppb; // chunks per pixel, pixels per workgroup
+  uint32_t pw_shift; // 2^pw_shift neighbouring pixels share each wavefront row
   uint32_t nblocks;
   float decay, cap;
   int32_t carry;
+  int32_t exact_only;  // 1: every sample takes IEEE division (extreme depths)
 };
 
 struct ExtractArgs {
@@ -144,6 +174,9 @@ int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_
 int launch_extract(const ExtractArgs &a, int V, uint32_t threads, hipStream_t s);
 int launch_extract_backward(const ExtractArgs &a, hipStream_t s);
 int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s);
+int launch_recip_selftest(uint32_t e_lo, uint32_t n_exp, unsigned long long *mismatches,
+                          hipStream_t s);
+int launch_fast_recip(const float *in, float *out, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // splatting (splat.hip)

@@ -16,131 +16,19 @@
 //            reductions, so the result does not depend on the order in which
 //            list entries arrive: winners are bitwise reproducible and the
 //            colour is deterministic.
-#include <climits>
-
-#include "ggeom_internal.h"
+#include "splat_device.h"
 
 namespace gg {
 
-struct SplatGeom {
-  bool ok;
-  float x, y, z, s2, R2;
-  int a0, a1, b0, b1;  // candidate window (superset of covered pixels)
-};
-
-// Footprint of source pixel (i, j) at depth D in the target.
-__device__ __forceinline__ SplatGeom splat_geom(const SplatView &V, float D, uint32_t i,
-                                                uint32_t j, const SplatArgs &a) {
-  SplatGeom g;
-  g.ok = false;
-  if (!depth_ok(D)) return g;
-  float h0, h1, h2;
-  ray_of(V.P, (float)i + 0.5f, (float)j + 0.5f, h0, h1, h2);
-  const float X0 = fmaf(D, h0, V.P.c[0]);
-  const float X1 = fmaf(D, h1, V.P.c[1]);
-  const float Z = fmaf(D, h2, V.P.c[2]);
-  if (!(Z > a.zmin)) return g;
-  const float inv = 1.0f / Z;
-  g.x = X0 * inv;
-  g.y = X1 * inv;
-  g.z = Z;
-  const float sig = V.sscale * (D * inv);
-  g.s2 = sig * sig;
-  g.R2 = fminf(2.0f * g.s2, a.rmax2);
-  const float r = sqrtf(g.R2);
-  float ax0 = floorf(g.x - 0.5f - r) - 1.0f, ax1 = floorf(g.x - 0.5f + r) + 1.0f;
-  float by0 = floorf(g.y - 0.5f - r) - 1.0f, by1 = floorf(g.y - 0.5f + r) + 1.0f;
-  ax0 = fmaxf(ax0, 0.0f);
-  by0 = fmaxf(by0, 0.0f);
-  ax1 = fminf(ax1, (float)(a.Wt - 1));
-  by1 = fminf(by1, (float)(a.Ht - 1));
-  if (!(ax0 <= ax1 && by0 <= by1)) return g;
-  g.a0 = (int)ax0;
-  g.a1 = (int)ax1;
-  g.b0 = (int)by0;
-  g.b1 = (int)by1;
-  g.ok = true;
-  return g;
-}
-
-__device__ __forceinline__ float cover_d2(const SplatGeom &g, int aa, int b) {
-  const float dx = ((float)aa + 0.5f) - g.x;
-  const float dy = ((float)b + 0.5f) - g.y;
-  return fmaf(dx, dx, dy * dy);
-}
-
-// Wavefront-aggregated atomicAdd: lanes with the same key share one atomic;
-// each gets a distinct slot base + rank.
-__device__ __forceinline__ uint32_t aggregated_slot(uint32_t *counters, uint32_t key, bool has) {
-  uint32_t slot = 0;
-  unsigned long long pending = __ballot(has);
-  const int lane = __lane_id();
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lkey = __shfl(key, leader);
-    const bool mine = has && key == lkey;
-    const unsigned long long grp = __ballot(mine);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counters[lkey], (uint32_t)__popcll(grp));
-    base = __shfl(base, leader);
-    if (mine) slot = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
-    pending &= ~grp;
-  }
-  return slot;
-}
-
 template <bool kFill>
 __global__ __launch_bounds__(256) void splat_bin_kernel(SplatArgs a) {
-  const int k = blockIdx.y;
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  int tx0 = 0, ty0 = 0, nx = 0, n = 0;
-  if (q < a.ns) {
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(a.views[k], a.depth[(size_t)k * a.ns + q], i, j, a);
-    if (g.ok) {
-      tx0 = g.a0 / kTile;
-      ty0 = g.b0 / kTile;
-      nx = g.a1 / kTile - tx0 + 1;
-      n = nx * (g.b1 / kTile - ty0 + 1);
-    }
-  }
-  uint32_t *cnt = (kFill ? a.tile_cursor : a.tile_count) + (size_t)k * a.ntiles;
-  for (int s = 0;; ++s) {
-    const bool has = s < n;
-    if (__ballot(has) == 0ull) break;
-    const uint32_t tile = has ? (uint32_t)((ty0 + s / nx) * a.ntx + (tx0 + s % nx)) : 0u;
-    const uint32_t slot = aggregated_slot(cnt, tile, has);
-    if (kFill && has) {
-      const uint32_t pos = a.tile_offset[(size_t)k * a.ntiles + tile] + slot;
-      if (pos < a.list_cap) a.list[pos] = q;
-    }
-  }
+  splat_bin_block<kFill>(a, blockIdx.y, blockIdx.x);
 }
 
-// Exclusive scan of n counters by one workgroup; also clears the cursors.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint32_t *off,
                                                          uint32_t *cursor, uint32_t n) {
   __shared__ uint32_t s[1024];
-  const uint32_t t = threadIdx.x;
-  const uint32_t per = (n + 1023u) / 1024u;
-  const uint32_t b = t * per, e = min(b + per, n);
-  uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += cnt[i];
-  s[t] = sum;
-  __syncthreads();
-  for (uint32_t o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = t >= o ? s[t - o] : 0u;
-    __syncthreads();
-    s[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = s[t] - sum;
-  for (uint32_t i = b; i < e; ++i) {
-    off[i] = run;
-    run += cnt[i];
-    cursor[i] = 0u;
-  }
-  if (t == 1023) off[n] = s[1023];
+  tile_scan_block(cnt, off, cursor, n, s);
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
@@ -148,105 +36,9 @@ __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
     p[i] = 0u;
 }
 
-constexpr double kFixG = 1099511627776.0;  // 2^40: sums of G and G c
-constexpr double kFixL = 4294967296.0;     // 2^32: sums of log(1 - G)
-
 __global__ __launch_bounds__(256) void splat_raster_kernel(SplatArgs a) {
-  __shared__ unsigned long long zkey[kTile * kTile];
-  __shared__ unsigned long long sG[kTile * kTile], sR[kTile * kTile], sGr[kTile * kTile],
-      sB[kTile * kTile], sL[kTile * kTile];
-  __shared__ uint32_t sOnes[kTile * kTile];
-  const int k = blockIdx.y;
-  const uint32_t tile = blockIdx.x;
-  const int tyi = (int)(tile / (uint32_t)a.ntx), txi = (int)tile - tyi * a.ntx;
-  const int ax0 = txi * kTile, by0 = tyi * kTile;
-  const uint32_t t = threadIdx.x;
-  zkey[t] = ~0ull;
-  sG[t] = sR[t] = sGr[t] = sB[t] = sL[t] = 0ull;
-  sOnes[t] = 0u;
-  __syncthreads();
-  const size_t ti = (size_t)k * a.ntiles + tile;
-  const uint32_t beg = a.tile_offset[ti], end = min(a.tile_offset[ti + 1], a.list_cap);
-  const SplatView &V = a.views[k];
-  const float *dk = a.depth + (size_t)k * a.ns;
-  const uint8_t *ck = a.rgb + (size_t)k * a.ns * 3;
-  // z-test
-  for (uint32_t e = beg + t; e < end; e += blockDim.x) {
-    const uint32_t q = a.list[e];
-    if (q >= a.ns) continue;
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(V, dk[q], i, j, a);
-    if (!g.ok) continue;
-    const unsigned long long key = ((unsigned long long)__float_as_uint(g.z) << 32) | q;
-    const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
-    const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);
-    for (int b = b0; b <= b1; ++b)
-      for (int aa = a0; aa <= a1; ++aa)
-        if (cover_d2(g, aa, b) <= g.R2) atomicMin(&zkey[(b - by0) * kTile + (aa - ax0)], key);
-  }
-  __syncthreads();
-  // band blend
-  for (uint32_t e = beg + t; e < end; e += blockDim.x) {
-    const uint32_t q = a.list[e];
-    if (q >= a.ns) continue;
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(V, dk[q], i, j, a);
-    if (!g.ok) continue;
-    const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
-    const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);
-    for (int b = b0; b <= b1; ++b)
-      for (int aa = a0; aa <= a1; ++aa) {
-        const float d2 = cover_d2(g, aa, b);
-        if (!(d2 <= g.R2)) continue;
-        const int lp = (b - by0) * kTile + (aa - ax0);
-        const float zw = __uint_as_float((uint32_t)(zkey[lp] >> 32));
-        if (!(g.z <= zw * a.band)) continue;
-        const float G = expf((-0.5f * d2) / g.s2);
-        const float c0 = (float)ck[3 * (size_t)q + 0] / 255.0f;
-        const float c1 = (float)ck[3 * (size_t)q + 1] / 255.0f;
-        const float c2 = (float)ck[3 * (size_t)q + 2] / 255.0f;
-        atomicAdd(&sG[lp], (unsigned long long)llrint((double)G * kFixG));
-        atomicAdd(&sR[lp], (unsigned long long)llrint((double)(G * c0) * kFixG));
-        atomicAdd(&sGr[lp], (unsigned long long)llrint((double)(G * c1) * kFixG));
-        atomicAdd(&sB[lp], (unsigned long long)llrint((double)(G * c2) * kFixG));
-        if (G < 1.0f)
-          atomicAdd(&sL[lp], (unsigned long long)llrint((double)logf(1.0f - G) * kFixL));
-        else
-          atomicAdd(&sOnes[lp], 1u);
-      }
-  }
-  __syncthreads();
-  const int px = ax0 + (int)(t % kTile), py = by0 + (int)(t / kTile);
-  if (px >= a.Wt || py >= a.Ht) return;
-  const size_t p = (size_t)py * a.Wt + px;
-  const size_t o = (size_t)k * a.nt + p;
-  const unsigned long long wk = zkey[t];
-  float* rgb = a.out_rgb + (size_t)k * 3 * a.nt;
-  if (wk == ~0ull) {
-    a.win_idx[o] = -1;
-    a.out_depth[o] = 0.0f;
-    a.out_alpha[o] = 0.0f;
-    rgb[p] = rgb[a.nt + p] = rgb[2 * a.nt + p] = 0.0f;
-    if (a.out_tape) {
-      float *tp = a.out_tape + (size_t)k * 3 * a.nt;
-      tp[p] = tp[a.nt + p] = tp[2 * a.nt + p] = 0.0f;
-    }
-    return;
-  }
-  a.win_idx[o] = (int32_t)(uint32_t)(wk & 0xffffffffull);
-  a.out_depth[o] = __uint_as_float((uint32_t)(wk >> 32));
-  const double sg = (double)(long long)sG[t];
-  rgb[p] = (float)((double)(long long)sR[t] / sg);
-  rgb[a.nt + p] = (float)((double)(long long)sGr[t] / sg);
-  rgb[2 * a.nt + p] = (float)((double)(long long)sB[t] / sg);
-  const double L = (double)(long long)sL[t] / kFixL;
-  a.out_alpha[o] = sOnes[t] ? 1.0f : (float)(1.0 - exp(L));
-  if (a.out_tape) {
-    float *tp = a.out_tape + (size_t)k * 3 * a.nt;
-    tp[p] = (float)(sg / kFixG);
-    tp[a.nt + p] = (float)L;
-    tp[2 * a.nt + p] = (float)sOnes[t];
-  }
+  __shared__ RasterLds L;
+  raster_tile(a, blockIdx.y, blockIdx.x, L);
 }
 
 uint32_t splat_tiles_per_splat(float r_max) {

@@ -9,22 +9,12 @@
 // multiply-adds are explicit fmaf; divide and square root are correctly
 // rounded) so that the volume and the extracted bins are bitwise
 // reproducible and equal to the plain definition.
-#include <climits>
-
-#include "ggeom_internal.h"
+#include "tsdf_device.h"
 
 namespace gg {
 
 // ---------------------------------------------------------------------------
 // depth bins: z_d = 1 / (1/z_near - d du), tau_d = trunc du z_d^2 (in bins)
-
-__device__ __forceinline__ float bin_depth(int d, int D, float z_near, float z_far) {
-  const float un = 1.0f / z_near;
-  const float uf = 1.0f / z_far;
-  const float du = (un - uf) / (float)(D - 1);
-  const float u = un - (float)d * du;
-  return 1.0f / u;
-}
 
 __global__ void bins_kernel(int32_t D, float z_near, float z_far, float trunc, int32_t in_bins,
                             float2 *out) {
@@ -50,69 +40,9 @@ int launch_bins(const gg_tsdf_params &p, float2 *bins, hipStream_t s) {
 // view table (usable depth, or -inf for a hole so that the occlusion test
 // drops it; omega), one 8-byte record per pixel, gathered by the fusion.
 
-constexpr int kConfTX = 32, kConfTY = 8, kMaxR = (GG_MAX_WINDOW - 1) / 2;
-constexpr int kConfLW = kConfTX + 2 * kMaxR, kConfLH = kConfTY + 2 * kMaxR;
-
-// nu of Suppl. A.1 at pixel (i, j) with centre depth dq, reading the staged
-// tile (origin at image (i0 - r, j0 - r)); row-major over the window.
-__device__ __forceinline__ float window_nu(const float *tile, int li, int lj, int i, int j,
-                                           float dq, const ConfArgs &a) {
-  const int r = a.radius;
-  float nu = 0.0f;
-  for (int dy = -r; dy <= r; ++dy) {
-    const int jj = j + dy;
-    if (jj < 0 || jj >= a.Hs) continue;
-    for (int dx = -r; dx <= r; ++dx) {
-      const int ii = i + dx;
-      if (ii < 0 || ii >= a.Ws) continue;
-      const float dn = tile[(lj + dy) * kConfLW + (li + dx)];
-      float term;
-      if (depth_ok(dn)) {
-        const float dd = dq - dn;
-        term = fminf(dd * dd, a.tw2);
-      } else {
-        term = a.tw2;
-      }
-      nu = nu + term;
-    }
-  }
-  return nu;
-}
-
-__device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
-                                           const ConfArgs &a) {
-  const int r = a.radius;
-  const int tw = kConfTX + 2 * r, th = kConfTY + 2 * r;
-  for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
-    const int ly = e / tw, lx = e - ly * tw;
-    const int gi = i0 - r + lx, gj = j0 - r + ly;
-    float v = 0.0f;
-    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = dk[(size_t)gj * a.Ws + gi];
-    // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
-    // relative to the fixed centre origin
-    tile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
-  }
-}
-
 __global__ __launch_bounds__(256) void conf_kernel(ConfArgs a) {
   __shared__ float tile[kConfLH * kConfLW];
-  const int k = blockIdx.z;
-  const int i0 = blockIdx.x * kConfTX, j0 = blockIdx.y * kConfTY;
-  const float *dk = a.depth + (size_t)k * a.Ws * a.Hs;
-  stage_tile(tile, dk, i0, j0, a);
-  __syncthreads();
-  const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
-  const int i = i0 + lx, j = j0 + ly;
-  if (i >= a.Ws || j >= a.Hs) return;
-  const int li = lx + kMaxR, lj = ly + kMaxR;
-  const float dq = tile[lj * kConfLW + li];
-  float2 rec = make_float2(-INFINITY, 0.0f);
-  if (depth_ok(dq)) {
-    const float nu = window_nu(tile, li, lj, i, j, dq, a);
-    const float om = (nu == 0.0f) ? 1.0f : fminf(a.scale / sqrtf(nu / a.n2), 1.0f);
-    rec = make_float2(dq, om);
-  }
-  a.table[(size_t)k * a.Ws * a.Hs + (size_t)j * a.Ws + i] = rec;
+  conf_tile(a, blockIdx.z, blockIdx.x, blockIdx.y, tile);
 }
 
 int launch_conf(const ConfArgs &a, hipStream_t s) {
@@ -122,178 +52,33 @@ int launch_conf(const ConfArgs &a, hipStream_t s) {
   return check_hip(hipGetLastError(), "conf_kernel");
 }
 
-// ---------------------------------------------------------------------------
-// vector access of V consecutive floats (V = 4, 2, 1)
-
-template <int V>
-__device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
-  if constexpr (V == 4) {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-  } else if constexpr (V == 2) {
-    const float2 v = *reinterpret_cast<const float2 *>(p);
-    o[0] = v.x; o[1] = v.y;
-  } else {
-    o[0] = *p;
-  }
-}
-
-template <int V>
-__device__ __forceinline__ void storev(float *p, const float (&o)[V]) {
-  if constexpr (V == 4) {
-    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
-  } else if constexpr (V == 2) {
-    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
-  } else {
-    *p = o[0];
-  }
-}
-
-// First crossing inside this thread's V bins, given the next chunk's first
-// bin (F, W); INT_MAX if none.
-template <int V>
-__device__ __forceinline__ int local_crossing(const float (&F)[V], const float (&W)[V], float nF,
-                                              float nW, int d0, int D) {
-  int cand = INT_MAX;
-#pragma unroll
-  for (int v = V - 1; v >= 0; --v) {
-    const float f1 = (v + 1 < V) ? F[(v + 1) % V] : nF;
-    const float w1 = (v + 1 < V) ? W[(v + 1) % V] : nW;
-    if (d0 + v + 1 < D && W[v] > 0.0f && w1 > 0.0f && F[v] > 0.0f && f1 <= 0.0f) cand = d0 + v;
-  }
-  return cand;
-}
-
-// Extraction across the workgroup: each thread holds V bins of one pixel;
-// the chunk's first bin is exchanged through LDS, the smallest crossing per
-// pixel is an LDS atomic minimum (order-free), and the owning thread
-// interpolates.  zf(d) returns z_d for the owning thread.
-template <int V, typename ZF>
-__device__ __forceinline__ void extract_block(const float (&F)[V], const float (&W)[V],
-                                              bool active, uint32_t pix, uint32_t lp,
-                                              uint32_t chunk, uint32_t cpp, int d0, int D,
-                                              float *sF, float *sW, int *sBest,
-                                              float *out_depth, int32_t *out_bin, ZF zf) {
-  const uint32_t t = threadIdx.x;
-  sF[t] = F[0];
-  sW[t] = W[0];
-  if (chunk == 0) sBest[lp] = INT_MAX;
-  __syncthreads();
-  const bool has_next = chunk + 1 < cpp;
-  const float nF = has_next ? sF[t + 1] : 0.0f;
-  const float nW = has_next ? sW[t + 1] : 0.0f;
-  if (active) {
-    const int cand = local_crossing<V>(F, W, nF, nW, d0, D);
-    if (cand != INT_MAX) atomicMin(&sBest[lp], cand);
-  }
-  __syncthreads();
-  if (!active) return;
-  const int best = sBest[lp];
-  if (best == INT_MAX) {
-    if (chunk == 0) {
-      out_depth[pix] = 0.0f;
-      out_bin[pix] = -1;
-    }
-    return;
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    if (best == d0 + v) {
-      const float f0 = F[v];
-      const float f1 = (v + 1 < V) ? F[(v + 1) % V] : nF;
-      const float za = zf(best), zb = zf(best + 1);
-      const float frac = f0 / (f0 - f1);
-      out_depth[pix] = za + (zb - za) * frac;
-      out_bin[pix] = best;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// fused integrate + extraction.  Workgroup = ppb whole pixels; thread = V
-// consecutive bins of one pixel (the volume is D-innermost, so a wavefront
-// reads and writes one contiguous span of F and W: fully coalesced).
-
-template <int V>
+template <int V, int KC, bool kExact>
 __global__ __launch_bounds__(1024) void integrate_kernel(IntegrateArgs a) {
   extern __shared__ float smem[];
-  float *sF = smem;
-  float *sW = smem + blockDim.x;
-  int *sBest = reinterpret_cast<int *>(smem + 2 * blockDim.x);
+  integrate_tile<V, KC, kExact>(a, xcd_tile(blockIdx.x, a.nblocks), smem);
+}
 
-  const uint32_t t = threadIdx.x;
-  const uint32_t lp = fdiv(t, a.cpp_div);
-  const uint32_t chunk = t - lp * a.cpp;
-  const uint32_t tile = xcd_tile(blockIdx.x, a.nblocks);
-  const uint32_t pix = tile * a.ppb + lp;
-  const bool active = pix < a.npix;
-  const int d0 = (int)chunk * V;
+template <int V, int KC>
+static void launch_integrate_vk(const IntegrateArgs &a, uint32_t threads, size_t shm,
+                                hipStream_t s) {
+  if (a.exact_only)
+    hipLaunchKernelGGL((integrate_kernel<V, KC, true>), dim3(a.nblocks), dim3(threads), shm, s, a);
+  else
+    hipLaunchKernelGGL((integrate_kernel<V, KC, false>), dim3(a.nblocks), dim3(threads), shm, s,
+                       a);
+}
 
-  float z[V], tau[V], S[V], Wo[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const float2 b = a.bins[d0 + v];
-    z[v] = b.x;
-    tau[v] = b.y;
-    S[v] = 0.0f;
-    Wo[v] = 0.0f;
-  }
-  float Fn[V], Wn[V];
-  if (active) {
-    const uint32_t y = fdiv(pix, a.wt_div);
-    const uint32_t x = pix - y * a.wt_div.d;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const float fWs = (float)a.Ws, fHs = (float)a.Hs;
-    for (int k = 0; k < a.K; ++k) {
-      const Proj &P = a.views[k];
-      float h0, h1, h2;
-      ray_of(P, px, py, h0, h1, h2);
-      const float2 *tab = a.table + (size_t)k * a.ns;
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const float X0 = fmaf(z[v], h0, P.c[0]);
-        const float X1 = fmaf(z[v], h1, P.c[1]);
-        const float Z = fmaf(z[v], h2, P.c[2]);
-        if (Z > 0.0f) {
-          const float inv = 1.0f / Z;
-          const float u = X0 * inv, w = X1 * inv;
-          if (u >= 0.0f && u < fWs && w >= 0.0f && w < fHs) {
-            const float2 e = tab[(uint32_t)w * (uint32_t)a.Ws + (uint32_t)u];
-            const float s = e.x - Z;  // -inf for a hole: dropped below
-            if (!(s < -tau[v])) {
-              const float c = fminf(s, tau[v]);
-              S[v] = fmaf(e.y, c, S[v]);
-              Wo[v] = Wo[v] + e.y;
-            }
-          }
-        }
-      }
-    }
-    const size_t base = (size_t)pix * a.D + d0;
-    float Fp[V], Wp[V];
-    if (a.carry) {
-      loadv<V>(a.F_prev + base, Fp);
-      loadv<V>(a.W_prev + base, Wp);
-    }
-    const float m = a.mask ? fmaxf(1.0f - a.mask[pix], 0.0f) : 1.0f;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const float wp = a.carry ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
-      const float Fpv = a.carry ? Fp[v] : 0.0f;
-      const float wn = wp + Wo[v];
-      Fn[v] = (wn > 0.0f) ? fmaf(wp, Fpv, S[v]) / wn : 0.0f;
-      Wn[v] = wn;
-    }
-    storev<V>(a.F + base, Fn);
-    storev<V>(a.W + base, Wn);
-  } else {
-#pragma unroll
-    for (int v = 0; v < V; ++v) Fn[v] = Wn[v] = 0.0f;
-  }
-  if (a.out_depth) {
-    const float2 *bins = a.bins;
-    extract_block<V>(Fn, Wn, active, pix, lp, chunk, a.cpp, d0, a.D, sF, sW, sBest, a.out_depth,
-                     a.out_bin, [bins](int d) { return bins[d].x; });
+template <int V>
+static void launch_integrate_v(const IntegrateArgs &a, uint32_t threads, size_t shm,
+                               hipStream_t s) {
+  switch (a.K) {
+    case 1: launch_integrate_vk<V, 1>(a, threads, shm, s); break;
+    case 2: launch_integrate_vk<V, 2>(a, threads, shm, s); break;
+    case 3: launch_integrate_vk<V, 3>(a, threads, shm, s); break;
+    case 4: launch_integrate_vk<V, 4>(a, threads, shm, s); break;
+    case 6: launch_integrate_vk<V, 6>(a, threads, shm, s); break;
+    case 8: launch_integrate_vk<V, 8>(a, threads, shm, s); break;
+    default: launch_integrate_vk<V, 0>(a, threads, shm, s); break;
   }
 }
 
@@ -301,11 +86,11 @@ int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_
   KernelTimer t("integrate", s);
   const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * a.ppb;
   if (V == 4)
-    hipLaunchKernelGGL(integrate_kernel<4>, dim3(a.nblocks), dim3(threads), shm, s, a);
+    launch_integrate_v<4>(a, threads, shm, s);
   else if (V == 2)
-    hipLaunchKernelGGL(integrate_kernel<2>, dim3(a.nblocks), dim3(threads), shm, s, a);
+    launch_integrate_v<2>(a, threads, shm, s);
   else
-    hipLaunchKernelGGL(integrate_kernel<1>, dim3(a.nblocks), dim3(threads), shm, s, a);
+    launch_integrate_v<1>(a, threads, shm, s);
   return check_hip(hipGetLastError(), "integrate_kernel");
 }
 
@@ -325,7 +110,7 @@ __global__ __launch_bounds__(1024) void extract_kernel(ExtractArgs a) {
   const uint32_t pix = tile * a.ppb + lp;
   const bool active = pix < a.npix;
   const int d0 = (int)chunk * V;
-  float F[V], W[V];
+  float F[V], W[V];  // launched with exactly ppb * cpp threads: every lane used
   if (active) {
     loadv<V>(a.F + (size_t)pix * a.D + d0, F);
     loadv<V>(a.W + (size_t)pix * a.D + d0, W);
@@ -335,7 +120,7 @@ __global__ __launch_bounds__(1024) void extract_kernel(ExtractArgs a) {
   }
   const int D = a.D;
   const float zn = a.z_near, zf = a.z_far;
-  extract_block<V>(F, W, active, pix, lp, chunk, a.cpp, d0, D, sF, sW, sBest, a.out_depth,
+  extract_block<V>(F, W, true, active, pix, lp, chunk, a.cpp, 1u, d0, D, sF, sW, sBest, a.out_depth,
                    a.out_bin, [D, zn, zf](int d) { return bin_depth(d, D, zn, zf); });
 }
 
@@ -582,6 +367,42 @@ int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s) {
   KernelTimer t("tsdf_bwd_finish", s);
   hipLaunchKernelGGL(tsdf_bwd_finish_kernel, gs, dim3(256), 0, s, a);
   return check_hip(hipGetLastError(), "tsdf_bwd_finish_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// self-check of the fast reciprocal against IEEE division (test hook)
+
+__global__ void recip_selftest_kernel(uint32_t e_lo, uint32_t n_exp,
+                                      unsigned long long *mismatches) {
+  const uint64_t n = (uint64_t)n_exp << 23;
+  unsigned long long bad = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t bits = ((e_lo + (uint32_t)(i >> 23)) << 23) | (uint32_t)(i & 0x7fffffu);
+    const float z = __uint_as_float(bits);
+    const float a = recip_rn(z);
+    const float b = 1.0f / z;
+    bad += (__float_as_uint(a) != __float_as_uint(b)) ? 1ull : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(mismatches, bad);
+}
+
+__global__ void fast_recip_kernel(const float *in, float *out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = recip_pos(in[i]);
+}
+
+int launch_recip_selftest(uint32_t e_lo, uint32_t n_exp, unsigned long long *mismatches,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(recip_selftest_kernel, dim3(2048), dim3(256), 0, s, e_lo, n_exp, mismatches);
+  return check_hip(hipGetLastError(), "recip_selftest_kernel");
+}
+
+int launch_fast_recip(const float *in, float *out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fast_recip_kernel, dim3(1024), dim3(256), 0, s, in, out, n);
+  return check_hip(hipGetLastError(), "fast_recip_kernel");
 }
 
 }  // namespace gg

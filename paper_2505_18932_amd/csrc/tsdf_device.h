@@ -1,0 +1,345 @@
+// Device functions of the fusion (Suppl. A.1, A.2) shared by the plain
+// kernels (tsdf.hip) and the batched persistent kernels (batch.hip): one
+// definition, so both paths perform the identical operation sequence.
+#pragma once
+
+#include <climits>
+
+#include "ggeom_internal.h"
+
+namespace gg {
+
+// depth bins: z_d = 1 / (1/z_near - d du)
+__device__ __forceinline__ float bin_depth(int d, int D, float z_near, float z_far) {
+  const float un = 1.0f / z_near;
+  const float uf = 1.0f / z_far;
+  const float du = (un - uf) / (float)(D - 1);
+  const float u = un - (float)d * du;
+  return 1.0f / u;
+}
+
+// ---------------------------------------------------------------------------
+// fusion weight (Suppl. A.1)
+
+constexpr int kConfTX = 32, kConfTY = 8, kMaxR = (GG_MAX_WINDOW - 1) / 2;
+constexpr int kConfLW = kConfTX + 2 * kMaxR, kConfLH = kConfTY + 2 * kMaxR;
+
+// nu of Suppl. A.1 at pixel (i, j) with centre depth dq, reading the staged
+// tile (origin at image (i0 - r, j0 - r)); row-major over the window.
+__device__ __forceinline__ float window_nu(const float *tile, int li, int lj, int i, int j,
+                                           float dq, const ConfArgs &a) {
+  const int r = a.radius;
+  float nu = 0.0f;
+  for (int dy = -r; dy <= r; ++dy) {
+    const int jj = j + dy;
+    if (jj < 0 || jj >= a.Hs) continue;
+    for (int dx = -r; dx <= r; ++dx) {
+      const int ii = i + dx;
+      if (ii < 0 || ii >= a.Ws) continue;
+      const float dn = tile[(lj + dy) * kConfLW + (li + dx)];
+      float term;
+      if (depth_ok(dn)) {
+        const float dd = dq - dn;
+        term = fminf(dd * dd, a.tw2);
+      } else {
+        term = a.tw2;
+      }
+      nu = nu + term;
+    }
+  }
+  return nu;
+}
+
+__device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
+                                           const ConfArgs &a) {
+  const int r = a.radius;
+  const int tw = kConfTX + 2 * r, th = kConfTY + 2 * r;
+  for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
+    const int ly = e / tw, lx = e - ly * tw;
+    const int gi = i0 - r + lx, gj = j0 - r + ly;
+    float v = 0.0f;
+    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = dk[(size_t)gj * a.Ws + gi];
+    // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
+    // relative to the fixed centre origin
+    tile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
+  }
+}
+
+// One 32 x 8 tile (bx, by) of view k; tile: LDS of kConfLH x kConfLW floats.
+__device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int by, float *tile) {
+  const int i0 = bx * kConfTX, j0 = by * kConfTY;
+  const float *dk = a.depth + (size_t)k * a.Ws * a.Hs;
+  stage_tile(tile, dk, i0, j0, a);
+  __syncthreads();
+  const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
+  const int i = i0 + lx, j = j0 + ly;
+  if (ly < kConfTY && i < a.Ws && j < a.Hs) {
+    const int li = lx + kMaxR, lj = ly + kMaxR;
+    const float dq = tile[lj * kConfLW + li];
+    float2 rec = make_float2(-INFINITY, 0.0f);
+    if (depth_ok(dq)) {
+      const float nu = window_nu(tile, li, lj, i, j, dq, a);
+      const float om = (nu == 0.0f) ? 1.0f : fminf(a.scale / sqrtf(nu / a.n2), 1.0f);
+      rec = make_float2(dq, om);
+    }
+    a.table[(size_t)k * a.Ws * a.Hs + (size_t)j * a.Ws + i] = rec;
+  }
+  __syncthreads();  // the tile may be restaged by the caller's next iteration
+}
+
+// ---------------------------------------------------------------------------
+// vector access of V consecutive floats (V = 4, 2, 1)
+
+template <int V>
+__device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
+  if constexpr (V == 4) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else if constexpr (V == 2) {
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    o[0] = v.x; o[1] = v.y;
+  } else {
+    o[0] = *p;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void storev(float *p, const float (&o)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+  } else {
+    *p = o[0];
+  }
+}
+
+// First crossing inside this thread's V bins, given the next chunk's first
+// bin (F, W); INT_MAX if none.
+template <int V>
+__device__ __forceinline__ int local_crossing(const float (&F)[V], const float (&W)[V], float nF,
+                                              float nW, int d0, int D) {
+  int cand = INT_MAX;
+#pragma unroll
+  for (int v = V - 1; v >= 0; --v) {
+    const float f1 = (v + 1 < V) ? F[(v + 1) % V] : nF;
+    const float w1 = (v + 1 < V) ? W[(v + 1) % V] : nW;
+    if (d0 + v + 1 < D && W[v] > 0.0f && w1 > 0.0f && F[v] > 0.0f && f1 <= 0.0f) cand = d0 + v;
+  }
+  return cand;
+}
+
+// Extraction across the workgroup: each thread holds V bins of one pixel;
+// the chunk's first bin is exchanged through LDS, the smallest crossing per
+// pixel is an LDS atomic minimum (order-free), and the owning thread
+// interpolates.  zf(d) returns z_d for the owning thread.
+template <int V, typename ZF>
+__device__ __forceinline__ void extract_block(const float (&F)[V], const float (&W)[V],
+                                              bool lane, bool active, uint32_t pix, uint32_t lp,
+                                              uint32_t chunk, uint32_t cpp, uint32_t next_off,
+                                              int d0, int D,
+                                              float *sF, float *sW, int *sBest,
+                                              float *out_depth, int32_t *out_bin, ZF zf) {
+  // lane: this thread maps to a chunk of one of the workgroup's pixels
+  // (threads past ppb * cpp idle but take part in the barriers).
+  const uint32_t t = threadIdx.x;
+  if (lane) {
+    sF[t] = F[0];
+    sW[t] = W[0];
+    if (chunk == 0) sBest[lp] = INT_MAX;
+  }
+  __syncthreads();
+  const bool has_next = lane && chunk + 1 < cpp;
+  const float nF = has_next ? sF[t + next_off] : 0.0f;
+  const float nW = has_next ? sW[t + next_off] : 0.0f;
+  if (active) {
+    const int cand = local_crossing<V>(F, W, nF, nW, d0, D);
+    if (cand != INT_MAX) atomicMin(&sBest[lp], cand);
+  }
+  __syncthreads();
+  if (active) {
+    const int best = sBest[lp];
+    if (best == INT_MAX) {
+      if (chunk == 0) {
+        out_depth[pix] = 0.0f;
+        out_bin[pix] = -1;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (best == d0 + v) {
+          const float f0 = F[v];
+          const float f1 = (v + 1 < V) ? F[(v + 1) % V] : nF;
+          const float za = zf(best), zb = zf(best + 1);
+          const float frac = f0 / (f0 - f1);
+          out_depth[pix] = za + (zb - za) * frac;
+          out_bin[pix] = best;
+        }
+      }
+    }
+  }
+  __syncthreads();  // LDS reused by the caller's next tile
+}
+
+// ---------------------------------------------------------------------------
+// fused integrate + extraction.  Workgroup = ppb whole pixels; thread = V
+// consecutive bins of one pixel (the volume is D-innermost, so a wavefront
+// reads and writes one contiguous span of F and W: fully coalesced).
+//
+// Per voxel and view the work is branch-free: the sample pixel of every
+// (view, bin) pair the thread owns is computed first, then all their view-
+// table records (8 bytes: depth, weight) are gathered at once, then they are
+// accumulated in view order.  The gathers of a thread are independent, so
+// their L2 latencies overlap.
+
+// The pixel of view k sampled by the point (X0, X1, Z) (homogeneous pixel
+// coordinates): (floor(X0 / Z), floor(X1 / Z)) with the quotient evaluated
+// as X * (1 / Z).  Returns false if Z <= 0 or the pixel is outside the
+// image; idx is then 0 (a valid address).
+template <bool kExact>
+__device__ __forceinline__ bool sample_pixel(float X0, float X1, float Z, uint32_t Ws,
+                                             uint32_t Hs, float fWs, float fHs, uint32_t &idx) {
+  bool ok;
+  if constexpr (!kExact) {
+    const float inv = recip_rn(Z);
+    const uint32_t i = (uint32_t)floor_i32(X0 * inv), j = (uint32_t)floor_i32(X1 * inv);
+    ok = (Z > kRecipLo) && i < Ws && j < Hs;
+    idx = ok ? j * Ws + i : 0u;
+    // 0 < Z <= 2^-100: the reciprocal is outside the fast range (rare)
+    if (__builtin_expect(__any(Z > 0.0f && !(Z > kRecipLo)), 0)) {
+      if (Z > 0.0f && !(Z > kRecipLo)) {
+        const float iv = 1.0f / Z;
+        const float u = X0 * iv, w = X1 * iv;
+        ok = u >= 0.0f && u < fWs && w >= 0.0f && w < fHs;
+        idx = ok ? (uint32_t)w * Ws + (uint32_t)u : 0u;
+      }
+    }
+  } else {
+    ok = false;
+    idx = 0u;
+    if (Z > 0.0f) {
+      const float iv = 1.0f / Z;
+      const float u = X0 * iv, w = X1 * iv;
+      ok = u >= 0.0f && u < fWs && w >= 0.0f && w < fHs;
+      idx = ok ? (uint32_t)w * Ws + (uint32_t)u : 0u;
+    }
+  }
+  return ok;
+}
+
+// One view's samples of the V voxels: geometry, gather, accumulate.
+template <int V, bool kExact>
+__device__ __forceinline__ void fuse_view(const IntegrateArgs &a, int k, float px, float py,
+                                          const float (&z)[V], const float (&tau)[V],
+                                          float (&S)[V], float (&Wo)[V]) {
+  const Proj &P = a.views[k];
+  float h0, h1, h2;
+  ray_of(P, px, py, h0, h1, h2);
+  const float2 *tab = a.table + (size_t)k * a.ns;
+  const float fWs = (float)a.Ws, fHs = (float)a.Hs;
+  float Z[V];
+  bool ok[V];
+  uint32_t idx[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float X0 = fmaf(z[v], h0, P.c[0]);
+    const float X1 = fmaf(z[v], h1, P.c[1]);
+    Z[v] = fmaf(z[v], h2, P.c[2]);
+    ok[v] = sample_pixel<kExact>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs, idx[v]);
+  }
+  float2 e[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) e[v] = tab[idx[v]];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float s = e[v].x - Z[v];  // -inf for a hole: dropped by the test
+    if (ok[v] && !(s < -tau[v])) {
+      const float c = fminf(s, tau[v]);
+      S[v] = fmaf(e[v].y, c, S[v]);
+      Wo[v] = Wo[v] + e[v].y;
+    }
+  }
+}
+
+// KC > 0: the view count is a compile-time constant and the view loop is
+// unrolled (every view's gathers issued before any is consumed); KC == 0:
+// runtime view count.
+template <int V, int KC, bool kExact>
+__device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, float py,
+                                            const float (&z)[V], const float (&tau)[V],
+                                            float (&S)[V], float (&Wo)[V]) {
+  if constexpr (KC > 0) {
+#pragma unroll
+    for (int k = 0; k < KC; ++k) fuse_view<V, kExact>(a, k, px, py, z, tau, S, Wo);
+  } else {
+    for (int k = 0; k < a.K; ++k) fuse_view<V, kExact>(a, k, px, py, z, tau, S, Wo);
+  }
+}
+
+// One workgroup tile (ppb pixels x D bins).  smem: 2 * blockDim floats +
+// ppb ints.  Shared by the plain launch and the batched persistent kernel.
+template <int V, int KC, bool kExact>
+__device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t tile, float *smem) {
+  float *sF = smem;
+  float *sW = smem + blockDim.x;
+  int *sBest = reinterpret_cast<int *>(smem + 2 * blockDim.x);
+
+  // thread -> (pixel lp, chunk of V bins): 2^pw_shift neighbouring pixels
+  // of a row interleave in each wavefront, so one gather instruction reads
+  // neighbouring source pixels at a few depths (few cache lines) while each
+  // pixel's chunks still form contiguous runs of the volume
+  const uint32_t t = threadIdx.x;
+  const uint32_t pw = t & ((1u << a.pw_shift) - 1u), rest = t >> a.pw_shift;
+  const uint32_t grp = fdiv(rest, a.cpp_div);
+  const uint32_t chunk = rest - grp * a.cpp;
+  const uint32_t lp = (grp << a.pw_shift) + pw;
+  const bool lane = lp < a.ppb;
+  const uint32_t pix = tile * a.ppb + lp;
+  const bool active = lane && pix < a.npix;
+  const int d0 = lane ? (int)chunk * V : 0;
+  const size_t base = (size_t)pix * a.D + d0;
+
+  // the carried volume streams from HBM: start its loads first
+  float Fp[V], Wp[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) Fp[v] = Wp[v] = 0.0f;
+  if (active && a.carry) {
+    loadv<V>(a.F_prev + base, Fp);
+    loadv<V>(a.W_prev + base, Wp);
+  }
+  float z[V], tau[V], S[V], Wo[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float2 b = a.bins[d0 + v];
+    z[v] = b.x;
+    tau[v] = b.y;
+    S[v] = 0.0f;
+    Wo[v] = 0.0f;
+  }
+  float Fn[V], Wn[V];
+  if (active) {
+    const uint32_t y = fdiv(pix, a.wt_div);
+    const uint32_t x = pix - y * a.wt_div.d;
+    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo);
+    const float m = a.mask ? fmaxf(1.0f - a.mask[pix], 0.0f) : 1.0f;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float wp = a.carry ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
+      const float wn = wp + Wo[v];
+      Fn[v] = (wn > 0.0f) ? fmaf(wp, Fp[v], S[v]) / wn : 0.0f;
+      Wn[v] = wn;
+    }
+    storev<V>(a.F + base, Fn);
+    storev<V>(a.W + base, Wn);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) Fn[v] = Wn[v] = 0.0f;
+  }
+  if (a.out_depth) {
+    const float2 *bins = a.bins;
+    extract_block<V>(Fn, Wn, lane, active, pix, lp, chunk, a.cpp, 1u << a.pw_shift, d0, a.D, sF,
+                     sW, sBest, a.out_depth, a.out_bin, [bins](int d) { return bins[d].x; });
+  }
+}
+
+}  // namespace gg

@@ -280,3 +280,95 @@ def timing_read(name=None):
     L.check(L.lib().gg_timing_read(None if name is None else name.encode(), C.byref(ms),
                                    C.byref(n)))
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# batched path
+
+
+class BatchPlan:
+    """Many target views fused by one graph launch (see include/ggeom.h).
+
+    ``items``: dicts with keys src, depth, tgt, tsdf and optionally rgb,
+    splat, mask, F_prev, W_prev, F, W (allocated if absent), extract (True).
+    Outputs live in each item dict after creation: F, W, depth_out, bin_out
+    and, with rgb, splat = dict(win_idx, depth, rgb, alpha, tape).  The plan
+    binds these buffers; write new inputs into the same tensors between
+    launches."""
+
+    def __init__(self, items, volume_threads=0, blocks_per_cu=0):
+        self.items = items
+        self._keep = []
+        arr = (L.GGBatchItem * len(items))()
+        for i, it in enumerate(items):
+            depth = it["depth"]
+            dev = _device(depth)
+            sa, tg, tp = cameras(it["src"]), camera(it["tgt"]), tsdf_params(it["tsdf"])
+            K = len(sa)
+            sw, sh = _wh(sa)
+            th, tw, D = tg.height, tg.width, tp.num_bins
+            _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+            vol = (th, tw, D)
+            if it.get("F") is None:
+                it["F"] = torch.empty(vol, dtype=torch.float32, device=dev)
+            if it.get("W") is None:
+                it["W"] = torch.empty(vol, dtype=torch.float32, device=dev)
+            _need(it["F"], torch.float32, vol, "F", dev)
+            _need(it["W"], torch.float32, vol, "W", dev)
+            b = arr[i]
+            b.src = sa
+            b.K = K
+            b.depth = depth.data_ptr()
+            b.tgt = tg
+            b.tsdf = tp
+            for key in ("F_prev", "W_prev", "mask"):
+                if it.get(key) is not None:
+                    _need(it[key], torch.float32, vol if key != "mask" else (th, tw), key, dev)
+            b.temporal_mask = _ptr(it.get("mask"))
+            b.F_prev = _ptr(it.get("F_prev"))
+            b.W_prev = _ptr(it.get("W_prev"))
+            b.F = it["F"].data_ptr()
+            b.W = it["W"].data_ptr()
+            if it.get("extract", True):
+                it["depth_out"] = torch.empty((th, tw), dtype=torch.float32, device=dev)
+                it["bin_out"] = torch.empty((th, tw), dtype=torch.int32, device=dev)
+                b.out_depth = it["depth_out"].data_ptr()
+                b.out_bin = it["bin_out"].data_ptr()
+            if it.get("rgb") is not None:
+                _need(it["rgb"], torch.uint8, (K, sh, sw, 3), "rgb", dev)
+                b.rgb = it["rgb"].data_ptr()
+                b.splat = splat_params(it["splat"])
+                o = dict(win_idx=torch.empty((K, th, tw), dtype=torch.int32, device=dev),
+                         depth=torch.empty((K, th, tw), dtype=torch.float32, device=dev),
+                         rgb=torch.empty((K, 3, th, tw), dtype=torch.float32, device=dev),
+                         alpha=torch.empty((K, th, tw), dtype=torch.float32, device=dev),
+                         tape=torch.empty((K, 3, th, tw), dtype=torch.float32, device=dev))
+                it["splat_out"] = o
+                b.win_idx = o["win_idx"].data_ptr()
+                b.sp_depth = o["depth"].data_ptr()
+                b.sp_rgb = o["rgb"].data_ptr()
+                b.sp_alpha = o["alpha"].data_ptr()
+                b.sp_tape = o["tape"].data_ptr()
+            self._keep.append(sa)
+        self._arr = arr
+        tune = L.GGBatchTuning(int(volume_threads), int(blocks_per_cu))
+        h = C.c_void_p()
+        L.check(L.lib().gg_batch_create(arr, len(items), C.byref(tune), C.byref(h)))
+        self._h = h
+        self.device_bytes = int(L.lib().gg_batch_device_bytes(h))
+
+    def launch(self, stream=None):
+        dev = self.items[0]["depth"].device
+        L.check(L.lib().gg_batch_launch(self._h, _stream(dev, stream)))
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize()
+            L.lib().gg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -233,14 +233,14 @@ def test_volume_tile_shape_does_not_change_results():
     depth, _ = to_dev(c)
     base = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
     try:
-        for ppb in (1, 3, 8, 40):
-            gg._lib.check(gg._lib.lib().gg_set_volume_tile(ppb))
+        for ppb in ((1, 1), (3, 1), (8, 1), (8, 8), (40, 8), (32, 32)):
+            gg._lib.check(gg._lib.lib().gg_set_volume_tile(*ppb))
             v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
             torch.cuda.synchronize()
             for a, b in zip(v, base):
                 assert torch.equal(a.view(torch.int32), b.view(torch.int32)), ppb
     finally:
-        gg._lib.lib().gg_set_volume_tile(0)
+        gg._lib.lib().gg_set_volume_tile(0, 0)
 
 
 # ---------------------------------------------------------------------------
