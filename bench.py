@@ -236,6 +236,9 @@ def main():
         return gg.tsdf_integrate(src, depth[f], tgt, tp, F_prev=F if carry else None,
                                  W_prev=Wv if carry else None, F=F, W=Wv, ws=ws_t)
 
+    # launch shape of the fusion for this class (autotuned, results unchanged)
+    from paper_2505_18932_amd import autotune
+    tile, tile_times = autotune.tune_plain(src, depth[0], tgt, tp, use_cache=False)
     step(0, carry=False)
     for i in range(1, args.warmup):
         step(i)
@@ -282,7 +285,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "K": K, "width": Wd, "height": H, "bins": D,
-                   "frames_resident": nf},
+                   "frames_resident": nf, "fusion_tile": list(tile)},
         "roofline": roof,
         "kernel_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in kt.items()},
     }

@@ -275,8 +275,8 @@ int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, flo
  * whole target pixels per workgroup (each thread holding up to 4 consecutive
  * bins of one pixel) and the number of neighbouring pixels interleaved in a
  * wavefront row of tsdf_integrate (a power of two dividing the former; the
- * largest such <= pixels_per_row is used).  0 restores the defaults (256
- * threads' worth of pixels; up to 8 per row).  Results do not depend on the
+ * largest such <= pixels_per_row is used).  0 restores the defaults (512
+ * threads' worth of pixels; up to 16 per row).  Results do not depend on the
  * choice; it exists for the autotuner.  Process-wide. */
 int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
 

@@ -267,13 +267,13 @@ static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what) 
   s.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
   s.cpp = (uint32_t)(D / s.V);
   if (s.cpp > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
-  uint32_t ppb = g_ppb_override > 0 ? (uint32_t)g_ppb_override : 256u / s.cpp;
+  uint32_t ppb = g_ppb_override > 0 ? (uint32_t)g_ppb_override : 512u / s.cpp;
   if (ppb < 1) ppb = 1;
   while (ppb > 1 && ppb * s.cpp > 1024) --ppb;
   s.ppb = ppb;
   s.threads = ppb * s.cpp;
   s.nblocks = (npix + ppb - 1) / ppb;
-  s.pw_shift = pick_pw_shift(ppb, g_pw_override >= 0 ? g_pw_override : 8);
+  s.pw_shift = pick_pw_shift(ppb, g_pw_override >= 0 ? g_pw_override : 16);
   return GG_OK;
 }
 
@@ -786,7 +786,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
       integ[g].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
   }
   const size_t o_counts = off;
-  off += up256(4 * (count_words ? count_words : 1));
+  off += up256(4 * (count_words + kBatchCounters));
   auto put = [&](size_t bytes) { const size_t o = off; off += up256(bytes ? bytes : 1); return o; };
   const size_t o_conf = put(sizeof(WorkItem) * conf.size()), o_bin = put(sizeof(WorkItem) * bin.size()),
                o_raster = put(sizeof(WorkItem) * raster.size());
@@ -847,7 +847,8 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   P.d_splat_items = (uint32_t *)(dv + o_sitems);
   P.n_splat_items = (uint32_t)splat_items.size();
   P.zero_ptr = (uint32_t *)(dv + o_counts);
-  P.zero_words = count_words;
+  P.zero_words = count_words + kBatchCounters;
+  P.d_ctr = P.zero_ptr + count_words;
   int rc = GG_OK;
   auto cp = [&](size_t o, const void *src, size_t bytes) {
     if (rc == GG_OK && bytes) rc = check_hip(hipMemcpy(dv + o, src, bytes, hipMemcpyHostToDevice), N);

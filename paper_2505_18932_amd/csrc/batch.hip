@@ -32,26 +32,28 @@ __global__ void batch_bins_kernel(const BatchItem *__restrict__ items) {
     const float du = (un - uf) / (float)(it.D - 1);
     const float u = un - (float)d * du;
     const float z = 1.0f / u;
-    it.bins[d] = make_float2(z, it.trunc_in_bins ? (it.trunc * du) * (z * z) : it.trunc);
+    gstore2(it.bins + d, make_float2(z, it.trunc_in_bins ? (it.trunc * du) * (z * z) : it.trunc));
   }
 }
 
-// The contiguous range of work this workgroup owns.
-__device__ __forceinline__ void my_range(uint32_t n, uint32_t &b, uint32_t &e) {
-  const uint32_t g = gridDim.x;
-  const uint32_t per = (n + g - 1) / g;
-  const uint32_t lb = xcd_tile(blockIdx.x, g);
-  b = min(lb * per, n);
-  e = min(b + per, n);
+// Dynamic work distribution: each workgroup takes the next entry of the
+// phase's list from a counter the graph zeroes first.  Entries differ in cost
+// by orders of magnitude (items differ in size, view count and bins), so a
+// static split leaves long tails.  Which workgroup runs an entry never
+// changes its result.
+__device__ __forceinline__ uint32_t next_work(uint32_t *ctr, uint32_t *slot) {
+  __syncthreads();  // the previous entry is done with the slot
+  if (threadIdx.x == 0) *slot = atomicAdd(ctr, 1u);
+  __syncthreads();
+  return *slot;
 }
 
 __global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__restrict__ items,
                                                          const WorkItem *__restrict__ work,
-                                                         uint32_t n) {
+                                                         uint32_t n, uint32_t *ctr) {
   __shared__ float tile[kConfTileFloats];
-  uint32_t b, e;
-  my_range(n, b, e);
-  for (uint32_t w = b; w < e; ++w) {
+  __shared__ uint32_t slot;
+  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
     const WorkItem wi = work[w];
     conf_tile(items[wi.item].conf, wi.k, wi.x, wi.y, tile);
   }
@@ -60,10 +62,9 @@ __global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__rest
 template <bool kFill>
 __global__ __launch_bounds__(256) void batch_bin_kernel(const BatchItem *__restrict__ items,
                                                         const WorkItem *__restrict__ work,
-                                                        uint32_t n) {
-  uint32_t b, e;
-  my_range(n, b, e);
-  for (uint32_t w = b; w < e; ++w) {
+                                                        uint32_t n, uint32_t *ctr) {
+  __shared__ uint32_t slot;
+  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
     const WorkItem wi = work[w];
     splat_bin_block<kFill>(items[wi.item].splat, wi.k, work_tile(wi));
   }
@@ -78,11 +79,10 @@ __global__ __launch_bounds__(1024) void batch_scan_kernel(const BatchItem *__res
 
 __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__restrict__ items,
                                                            const WorkItem *__restrict__ work,
-                                                           uint32_t n) {
+                                                           uint32_t n, uint32_t *ctr) {
   __shared__ RasterLds lds;
-  uint32_t b, e;
-  my_range(n, b, e);
-  for (uint32_t w = b; w < e; ++w) {
+  __shared__ uint32_t slot;
+  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
     const WorkItem wi = work[w];
     raster_tile(items[wi.item].splat, wi.k, work_tile(wi), lds);
   }
@@ -110,11 +110,10 @@ __device__ __forceinline__ void batch_integrate_one(const IntegrateArgs &a, uint
 template <int V>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
-                                                               uint32_t n) {
+                                                               uint32_t n, uint32_t *ctr) {
   extern __shared__ float smem[];
-  uint32_t b, e;
-  my_range(n, b, e);
-  for (uint32_t w = b; w < e; ++w) {
+  __shared__ uint32_t slot;
+  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
     const WorkItem wi = work[w];
     batch_integrate_one<V>(items[wi.item].integ, work_tile(wi), smem);
   }
@@ -130,22 +129,21 @@ static int persistent_grid(uint32_t n, int per_cu, int cus) {
 
 int batch_record(BatchPlan &P, hipStream_t s) {
   const int cus = P.cus, per = P.blocks_per_cu;
-  if (P.zero_words) {
-    hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
-  }
+  // tile counts of every item and the phases' work counters
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
   hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
   if (P.n_conf)
     hipLaunchKernelGGL(batch_conf_kernel, dim3(persistent_grid(P.n_conf, per, cus)), dim3(256), 0,
-                       s, P.d_items, P.d_conf, P.n_conf);
+                       s, P.d_items, P.d_conf, P.n_conf, P.d_ctr + 0);
   if (P.n_bin) {
     hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(persistent_grid(P.n_bin, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin);
+                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin, P.d_ctr + 1);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
                        P.d_splat_items);
     hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(persistent_grid(P.n_bin, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin);
+                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin, P.d_ctr + 2);
     hipLaunchKernelGGL(batch_raster_kernel, dim3(persistent_grid(P.n_raster, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_raster, P.n_raster);
+                       dim3(256), 0, s, P.d_items, P.d_raster, P.n_raster, P.d_ctr + 3);
   }
   for (int g = 0; g < 3; ++g) {
     const uint32_t n = P.n_integ[g];
@@ -156,13 +154,13 @@ int batch_record(BatchPlan &P, hipStream_t s) {
     const dim3 grid(persistent_grid(n, per, cus));
     if (V == 4)
       hipLaunchKernelGGL(batch_integrate_kernel<4>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n);
+                         P.d_integ[g], n, P.d_ctr + 4 + g);
     else if (V == 2)
       hipLaunchKernelGGL(batch_integrate_kernel<2>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n);
+                         P.d_integ[g], n, P.d_ctr + 4 + g);
     else
       hipLaunchKernelGGL(batch_integrate_kernel<1>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n);
+                         P.d_integ[g], n, P.d_ctr + 4 + g);
   }
   return check_hip(hipGetLastError(), "batch phases");
 }

@@ -7,6 +7,7 @@
 namespace gg {
 
 constexpr int kConfTileFloats = kConfLH * kConfLW;
+constexpr int kBatchCounters = 8;
 
 // Everything one item's phases need, in device memory (read with scalar
 // loads: the descriptor address is uniform per work entry).
@@ -44,8 +45,9 @@ struct BatchPlan {
   uint32_t n_conf = 0, n_bin = 0, n_raster = 0, n_integ[3] = {};
   uint32_t *d_splat_items = nullptr;
   uint32_t n_splat_items = 0;
-  uint32_t *zero_ptr = nullptr;
+  uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
   size_t zero_words = 0;
+  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters (zeroed per launch)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

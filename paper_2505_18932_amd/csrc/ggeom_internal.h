@@ -50,6 +50,34 @@ void relproj(const gg_camera &a, const gg_camera &b, Proj &out);
 
 __device__ __forceinline__ bool depth_ok(float d) { return d > 0.0f && d < INFINITY; }
 
+// Global-memory view of a pointer.  Pointers read from memory (the batched
+// path's device-resident descriptors) carry no address space, and accesses
+// through them would compile to flat instead of global instructions.
+#define GG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GG_GLOBAL T *gmem(T *p) {
+  return (GG_GLOBAL T *)p;
+}
+
+// Vector loads and stores through global-memory views (HIP's float2/float4
+// classes cannot bind to address-space-qualified storage; these builtin
+// vectors can).
+typedef float gg_v2f __attribute__((ext_vector_type(2)));
+typedef float gg_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float2 gload2(const float2 *p) {
+  const gg_v2f v = *(const GG_GLOBAL gg_v2f *)p;
+  return make_float2(v.x, v.y);
+}
+
+__device__ __forceinline__ void gstore2(float2 *p, float2 v) {
+  *(GG_GLOBAL gg_v2f *)p = (gg_v2f){v.x, v.y};
+}
+
+__device__ __forceinline__ uint32_t gatomic_add(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Range in which recip_rn() is the correctly rounded reciprocal.
 constexpr float kRecipLo = 0x1p-100f, kRecipHi = 0x1p100f;
 

@@ -31,9 +31,12 @@ __device__ __forceinline__ SplatGeom splat_geom(const SplatView &V, float D, uin
   const float sig = V.sscale * (D * inv);
   g.s2 = sig * sig;
   g.R2 = fminf(2.0f * g.s2, a.rmax2);
-  const float r = sqrtf(g.R2);
-  float ax0 = floorf(g.x - 0.5f - r) - 1.0f, ax1 = floorf(g.x - 0.5f + r) + 1.0f;
-  float by0 = floorf(g.y - 0.5f - r) - 1.0f, by1 = floorf(g.y - 0.5f + r) + 1.0f;
+  // candidate window: covered pixels have |a + 0.5 - x| <= r (1 + 2^-21)
+  // (the rounded d2 is at least the rounded dx^2); the float bounds below
+  // carry at most 3 ulps of |x| + r < 2^-9 of error, inside the margin
+  const float r = sqrtf(g.R2) + 0x1p-6f;
+  float ax0 = ceilf(g.x - 0.5f - r), ax1 = floorf(g.x - 0.5f + r);
+  float by0 = ceilf(g.y - 0.5f - r), by1 = floorf(g.y - 0.5f + r);
   ax0 = fmaxf(ax0, 0.0f);
   by0 = fmaxf(by0, 0.0f);
   ax1 = fminf(ax1, (float)(a.Wt - 1));
@@ -65,7 +68,7 @@ __device__ __forceinline__ uint32_t aggregated_slot(uint32_t *counters, uint32_t
     const bool mine = has && key == lkey;
     const unsigned long long grp = __ballot(mine);
     uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counters[lkey], (uint32_t)__popcll(grp));
+    if (lane == leader) base = gatomic_add(&counters[lkey], (uint32_t)__popcll(grp));
     base = __shfl(base, leader);
     if (mine) slot = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
     pending &= ~grp;
@@ -81,7 +84,7 @@ __device__ __forceinline__ void splat_bin_block(const SplatArgs &a, int k, uint3
   int tx0 = 0, ty0 = 0, nx = 0, n = 0;
   if (q < a.ns) {
     const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(a.views[k], a.depth[(size_t)k * a.ns + q], i, j, a);
+    const SplatGeom g = splat_geom(a.views[k], gmem(a.depth)[(size_t)k * a.ns + q], i, j, a);
     if (g.ok) {
       tx0 = g.a0 / kTile;
       ty0 = g.b0 / kTile;
@@ -96,8 +99,8 @@ __device__ __forceinline__ void splat_bin_block(const SplatArgs &a, int k, uint3
     const uint32_t tile = has ? (uint32_t)((ty0 + s / nx) * a.ntx + (tx0 + s % nx)) : 0u;
     const uint32_t slot = aggregated_slot(cnt, tile, has);
     if (kFill && has) {
-      const uint32_t pos = a.tile_offset[(size_t)k * a.ntiles + tile] + slot;
-      if (pos < a.list_cap) a.list[pos] = q;
+      const uint32_t pos = gmem(a.tile_offset)[(size_t)k * a.ntiles + tile] + slot;
+      if (pos < a.list_cap) gmem(a.list)[pos] = q;
     }
   }
 }
@@ -110,7 +113,7 @@ __device__ __forceinline__ void tile_scan_block(const uint32_t *cnt, uint32_t *o
   const uint32_t per = (n + 1023u) / 1024u;
   const uint32_t b = t * per, e = min(b + per, n);
   uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += cnt[i];
+  for (uint32_t i = b; i < e; ++i) sum += gmem(cnt)[i];
   s[t] = sum;
   __syncthreads();
   for (uint32_t o = 1; o < 1024; o <<= 1) {
@@ -121,11 +124,11 @@ __device__ __forceinline__ void tile_scan_block(const uint32_t *cnt, uint32_t *o
   }
   uint32_t run = s[t] - sum;
   for (uint32_t i = b; i < e; ++i) {
-    off[i] = run;
-    run += cnt[i];
-    cursor[i] = 0u;
+    gmem(off)[i] = run;
+    run += gmem(cnt)[i];
+    gmem(cursor)[i] = 0u;
   }
-  if (t == 1023) off[n] = s[1023];
+  if (t == 1023) gmem(off)[n] = s[1023];
   __syncthreads();
 }
 
@@ -149,28 +152,30 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
   const size_t p = (size_t)py * a.Wt + px;
   const size_t o = (size_t)k * a.nt + p;
   const unsigned long long wk = zkey[t];
-  float* rgb = a.out_rgb + (size_t)k * 3 * a.nt;
+  GG_GLOBAL float *rgb = gmem(a.out_rgb + (size_t)k * 3 * a.nt);
+  GG_GLOBAL int32_t *win = gmem(a.win_idx);
+  GG_GLOBAL float *dep = gmem(a.out_depth), *alp = gmem(a.out_alpha);
   if (wk == ~0ull) {
-    a.win_idx[o] = -1;
-    a.out_depth[o] = 0.0f;
-    a.out_alpha[o] = 0.0f;
+    win[o] = -1;
+    dep[o] = 0.0f;
+    alp[o] = 0.0f;
     rgb[p] = rgb[a.nt + p] = rgb[2 * a.nt + p] = 0.0f;
     if (a.out_tape) {
-      float *tp = a.out_tape + (size_t)k * 3 * a.nt;
+      GG_GLOBAL float *tp = gmem(a.out_tape + (size_t)k * 3 * a.nt);
       tp[p] = tp[a.nt + p] = tp[2 * a.nt + p] = 0.0f;
     }
     return;
   }
-  a.win_idx[o] = (int32_t)(uint32_t)(wk & 0xffffffffull);
-  a.out_depth[o] = __uint_as_float((uint32_t)(wk >> 32));
+  win[o] = (int32_t)(uint32_t)(wk & 0xffffffffull);
+  dep[o] = __uint_as_float((uint32_t)(wk >> 32));
   const double sg = (double)(long long)sG[t];
   rgb[p] = (float)((double)(long long)sR[t] / sg);
   rgb[a.nt + p] = (float)((double)(long long)sGr[t] / sg);
   rgb[2 * a.nt + p] = (float)((double)(long long)sB[t] / sg);
   const double L = (double)(long long)sL[t] / kFixL;
-  a.out_alpha[o] = sOnes[t] ? 1.0f : (float)(1.0 - exp(L));
+  alp[o] = sOnes[t] ? 1.0f : (float)(1.0 - exp(L));
   if (a.out_tape) {
-    float *tp = a.out_tape + (size_t)k * 3 * a.nt;
+    GG_GLOBAL float *tp = gmem(a.out_tape + (size_t)k * 3 * a.nt);
     tp[p] = (float)(sg / kFixG);
     tp[a.nt + p] = (float)L;
     tp[2 * a.nt + p] = (float)sOnes[t];
@@ -192,16 +197,16 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
   sOnes[t] = 0u;
   __syncthreads();
   const size_t ti = (size_t)k * a.ntiles + tile;
-  const uint32_t beg = a.tile_offset[ti], end = min(a.tile_offset[ti + 1], a.list_cap);
+  const uint32_t beg = gmem(a.tile_offset)[ti], end = min(gmem(a.tile_offset)[ti + 1], a.list_cap);
   const SplatView &V = a.views[k];
   const float *dk = a.depth + (size_t)k * a.ns;
   const uint8_t *ck = a.rgb + (size_t)k * a.ns * 3;
   // z-test
   for (uint32_t e = beg + t; e < end; e += blockDim.x) {
-    const uint32_t q = a.list[e];
+    const uint32_t q = gmem(a.list)[e];
     if (q >= a.ns) continue;
     const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(V, dk[q], i, j, a);
+    const SplatGeom g = splat_geom(V, gmem(dk)[q], i, j, a);
     if (!g.ok) continue;
     const unsigned long long key = ((unsigned long long)__float_as_uint(g.z) << 32) | q;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
@@ -213,10 +218,10 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
   __syncthreads();
   // band blend
   for (uint32_t e = beg + t; e < end; e += blockDim.x) {
-    const uint32_t q = a.list[e];
+    const uint32_t q = gmem(a.list)[e];
     if (q >= a.ns) continue;
     const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(V, dk[q], i, j, a);
+    const SplatGeom g = splat_geom(V, gmem(dk)[q], i, j, a);
     if (!g.ok) continue;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
     const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);
@@ -228,9 +233,9 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
         const float zw = __uint_as_float((uint32_t)(zkey[lp] >> 32));
         if (!(g.z <= zw * a.band)) continue;
         const float G = expf((-0.5f * d2) / g.s2);
-        const float c0 = (float)ck[3 * (size_t)q + 0] / 255.0f;
-        const float c1 = (float)ck[3 * (size_t)q + 1] / 255.0f;
-        const float c2 = (float)ck[3 * (size_t)q + 2] / 255.0f;
+        const float c0 = (float)gmem(ck)[3 * (size_t)q + 0] / 255.0f;
+        const float c1 = (float)gmem(ck)[3 * (size_t)q + 1] / 255.0f;
+        const float c2 = (float)gmem(ck)[3 * (size_t)q + 2] / 255.0f;
         atomicAdd(&sG[lp], (unsigned long long)llrint((double)G * kFixG));
         atomicAdd(&sR[lp], (unsigned long long)llrint((double)(G * c0) * kFixG));
         atomicAdd(&sGr[lp], (unsigned long long)llrint((double)(G * c1) * kFixG));

@@ -58,7 +58,7 @@ __device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0,
     const int ly = e / tw, lx = e - ly * tw;
     const int gi = i0 - r + lx, gj = j0 - r + ly;
     float v = 0.0f;
-    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = dk[(size_t)gj * a.Ws + gi];
+    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = gmem(dk)[(size_t)gj * a.Ws + gi];
     // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
     // relative to the fixed centre origin
     tile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
       const float om = (nu == 0.0f) ? 1.0f : fminf(a.scale / sqrtf(nu / a.n2), 1.0f);
       rec = make_float2(dq, om);
     }
-    a.table[(size_t)k * a.Ws * a.Hs + (size_t)j * a.Ws + i] = rec;
+    gstore2(a.table + (size_t)k * a.Ws * a.Hs + (size_t)j * a.Ws + i, rec);
   }
   __syncthreads();  // the tile may be restaged by the caller's next iteration
 }
@@ -93,24 +93,24 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
 template <int V>
 __device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
   if constexpr (V == 4) {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
+    const gg_v4f v = *(const GG_GLOBAL gg_v4f *)p;
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   } else if constexpr (V == 2) {
-    const float2 v = *reinterpret_cast<const float2 *>(p);
+    const gg_v2f v = *(const GG_GLOBAL gg_v2f *)p;
     o[0] = v.x; o[1] = v.y;
   } else {
-    o[0] = *p;
+    o[0] = *gmem(p);
   }
 }
 
 template <int V>
 __device__ __forceinline__ void storev(float *p, const float (&o)[V]) {
   if constexpr (V == 4) {
-    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    *(GG_GLOBAL gg_v4f *)p = (gg_v4f){o[0], o[1], o[2], o[3]};
   } else if constexpr (V == 2) {
-    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+    *(GG_GLOBAL gg_v2f *)p = (gg_v2f){o[0], o[1]};
   } else {
-    *p = o[0];
+    *gmem(p) = o[0];
   }
 }
 
@@ -161,8 +161,8 @@ __device__ __forceinline__ void extract_block(const float (&F)[V], const float (
     const int best = sBest[lp];
     if (best == INT_MAX) {
       if (chunk == 0) {
-        out_depth[pix] = 0.0f;
-        out_bin[pix] = -1;
+        gmem(out_depth)[pix] = 0.0f;
+        gmem(out_bin)[pix] = -1;
       }
     } else {
 #pragma unroll
@@ -172,8 +172,8 @@ __device__ __forceinline__ void extract_block(const float (&F)[V], const float (
           const float f1 = (v + 1 < V) ? F[(v + 1) % V] : nF;
           const float za = zf(best), zb = zf(best + 1);
           const float frac = f0 / (f0 - f1);
-          out_depth[pix] = za + (zb - za) * frac;
-          out_bin[pix] = best;
+          gmem(out_depth)[pix] = za + (zb - za) * frac;
+          gmem(out_bin)[pix] = best;
         }
       }
     }
@@ -227,18 +227,17 @@ __device__ __forceinline__ bool sample_pixel(float X0, float X1, float Z, uint32
   return ok;
 }
 
-// One view's samples of the V voxels: geometry, gather, accumulate.
+// One view's samples of the V voxels: geometry and gathers (issued, not
+// consumed).
 template <int V, bool kExact>
-__device__ __forceinline__ void fuse_view(const IntegrateArgs &a, int k, float px, float py,
-                                          const float (&z)[V], const float (&tau)[V],
-                                          float (&S)[V], float (&Wo)[V]) {
+__device__ __forceinline__ void view_samples(const IntegrateArgs &a, int k, float px, float py,
+                                             const float (&z)[V], float (&Z)[V], bool (&ok)[V],
+                                             float2 (&e)[V]) {
   const Proj &P = a.views[k];
   float h0, h1, h2;
   ray_of(P, px, py, h0, h1, h2);
   const float2 *tab = a.table + (size_t)k * a.ns;
   const float fWs = (float)a.Ws, fHs = (float)a.Hs;
-  float Z[V];
-  bool ok[V];
   uint32_t idx[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -247,9 +246,15 @@ __device__ __forceinline__ void fuse_view(const IntegrateArgs &a, int k, float p
     Z[v] = fmaf(z[v], h2, P.c[2]);
     ok[v] = sample_pixel<kExact>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs, idx[v]);
   }
-  float2 e[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) e[v] = tab[idx[v]];
+  for (int v = 0; v < V; ++v) e[v] = gload2(tab + idx[v]);
+}
+
+// Accumulate one view's samples: s = D_k - z_k, occlusion cut, clamp.
+template <int V>
+__device__ __forceinline__ void view_accumulate(const float (&Z)[V], const bool (&ok)[V],
+                                                const float2 (&e)[V], const float (&tau)[V],
+                                                float (&S)[V], float (&Wo)[V]) {
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const float s = e[v].x - Z[v];  // -inf for a hole: dropped by the test
@@ -261,23 +266,52 @@ __device__ __forceinline__ void fuse_view(const IntegrateArgs &a, int k, float p
   }
 }
 
-// KC > 0: the view count is a compile-time constant and the view loop is
-// unrolled (every view's gathers issued before any is consumed); KC == 0:
-// runtime view count.
-template <int V, int KC, bool kExact>
+// G views k0 .. k0+G-1: every gather of the group is issued, then
+// after_issue() (the caller's own loads, so that in-order load completion
+// lets the gathers be consumed while those are still in flight), then the
+// samples are accumulated in view order.
+template <int V, int G, bool kExact, typename AfterIssue>
+__device__ __forceinline__ void fuse_group(const IntegrateArgs &a, int k0, float px, float py,
+                                           const float (&z)[V], const float (&tau)[V],
+                                           float (&S)[V], float (&Wo)[V],
+                                           AfterIssue &&after_issue) {
+  float Z[G][V];
+  bool ok[G][V];
+  float2 e[G][V];
+#pragma unroll
+  for (int g = 0; g < G; ++g) view_samples<V, kExact>(a, k0 + g, px, py, z, Z[g], ok[g], e[g]);
+  after_issue();
+#pragma unroll
+  for (int g = 0; g < G; ++g) view_accumulate<V>(Z[g], ok[g], e[g], tau, S, Wo);
+}
+
+// Views per group for a compile-time view count (at most 4 in flight).
+template <int KC>
+constexpr int view_group() {
+  return KC <= 4 ? KC : (KC % 4 == 0 ? 4 : (KC % 3 == 0 ? 3 : (KC % 2 == 0 ? 2 : 1)));
+}
+
+// KC > 0: the view count is a compile-time constant; views are processed in
+// unrolled groups and the caller's loads are issued after the first group's
+// gathers.  KC == 0: runtime view count, one view at a time, the caller's
+// loads issued first.
+template <int V, int KC, bool kExact, typename AfterIssue>
 __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, float py,
                                             const float (&z)[V], const float (&tau)[V],
-                                            float (&S)[V], float (&Wo)[V]) {
+                                            float (&S)[V], float (&Wo)[V],
+                                            AfterIssue &&after_issue) {
   if constexpr (KC > 0) {
+    constexpr int G = view_group<KC>();
+    fuse_group<V, G, kExact>(a, 0, px, py, z, tau, S, Wo, after_issue);
 #pragma unroll
-    for (int k = 0; k < KC; ++k) fuse_view<V, kExact>(a, k, px, py, z, tau, S, Wo);
+    for (int k0 = G; k0 < KC; k0 += G)
+      fuse_group<V, G, kExact>(a, k0, px, py, z, tau, S, Wo, [] {});
   } else {
-    for (int k = 0; k < a.K; ++k) fuse_view<V, kExact>(a, k, px, py, z, tau, S, Wo);
+    after_issue();
+    for (int k = 0; k < a.K; ++k) fuse_group<V, 1, kExact>(a, k, px, py, z, tau, S, Wo, [] {});
   }
 }
 
-// One workgroup tile (ppb pixels x D bins).  smem: 2 * blockDim floats +
-// ppb ints.  Shared by the plain launch and the batched persistent kernel.
 template <int V, int KC, bool kExact>
 __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t tile, float *smem) {
   float *sF = smem;
@@ -299,29 +333,35 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   const int d0 = lane ? (int)chunk * V : 0;
   const size_t base = (size_t)pix * a.D + d0;
 
-  // the carried volume streams from HBM: start its loads first
-  float Fp[V], Wp[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) Fp[v] = Wp[v] = 0.0f;
-  if (active && a.carry) {
-    loadv<V>(a.F_prev + base, Fp);
-    loadv<V>(a.W_prev + base, Wp);
-  }
   float z[V], tau[V], S[V], Wo[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const float2 b = a.bins[d0 + v];
+    const float2 b = gload2(a.bins + d0 + v);
     z[v] = b.x;
     tau[v] = b.y;
     S[v] = 0.0f;
     Wo[v] = 0.0f;
   }
+  // the carried volume streams from HBM; its loads are issued after the
+  // first views' gathers (see fuse_voxels)
+  float Fp[V], Wp[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) Fp[v] = Wp[v] = 0.0f;
+  const bool carry = active && a.carry;
+  float mraw = 0.0f;
+  auto load_volume = [&] {
+    if (carry) {
+      loadv<V>(a.F_prev + base, Fp);
+      loadv<V>(a.W_prev + base, Wp);
+    }
+    if (active && a.mask) mraw = gmem(a.mask)[pix];
+  };
   float Fn[V], Wn[V];
   if (active) {
     const uint32_t y = fdiv(pix, a.wt_div);
     const uint32_t x = pix - y * a.wt_div.d;
-    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo);
-    const float m = a.mask ? fmaxf(1.0f - a.mask[pix], 0.0f) : 1.0f;
+    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
+    const float m = a.mask ? fmaxf(1.0f - mraw, 0.0f) : 1.0f;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const float wp = a.carry ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
@@ -338,7 +378,8 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   if (a.out_depth) {
     const float2 *bins = a.bins;
     extract_block<V>(Fn, Wn, lane, active, pix, lp, chunk, a.cpp, 1u << a.pw_shift, d0, a.D, sF,
-                     sW, sBest, a.out_depth, a.out_bin, [bins](int d) { return bins[d].x; });
+                     sW, sBest, a.out_depth, a.out_bin,
+                     [bins](int d) { return gload2(bins + d).x; });
   }
 }
 
