@@ -50,7 +50,7 @@ def make_frames(n, procs):
 
 def kernel_sha():
     h = hashlib.sha256()
-    for name in ("tsdf.hip", "ggeom_internal.h"):
+    for name in ("tsdf.hip", "tsdf_device.h", "ggeom_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2505_18932_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -268,7 +268,7 @@ def main():
     achieved = alg / (int_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
-            "kernel": "integrate_kernel<4>", "kernel_ms": round(int_ms, 4),
+            "kernel": "integrate_kernel<V=%d, K=%d>" % (tile[2], K), "kernel_ms": round(int_ms, 4),
             "algorithmic_bytes_per_launch": alg}
 
     if args.copy_calibration:

@@ -272,13 +272,21 @@ const char *gg_last_error(void);
 int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c);
 
 /* Launch shape of the volume kernels (tsdf_integrate, tsdf_extract_depth):
- * whole target pixels per workgroup (each thread holding up to 4 consecutive
- * bins of one pixel) and the number of neighbouring pixels interleaved in a
- * wavefront row of tsdf_integrate (a power of two dividing the former; the
- * largest such <= pixels_per_row is used).  0 restores the defaults (512
- * threads' worth of pixels; up to 16 per row).  Results do not depend on the
- * choice; it exists for the autotuner.  Process-wide. */
+ * whole target pixels per workgroup (each thread holding consecutive bins of
+ * one pixel, see gg_set_volume_vector) and the number of neighbouring pixels
+ * interleaved in a wavefront row of tsdf_integrate (a power of two dividing
+ * the former; the largest such <= pixels_per_row is used).  0 restores the
+ * defaults (512 threads' worth of pixels; up to 16 per row).  Results do not
+ * depend on the choice; it exists for the autotuner.  Process-wide. */
 int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
+
+/* Bins held by each thread of the volume kernels: 1, 2, 4 or 8 (0 restores
+ * the default, 4 where it divides num_bins).  Used where it divides
+ * num_bins and, for 8, where every volume argument is 32-byte aligned;
+ * otherwise the largest of 4, 2, 1 dividing num_bins.  Results do not
+ * depend on it; it exists for the autotuner.  Process-wide.  Returns
+ * GG_ERR_INVALID for any other value. */
+int gg_set_volume_vector(int bins_per_thread);
 
 /* Self-check of the correctly rounded reciprocal the fusion kernels use for
  * 1/z: for every FP32 value with biased exponent in [e_lo, e_hi] (all 2^23

@@ -78,6 +78,7 @@ SIGNATURES = {
     "gg_timing_reset": (C.c_int, []),
     "gg_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gg_set_volume_tile": (C.c_int, [C.c_int, C.c_int]),
+    "gg_set_volume_vector": (C.c_int, [C.c_int]),
     "gg_selftest_reciprocal": (C.c_int, [I32, I32, P, P]),
     "gg_batch_create": (C.c_int, [C.POINTER(GGBatchItem), I32, C.POINTER(GGBatchTuning),
                                   C.POINTER(C.c_void_p)]),

@@ -5,8 +5,9 @@ the time does.  The tuner times candidates on the device with HIP events and
 caches the winner per GPU architecture and workload class in a JSON file
 next to this module (``tuning_cache.json``):
 
-* plain path: pixels per workgroup and per wavefront row of the fusion for a
-  (K, D, width, height) class, applied through ``gg_set_volume_tile``;
+* plain path: bins per thread, pixels per workgroup and per wavefront row of
+  the fusion for a (K, D, width, height) class, applied through
+  ``gg_set_volume_vector`` and ``gg_set_volume_tile``;
 * batched path: (threads per fusion workgroup, persistent workgroups per
   compute unit) for a batch signature.
 """
@@ -24,8 +25,9 @@ from . import ops
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
-# (pixels per workgroup, pixels per wavefront row); (0, 0) = defaults
-PLAIN_CANDIDATES = [(0, 0), (0, 1), (4, 4), (8, 1), (8, 8), (16, 8), (16, 16), (32, 8)]
+# (pixels per workgroup, pixels per wavefront row, bins per thread); 0 = default
+PLAIN_CANDIDATES = [(0, 0, 4), (8, 8, 4), (16, 8, 4), (16, 16, 4), (32, 8, 4), (32, 16, 4),
+                    (0, 0, 8), (16, 16, 8), (32, 16, 8), (32, 32, 8), (64, 16, 8), (64, 32, 8)]
 BATCH_CANDIDATES = [(128, 4), (256, 2), (256, 4), (256, 8), (512, 2), (512, 4), (1024, 1),
                     (1024, 2)]
 
@@ -65,28 +67,35 @@ def _time(fn, reps=5, warm=2):
 
 
 def plain_key(K, D, width, height):
-    return f"plain/K{K}/D{D}/{width}x{height}"
+    return f"plain-v/K{K}/D{D}/{width}x{height}"
+
+
+def set_plain(cand):
+    ppb, pw, vec = cand
+    L.check(L.lib().gg_set_volume_tile(ppb, pw))
+    L.check(L.lib().gg_set_volume_vector(vec))
 
 
 def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
-    """Best (pixels per workgroup, pixels per row) of tsdf_integrate for this
-    class; sets it process-wide and returns (best, {candidate: ms})."""
+    """Best (pixels per workgroup, pixels per row, bins per thread) of
+    tsdf_integrate for this class; sets it process-wide and returns
+    (best, {candidate: ms})."""
     tg, tp = ops.camera(tgt), ops.tsdf_params(params)
     key = plain_key(len(src), tp.num_bins, tg.width, tg.height)
     cache = _load()
     a = arch(depth.device)
     if use_cache and key in cache.get(a, {}):
         best = tuple(cache[a][key]["best"])
-        L.check(L.lib().gg_set_volume_tile(*best))
+        set_plain(best)
         return best, cache[a][key]["times"]
     F, W, _, _ = ops.tsdf_integrate(src, depth, tgt, params)
     times = {}
     for cand in PLAIN_CANDIDATES:
-        L.check(L.lib().gg_set_volume_tile(*cand))
-        times["%d,%d" % cand] = _time(lambda: ops.tsdf_integrate(src, depth, tgt, params, F_prev=F,
-                                                                   W_prev=W, F=F, W=W), reps)
+        set_plain(cand)
+        times["%d,%d,%d" % cand] = _time(lambda: ops.tsdf_integrate(
+            src, depth, tgt, params, F_prev=F, W_prev=W, F=F, W=W), reps)
     best = tuple(int(v) for v in min(times, key=times.get).split(","))
-    L.check(L.lib().gg_set_volume_tile(*best))
+    set_plain(best)
     cache.setdefault(a, {})[key] = {"best": list(best), "times": times, "when": time.time()}
     _save(cache)
     return best, times

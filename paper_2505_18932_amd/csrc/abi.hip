@@ -250,6 +250,7 @@ static int check_ws(void *ws, size_t have, size_t need, const char *what) {
 // gg_set_volume_tile).
 static int g_ppb_override = 0;
 static int g_pw_override = -1;
+static int g_v_override = 0;  // bins per thread (gg_set_volume_vector)
 
 struct VolumeShape {
   int V;
@@ -263,8 +264,18 @@ static uint32_t pick_pw_shift(uint32_t ppb, int cap) {
   return sh;
 }
 
-static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what) {
-  s.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+// Bins per thread: the gg_set_volume_vector choice where it divides D (and,
+// for 8, the volumes are 32-byte aligned), else 4, 2 or 1, the largest
+// dividing D.
+static int volume_v(int D, bool aligned32) {
+  const int o = g_v_override;
+  if (o > 0 && D % o == 0 && (o < 8 || aligned32)) return o;
+  return (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+}
+
+static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what,
+                        bool aligned32) {
+  s.V = volume_v(D, aligned32);
   s.cpp = (uint32_t)(D / s.V);
   if (s.cpp > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
   uint32_t ppb = g_ppb_override > 0 ? (uint32_t)g_ppb_override : 512u / s.cpp;
@@ -324,6 +335,15 @@ int gg_set_volume_tile(int pixels_per_block, int pixels_per_row) {
                 pixels_per_row);
   g_ppb_override = pixels_per_block;
   g_pw_override = pixels_per_row == 0 ? -1 : pixels_per_row;
+  return GG_OK;
+}
+
+int gg_set_volume_vector(int bins_per_thread) {
+  if (bins_per_thread != 0 && bins_per_thread != 1 && bins_per_thread != 2 &&
+      bins_per_thread != 4 && bins_per_thread != 8)
+    return fail(GG_ERR_INVALID, "gg_set_volume_vector: %d not in {0, 1, 2, 4, 8}",
+                bins_per_thread);
+  g_v_override = bins_per_thread;
   return GG_OK;
 }
 
@@ -507,7 +527,9 @@ int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg
   const int sw = src[0].width, sh = src[0].height, D = prm->num_bins;
   const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
   VolumeShape vs;
-  if (int rc = volume_shape(D, npix, vs, N)) return rc;
+  const bool a32 = aligned(F, 32) && aligned(W, 32) && (!F_prev || (aligned(F_prev, 32) &&
+                                                                     aligned(W_prev, 32)));
+  if (int rc = volume_shape(D, npix, vs, N, a32)) return rc;
   const size_t va = 4 * (size_t)vs.V;
   if (!aligned(F, va) || !aligned(W, va) || (F_prev && (!aligned(F_prev, va) || !aligned(W_prev, va))))
     return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
@@ -534,7 +556,8 @@ int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const fl
   if (!F || !W || !out_depth || !out_bin) return fail(GG_ERR_INVALID, "%s: NULL argument", N);
   const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
   VolumeShape vs;
-  if (int rc = volume_shape(prm->num_bins, npix, vs, N)) return rc;
+  if (int rc = volume_shape(prm->num_bins, npix, vs, N, aligned(F, 32) && aligned(W, 32)))
+    return rc;
   const size_t va = 4 * (size_t)vs.V;
   if (!aligned(F, va) || !aligned(W, va))
     return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);

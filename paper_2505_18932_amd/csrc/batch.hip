@@ -36,56 +36,71 @@ __global__ void batch_bins_kernel(const BatchItem *__restrict__ items) {
   }
 }
 
-// Dynamic work distribution: each workgroup takes the next entry of the
-// phase's list from a counter the graph zeroes first.  Entries differ in cost
-// by orders of magnitude (items differ in size, view count and bins), so a
-// static split leaves long tails.  Which workgroup runs an entry never
-// changes its result.
-__device__ __forceinline__ uint32_t next_work(uint32_t *ctr, uint32_t *slot) {
-  __syncthreads();  // the previous entry is done with the slot
-  if (threadIdx.x == 0) *slot = atomicAdd(ctr, 1u);
+// Dynamic work distribution in chunks: each workgroup takes the next
+// `chunk` consecutive entries of the phase's list from a counter the graph
+// zeroes first.  Entries differ in cost by orders of magnitude (items differ
+// in size, view count and bins), so a static split leaves long tails; one
+// atomic per entry, on the other hand, serialises on the counter.  The host
+// sizes chunks to about eight per workgroup.  Which workgroup runs an entry
+// never changes its result.
+__device__ __forceinline__ uint32_t next_chunk(uint32_t *ctr, uint32_t chunk, uint32_t *slot) {
+  __syncthreads();  // the previous chunk is done with the slot
+  if (threadIdx.x == 0) *slot = atomicAdd(ctr, chunk);
   __syncthreads();
-  return *slot;
+  // uniform across the workgroup: the entries' descriptors then load
+  // through the scalar unit into SGPRs instead of once per lane
+  return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+// Runs body(w) for every entry w < n this workgroup takes.
+template <typename Body>
+__device__ __forceinline__ void for_each_entry(uint32_t n, uint32_t chunk, uint32_t *ctr,
+                                               Body &&body) {
+  __shared__ uint32_t slot;
+  for (uint32_t w0; (w0 = next_chunk(ctr, chunk, &slot)) < n;) {
+    const uint32_t w1 = n - w0 < chunk ? n : w0 + chunk;
+    for (uint32_t w = w0; w < w1; ++w) body(w);
+  }
 }
 
 __global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__restrict__ items,
                                                          const WorkItem *__restrict__ work,
-                                                         uint32_t n, uint32_t *ctr) {
+                                                         uint32_t n, uint32_t chunk,
+                                                         uint32_t *ctr) {
   __shared__ float tile[kConfTileFloats];
-  __shared__ uint32_t slot;
-  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
+  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
     conf_tile(items[wi.item].conf, wi.k, wi.x, wi.y, tile);
-  }
+  });
 }
 
 template <bool kFill>
 __global__ __launch_bounds__(256) void batch_bin_kernel(const BatchItem *__restrict__ items,
                                                         const WorkItem *__restrict__ work,
-                                                        uint32_t n, uint32_t *ctr) {
-  __shared__ uint32_t slot;
-  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
+                                                        uint32_t n, uint32_t chunk,
+                                                        uint32_t *ctr) {
+  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
     splat_bin_block<kFill>(items[wi.item].splat, wi.k, work_tile(wi));
-  }
+  });
 }
 
 __global__ __launch_bounds__(1024) void batch_scan_kernel(const BatchItem *__restrict__ items,
                                                           const uint32_t *__restrict__ list) {
-  __shared__ uint32_t s[1024];
+  __shared__ ScanLds lds;
   const SplatArgs &a = items[list[blockIdx.x]].splat;
-  tile_scan_block(a.tile_count, a.tile_offset, a.tile_cursor, (uint32_t)a.K * a.ntiles, s);
+  tile_scan_block(a.tile_count, a.tile_offset, a.tile_cursor, (uint32_t)a.K * a.ntiles, lds);
 }
 
 __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__restrict__ items,
                                                            const WorkItem *__restrict__ work,
-                                                           uint32_t n, uint32_t *ctr) {
+                                                           uint32_t n, uint32_t chunk,
+                                                           uint32_t *ctr) {
   __shared__ RasterLds lds;
-  __shared__ uint32_t slot;
-  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
+  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
     raster_tile(items[wi.item].splat, wi.k, work_tile(wi), lds);
-  }
+  });
 }
 
 // Fusion: one workgroup tile of one item per work entry; the view count
@@ -110,13 +125,13 @@ __device__ __forceinline__ void batch_integrate_one(const IntegrateArgs &a, uint
 template <int V>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
-                                                               uint32_t n, uint32_t *ctr) {
+                                                               uint32_t n, uint32_t chunk,
+                                                               uint32_t *ctr) {
   extern __shared__ float smem[];
-  __shared__ uint32_t slot;
-  for (uint32_t w; (w = next_work(ctr, &slot)) < n;) {
+  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
     batch_integrate_one<V>(items[wi.item].integ, work_tile(wi), smem);
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -127,23 +142,33 @@ static int persistent_grid(uint32_t n, int per_cu, int cus) {
   return (int)(n < g ? (n ? n : 1) : g);
 }
 
+// Entries per counter grab: about eight grabs per workgroup.
+static uint32_t chunk_of(uint32_t n, int grid) {
+  const uint64_t c = (uint64_t)n / ((uint64_t)grid * 8u);
+  return c ? (uint32_t)c : 1u;
+}
+
 int batch_record(BatchPlan &P, hipStream_t s) {
   const int cus = P.cus, per = P.blocks_per_cu;
   // tile counts of every item and the phases' work counters
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
   hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
-  if (P.n_conf)
-    hipLaunchKernelGGL(batch_conf_kernel, dim3(persistent_grid(P.n_conf, per, cus)), dim3(256), 0,
-                       s, P.d_items, P.d_conf, P.n_conf, P.d_ctr + 0);
+  if (P.n_conf) {
+    const int g = persistent_grid(P.n_conf, per, cus);
+    hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
+                       chunk_of(P.n_conf, g), P.d_ctr + 0);
+  }
   if (P.n_bin) {
-    hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(persistent_grid(P.n_bin, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin, P.d_ctr + 1);
+    const int gb = persistent_grid(P.n_bin, per, cus);
+    const int gr = persistent_grid(P.n_raster, per, cus);
+    hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
                        P.d_splat_items);
-    hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(persistent_grid(P.n_bin, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_bin, P.n_bin, P.d_ctr + 2);
-    hipLaunchKernelGGL(batch_raster_kernel, dim3(persistent_grid(P.n_raster, per, cus)),
-                       dim3(256), 0, s, P.d_items, P.d_raster, P.n_raster, P.d_ctr + 3);
+    hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2);
+    hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, s, P.d_items, P.d_raster,
+                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3);
   }
   for (int g = 0; g < 3; ++g) {
     const uint32_t n = P.n_integ[g];
@@ -151,16 +176,17 @@ int batch_record(BatchPlan &P, hipStream_t s) {
     const int V = g == 0 ? 4 : (g == 1 ? 2 : 1);
     const uint32_t threads = P.integ_threads;
     const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * threads;
-    const dim3 grid(persistent_grid(n, per, cus));
+    const int gi = persistent_grid(n, per, cus);
+    const uint32_t ch = chunk_of(n, gi);
     if (V == 4)
-      hipLaunchKernelGGL(batch_integrate_kernel<4>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, P.d_ctr + 4 + g);
+      hipLaunchKernelGGL(batch_integrate_kernel<4>, dim3(gi), dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
     else if (V == 2)
-      hipLaunchKernelGGL(batch_integrate_kernel<2>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, P.d_ctr + 4 + g);
+      hipLaunchKernelGGL(batch_integrate_kernel<2>, dim3(gi), dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
     else
-      hipLaunchKernelGGL(batch_integrate_kernel<1>, grid, dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, P.d_ctr + 4 + g);
+      hipLaunchKernelGGL(batch_integrate_kernel<1>, dim3(gi), dim3(threads), shm, s, P.d_items,
+                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
   }
   return check_hip(hipGetLastError(), "batch phases");
 }

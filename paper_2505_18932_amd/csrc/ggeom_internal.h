@@ -74,6 +74,23 @@ __device__ __forceinline__ void gstore2(float2 *p, float2 v) {
   *(GG_GLOBAL gg_v2f *)p = (gg_v2f){v.x, v.y};
 }
 
+// Range-checked loads through a buffer resource (raw addressing, stride 0):
+// a load at a byte offset at or beyond the resource's size returns zeros
+// and touches no memory.  kOutOfRange is beyond every resource made here
+// (sizes are at most 2^31 bytes).
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *p, uint32_t bytes) {
+  // last word: 32-bit data format, no swizzle, no index addressing
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const gg_v2f v = __builtin_bit_cast(gg_v2f, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return make_float2(v.x, v.y);
+}
+
 __device__ __forceinline__ uint32_t gatomic_add(uint32_t *p, uint32_t v) {
   return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -27,8 +27,8 @@ __global__ __launch_bounds__(256) void splat_bin_kernel(SplatArgs a) {
 
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint32_t *off,
                                                          uint32_t *cursor, uint32_t n) {
-  __shared__ uint32_t s[1024];
-  tile_scan_block(cnt, off, cursor, n, s);
+  __shared__ ScanLds lds;
+  tile_scan_block(cnt, off, cursor, n, lds);
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {

@@ -107,28 +107,65 @@ __device__ __forceinline__ void splat_bin_block(const SplatArgs &a, int k, uint3
 
 // Exclusive scan of n counters by one workgroup of 1024 threads; also
 // clears the cursors.  off has n + 1 entries (the last is the total).
+// Chunks of kScanChunk counters are staged through LDS so that global loads
+// and stores are coalesced; each thread scans 8 consecutive entries, the
+// 1024 partial sums are scanned with wavefront shuffles.
+constexpr uint32_t kScanChunk = 8192;
+struct ScanLds {
+  uint32_t buf[kScanChunk];
+  uint32_t wave[16];
+  uint32_t part[1024];
+};
+
 __device__ __forceinline__ void tile_scan_block(const uint32_t *cnt, uint32_t *off,
-                                                uint32_t *cursor, uint32_t n, uint32_t *s) {
-  const uint32_t t = threadIdx.x;
-  const uint32_t per = (n + 1023u) / 1024u;
-  const uint32_t b = t * per, e = min(b + per, n);
-  uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += gmem(cnt)[i];
-  s[t] = sum;
-  __syncthreads();
-  for (uint32_t o = 1; o < 1024; o <<= 1) {
-    const uint32_t v = t >= o ? s[t - o] : 0u;
+                                                uint32_t *cursor, uint32_t n, ScanLds &L) {
+  const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < n; base += kScanChunk) {
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) {
+      const uint32_t g = base + t + 1024u * i;
+      L.buf[t + 1024u * i] = g < n ? gmem(cnt)[g] : 0u;
+    }
     __syncthreads();
-    s[t] += v;
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) sum += L.buf[8u * t + i];
+    // inclusive scan of the partial sums within the wavefront
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(inc, d);
+      if ((int)lane >= d) inc += v;
+    }
+    if (lane == 63) L.wave[wv] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      const uint32_t x = L.wave[w];
+      wbase += w < wv ? x : 0u;
+      total += x;
+    }
+    uint32_t run = carry + wbase + inc - sum;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) {
+      const uint32_t c = L.buf[8u * t + i];
+      L.buf[8u * t + i] = run;
+      run += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) {
+      const uint32_t g = base + t + 1024u * i;
+      if (g < n) {
+        gmem(off)[g] = L.buf[t + 1024u * i];
+        gmem(cursor)[g] = 0u;
+      }
+    }
+    carry += total;
     __syncthreads();
   }
-  uint32_t run = s[t] - sum;
-  for (uint32_t i = b; i < e; ++i) {
-    gmem(off)[i] = run;
-    run += gmem(cnt)[i];
-    gmem(cursor)[i] = 0u;
-  }
-  if (t == 1023) gmem(off)[n] = s[1023];
+  if (t == 0) gmem(off)[n] = carry;
   __syncthreads();
 }
 

@@ -85,7 +85,9 @@ static void launch_integrate_v(const IntegrateArgs &a, uint32_t threads, size_t 
 int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_t s) {
   KernelTimer t("integrate", s);
   const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * a.ppb;
-  if (V == 4)
+  if (V == 8)
+    launch_integrate_v<8>(a, threads, shm, s);
+  else if (V == 4)
     launch_integrate_v<4>(a, threads, shm, s);
   else if (V == 2)
     launch_integrate_v<2>(a, threads, shm, s);
@@ -127,7 +129,9 @@ __global__ __launch_bounds__(1024) void extract_kernel(ExtractArgs a) {
 int launch_extract(const ExtractArgs &a, int V, uint32_t threads, hipStream_t s) {
   KernelTimer t("extract", s);
   const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * a.ppb;
-  if (V == 4)
+  if (V == 8)
+    hipLaunchKernelGGL(extract_kernel<8>, dim3(a.nblocks), dim3(threads), shm, s, a);
+  else if (V == 4)
     hipLaunchKernelGGL(extract_kernel<4>, dim3(a.nblocks), dim3(threads), shm, s, a);
   else if (V == 2)
     hipLaunchKernelGGL(extract_kernel<2>, dim3(a.nblocks), dim3(threads), shm, s, a);

@@ -92,7 +92,11 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
 
 template <int V>
 __device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
-  if constexpr (V == 4) {
+  if constexpr (V == 8) {
+    const gg_v4f a = *(const GG_GLOBAL gg_v4f *)p, b = *(const GG_GLOBAL gg_v4f *)(p + 4);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+  } else if constexpr (V == 4) {
     const gg_v4f v = *(const GG_GLOBAL gg_v4f *)p;
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   } else if constexpr (V == 2) {
@@ -105,7 +109,10 @@ __device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
 
 template <int V>
 __device__ __forceinline__ void storev(float *p, const float (&o)[V]) {
-  if constexpr (V == 4) {
+  if constexpr (V == 8) {
+    *(GG_GLOBAL gg_v4f *)p = (gg_v4f){o[0], o[1], o[2], o[3]};
+    *(GG_GLOBAL gg_v4f *)(p + 4) = (gg_v4f){o[4], o[5], o[6], o[7]};
+  } else if constexpr (V == 4) {
     *(GG_GLOBAL gg_v4f *)p = (gg_v4f){o[0], o[1], o[2], o[3]};
   } else if constexpr (V == 2) {
     *(GG_GLOBAL gg_v2f *)p = (gg_v2f){o[0], o[1]};
@@ -192,77 +199,104 @@ __device__ __forceinline__ void extract_block(const float (&F)[V], const float (
 // accumulated in view order.  The gathers of a thread are independent, so
 // their L2 latencies overlap.
 
-// The pixel of view k sampled by the point (X0, X1, Z) (homogeneous pixel
-// coordinates): (floor(X0 / Z), floor(X1 / Z)) with the quotient evaluated
-// as X * (1 / Z).  Returns false if Z <= 0 or the pixel is outside the
-// image; idx is then 0 (a valid address).
-template <bool kExact>
-__device__ __forceinline__ bool sample_pixel(float X0, float X1, float Z, uint32_t Ws,
-                                             uint32_t Hs, float fWs, float fHs, uint32_t &idx) {
-  bool ok;
-  if constexpr (!kExact) {
-    const float inv = recip_rn(Z);
-    const uint32_t i = (uint32_t)floor_i32(X0 * inv), j = (uint32_t)floor_i32(X1 * inv);
-    ok = (Z > kRecipLo) && i < Ws && j < Hs;
-    idx = ok ? j * Ws + i : 0u;
-    // 0 < Z <= 2^-100: the reciprocal is outside the fast range (rare)
-    if (__builtin_expect(__any(Z > 0.0f && !(Z > kRecipLo)), 0)) {
-      if (Z > 0.0f && !(Z > kRecipLo)) {
-        const float iv = 1.0f / Z;
-        const float u = X0 * iv, w = X1 * iv;
-        ok = u >= 0.0f && u < fWs && w >= 0.0f && w < fHs;
-        idx = ok ? (uint32_t)w * Ws + (uint32_t)u : 0u;
-      }
-    }
-  } else {
-    ok = false;
-    idx = 0u;
+// How a view's samples of the thread's bins find their pixels.  The pixel
+// of the point (X0, X1, Z) (homogeneous pixel coordinates) is
+// (floor(X0 / Z), floor(X1 / Z)) with the quotient evaluated as X * (1 / Z),
+// none if Z <= 0 or outside the image.  1 / Z is correctly rounded in every
+// mode: by recip_rn where it is exact (0 < Z < 2^100; the upper end is
+// checked on the host), by IEEE division where a depth may lie in
+// (0, 2^-100].
+enum : int {
+  kInFront = 0,  // every sample has Z > 2^-100: no depth test per sample
+  kChecked = 1,  // no sample has Z in (0, 2^-100]: recip_rn, Z tested
+  kDivide = 2,   // IEEE division
+};
+
+// Byte offset of the sample's view-table record, kOutOfRange if none.
+template <int kMode>
+__device__ __forceinline__ uint32_t sample_offset(float X0, float X1, float Z, uint32_t Ws,
+                                                  uint32_t Hs, float fWs, float fHs) {
+  if constexpr (kMode == kDivide) {
+    uint32_t off = kOutOfRange;
     if (Z > 0.0f) {
       const float iv = 1.0f / Z;
       const float u = X0 * iv, w = X1 * iv;
-      ok = u >= 0.0f && u < fWs && w >= 0.0f && w < fHs;
-      idx = ok ? (uint32_t)w * Ws + (uint32_t)u : 0u;
+      if (u >= 0.0f && u < fWs && w >= 0.0f && w < fHs)
+        off = ((uint32_t)w * Ws + (uint32_t)u) << 3;
     }
+    return off;
+  } else {
+    const float inv = recip_rn(Z);
+    const uint32_t i = (uint32_t)floor_i32(X0 * inv), j = (uint32_t)floor_i32(X1 * inv);
+    bool ok = i < Ws && j < Hs;
+    if constexpr (kMode == kChecked) ok = ok && (Z > kRecipLo);
+    // sizes are at most 16384 (host check): Ws * 8 < 2^24, the offset < 2^31
+    return ok ? __umul24(j, Ws << 3) + (i << 3) : kOutOfRange;
   }
-  return ok;
 }
 
-// One view's samples of the V voxels: geometry and gathers (issued, not
-// consumed).
-template <int V, bool kExact>
+// The view's depth over the thread's bins, fma(z, h2, c2), is monotone in z
+// and the bin depths increase with the bin index, so the end bins bound it.
+template <int V>
+__device__ __forceinline__ void view_depth_range(const Proj &P, float px, float py,
+                                                 const float (&z)[V], float &lo, float &hi) {
+  float h0, h1, h2;
+  ray_of(P, px, py, h0, h1, h2);
+  const float Za = fmaf(z[0], h2, P.c[2]), Zb = fmaf(z[V - 1], h2, P.c[2]);
+  lo = fminf(Za, Zb);
+  hi = fmaxf(Za, Zb);
+}
+
+// Wave-uniform mode for one view.
+template <int V>
+__device__ __forceinline__ int view_mode(const Proj &P, float px, float py, const float (&z)[V]) {
+  float lo, hi;
+  view_depth_range<V>(P, px, py, z, lo, hi);
+  if (__all(lo > kRecipLo)) return kInFront;
+  // a lane whose bins straddle the camera plane may have a depth in (0, 2^-100]
+  return __any(hi > 0.0f && !(lo > kRecipLo)) ? kDivide : kChecked;
+}
+
+// One view's samples of the V voxels: depths and table gathers (left in
+// flight for the caller).  A sample with no pixel reads the record (0, 0)
+// from the range-checked load, whose zero weight drops it.
+template <int V, int kMode>
 __device__ __forceinline__ void view_samples(const IntegrateArgs &a, int k, float px, float py,
-                                             const float (&z)[V], float (&Z)[V], bool (&ok)[V],
+                                             const float (&z)[V], float (&Z)[V],
                                              float2 (&e)[V]) {
   const Proj &P = a.views[k];
   float h0, h1, h2;
   ray_of(P, px, py, h0, h1, h2);
-  const float2 *tab = a.table + (size_t)k * a.ns;
+  const __amdgpu_buffer_rsrc_t tab = buffer_of(a.table + (size_t)k * a.ns, a.ns * 8u);
   const float fWs = (float)a.Ws, fHs = (float)a.Hs;
-  uint32_t idx[V];
+  uint32_t off[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const float X0 = fmaf(z[v], h0, P.c[0]);
     const float X1 = fmaf(z[v], h1, P.c[1]);
     Z[v] = fmaf(z[v], h2, P.c[2]);
-    ok[v] = sample_pixel<kExact>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs, idx[v]);
+    off[v] = sample_offset<kMode>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs);
   }
 #pragma unroll
-  for (int v = 0; v < V; ++v) e[v] = gload2(tab + idx[v]);
+  for (int v = 0; v < V; ++v) e[v] = bload2(tab, off[v]);
 }
 
-// Accumulate one view's samples: s = D_k - z_k, occlusion cut, clamp.
+// Accumulate one view's samples: s = D_k - z_k, occlusion cut (s < -tau:
+// dropped), clamp min(s, tau).  Branch-free: the clamp to [-tau, tau] equals
+// min(s, tau) for every kept sample and stays finite for dropped ones (a
+// hole's depth is -inf), which add (+0) * c and +0 and so leave S and Wo
+// bitwise unchanged (both start at +0 and never become -0).
 template <int V>
-__device__ __forceinline__ void view_accumulate(const float (&Z)[V], const bool (&ok)[V],
-                                                const float2 (&e)[V], const float (&tau)[V],
-                                                float (&S)[V], float (&Wo)[V]) {
+__device__ __forceinline__ void view_accumulate(const float (&Z)[V], const float2 (&e)[V],
+                                                const float (&tau)[V], float (&S)[V],
+                                                float (&Wo)[V]) {
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const float s = e[v].x - Z[v];  // -inf for a hole: dropped by the test
-    if (ok[v] && !(s < -tau[v])) {
-      const float c = fminf(s, tau[v]);
-      S[v] = fmaf(e[v].y, c, S[v]);
-      Wo[v] = Wo[v] + e[v].y;
-    }
+    const float s = e[v].x - Z[v];
+    const float c = __builtin_amdgcn_fmed3f(s, -tau[v], tau[v]);
+    const float w = (s < -tau[v]) ? 0.0f : e[v].y;
+    S[v] = fmaf(w, c, S[v]);
+    Wo[v] = Wo[v] + w;
   }
 }
 
@@ -270,45 +304,78 @@ __device__ __forceinline__ void view_accumulate(const float (&Z)[V], const bool 
 // after_issue() (the caller's own loads, so that in-order load completion
 // lets the gathers be consumed while those are still in flight), then the
 // samples are accumulated in view order.
-template <int V, int G, bool kExact, typename AfterIssue>
+template <int V, int G, int kMode, typename AfterIssue>
 __device__ __forceinline__ void fuse_group(const IntegrateArgs &a, int k0, float px, float py,
                                            const float (&z)[V], const float (&tau)[V],
                                            float (&S)[V], float (&Wo)[V],
                                            AfterIssue &&after_issue) {
   float Z[G][V];
-  bool ok[G][V];
   float2 e[G][V];
 #pragma unroll
-  for (int g = 0; g < G; ++g) view_samples<V, kExact>(a, k0 + g, px, py, z, Z[g], ok[g], e[g]);
+  for (int g = 0; g < G; ++g) view_samples<V, kMode>(a, k0 + g, px, py, z, Z[g], e[g]);
   after_issue();
 #pragma unroll
-  for (int g = 0; g < G; ++g) view_accumulate<V>(Z[g], ok[g], e[g], tau, S, Wo);
+  for (int g = 0; g < G; ++g) view_accumulate<V>(Z[g], e[g], tau, S, Wo);
 }
 
-// Views per group for a compile-time view count (at most 4 in flight).
-template <int KC>
+// Views per group for a compile-time view count: at most 16 samples (and
+// 4 views) in flight, the group size dividing KC.
+template <int KC, int V>
 constexpr int view_group() {
-  return KC <= 4 ? KC : (KC % 4 == 0 ? 4 : (KC % 3 == 0 ? 3 : (KC % 2 == 0 ? 2 : 1)));
+  constexpr int m = (16 / V < 4) ? (16 / V < 1 ? 1 : 16 / V) : 4;
+  int g = KC < m ? KC : m;
+  while (g > 1 && KC % g != 0) --g;
+  return g;
 }
 
-// KC > 0: the view count is a compile-time constant; views are processed in
-// unrolled groups and the caller's loads are issued after the first group's
-// gathers.  KC == 0: runtime view count, one view at a time, the caller's
-// loads issued first.
+// View count KC > 0 known at compile time, every sample in front of its
+// view: views in unrolled groups, the caller's loads issued after the first
+// group's gathers.
+template <int V, int KC, typename AfterIssue>
+__device__ __forceinline__ void fuse_views_in_front(const IntegrateArgs &a, float px, float py,
+                                                    const float (&z)[V], const float (&tau)[V],
+                                                    float (&S)[V], float (&Wo)[V],
+                                                    AfterIssue &&after_issue) {
+  constexpr int G = view_group<KC, V>();
+  fuse_group<V, G, kInFront>(a, 0, px, py, z, tau, S, Wo, after_issue);
+#pragma unroll
+  for (int k0 = G; k0 < KC; k0 += G)
+    fuse_group<V, G, kInFront>(a, k0, px, py, z, tau, S, Wo, [] {});
+}
+
+// KC > 0 and every sample of the wave in front of every view (one
+// wave-uniform test): the unrolled straight-line variant.  Otherwise (and
+// for a runtime view count, KC == 0, or under kExact) one view at a time in
+// a loop, each in its own wave-uniform mode, the caller's loads first.
 template <int V, int KC, bool kExact, typename AfterIssue>
 __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, float py,
                                             const float (&z)[V], const float (&tau)[V],
                                             float (&S)[V], float (&Wo)[V],
                                             AfterIssue &&after_issue) {
-  if constexpr (KC > 0) {
-    constexpr int G = view_group<KC>();
-    fuse_group<V, G, kExact>(a, 0, px, py, z, tau, S, Wo, after_issue);
+  if constexpr (KC > 0 && !kExact) {
+    bool front = true;
 #pragma unroll
-    for (int k0 = G; k0 < KC; k0 += G)
-      fuse_group<V, G, kExact>(a, k0, px, py, z, tau, S, Wo, [] {});
-  } else {
-    after_issue();
-    for (int k = 0; k < a.K; ++k) fuse_group<V, 1, kExact>(a, k, px, py, z, tau, S, Wo, [] {});
+    for (int k = 0; k < KC; ++k) {
+      float lo, hi;
+      view_depth_range<V>(a.views[k], px, py, z, lo, hi);
+      front = front && lo > kRecipLo;
+    }
+    if (__builtin_expect(__all(front), 1)) {
+      fuse_views_in_front<V, KC>(a, px, py, z, tau, S, Wo, after_issue);
+      return;
+    }
+  }
+  after_issue();
+  const int K = KC > 0 ? KC : a.K;
+#pragma nounroll
+  for (int k = 0; k < K; ++k) {
+    const int mode = kExact ? kDivide : view_mode<V>(a.views[k], px, py, z);
+    if (mode == kInFront)
+      fuse_group<V, 1, kInFront>(a, k, px, py, z, tau, S, Wo, [] {});
+    else if (mode == kChecked)
+      fuse_group<V, 1, kChecked>(a, k, px, py, z, tau, S, Wo, [] {});
+    else
+      fuse_group<V, 1, kDivide>(a, k, px, py, z, tau, S, Wo, [] {});
   }
 }
 

@@ -119,6 +119,18 @@ def test_tsdf_rejects_invalid_arguments():
         L.GG_ERR_INVALID
 
 
+def test_launch_shape_setters_validate():
+    lib = L.lib()
+    for bad in (-1, 3, 5, 16):
+        assert lib.gg_set_volume_vector(bad) == L.GG_ERR_INVALID
+    for ok in (0, 1, 2, 4, 8, 0):
+        assert lib.gg_set_volume_vector(ok) == L.GG_OK
+    assert lib.gg_set_volume_tile(-1, 0) == L.GG_ERR_INVALID
+    assert lib.gg_set_volume_tile(1025, 0) == L.GG_ERR_INVALID
+    assert lib.gg_set_volume_tile(8, 65) == L.GG_ERR_INVALID
+    assert lib.gg_set_volume_tile(0, 0) == L.GG_OK
+
+
 def test_workspace_sizes():
     sp = scenes.splat_params()
     n = ops.workspace_size(L.GG_OP_SPLAT, 4, 1280, 720, 1280, 720, 2, sp)

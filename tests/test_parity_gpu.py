@@ -232,15 +232,22 @@ def test_volume_tile_shape_does_not_change_results():
     c = small(bins=96)
     depth, _ = to_dev(c)
     base = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    F, W = base[0], base[1]
     try:
-        for ppb in ((1, 1), (3, 1), (8, 1), (8, 8), (40, 8), (32, 32)):
-            gg._lib.check(gg._lib.lib().gg_set_volume_tile(*ppb))
-            v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
-            torch.cuda.synchronize()
-            for a, b in zip(v, base):
-                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), ppb
+        for vec in (1, 2, 4, 8):
+            gg._lib.check(gg._lib.lib().gg_set_volume_vector(vec))
+            for ppb in ((0, 0), (1, 1), (3, 1), (8, 1), (8, 8), (40, 8), (32, 32)):
+                gg._lib.check(gg._lib.lib().gg_set_volume_tile(*ppb))
+                v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+                e = gg.tsdf_extract_depth(c["tgt"], c["tsdf"], F, W)
+                torch.cuda.synchronize()
+                for a, b in zip(v, base):
+                    assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (vec, ppb)
+                for a, b in zip(e, base[2:]):
+                    assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (vec, ppb)
     finally:
         gg._lib.lib().gg_set_volume_tile(0, 0)
+        gg._lib.lib().gg_set_volume_vector(0)
 
 
 # ---------------------------------------------------------------------------
