@@ -704,6 +704,13 @@ struct gg_batch {
   std::vector<char> keep;  // nothing host-side is needed after creation
 };
 
+// Bins per thread of a batch item (as for the plain call).
+static int item_vec(const gg_batch_item &it) {
+  const bool a32 = aligned(it.F, 32) && aligned(it.W, 32) &&
+                   (!it.F_prev || (aligned(it.F_prev, 32) && aligned(it.W_prev, 32)));
+  return volume_v(it.tsdf.num_bins, a32);
+}
+
 static int check_item(const gg_batch_item &it, int i) {
   char what[64];
   snprintf(what, sizeof what, "gg_batch_create: item %d", i);
@@ -721,7 +728,7 @@ static int check_item(const gg_batch_item &it, int i) {
       return fail(GG_ERR_INVALID, "%s: splat outputs required with rgb", what);
   }
   const int D = it.tsdf.num_bins;
-  const int V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+  const int V = item_vec(it);
   if (D / V > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
   const size_t va = 4 * (size_t)V;
   if (!aligned(it.F, va) || !aligned(it.W, va) ||
@@ -745,7 +752,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
                 "blocks_per_cu in 1..64", N);
   for (int i = 0; i < n; ++i) {
     const int D = items[i].tsdf.num_bins;
-    const int V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+    const int V = item_vec(items[i]);
     while (threads < D / V) threads += 64;
   }
   int dev = 0, cus = 256;
@@ -755,7 +762,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
 
   // host descriptors, work lists and the device-memory layout
   std::vector<BatchItem> h(n);
-  std::vector<WorkItem> conf, bin, raster, integ[3];
+  std::vector<WorkItem> conf, bin, raster, integ[kIntegClasses];
   std::vector<uint32_t> splat_items;
   std::vector<VolumeShape> shapes(n);
   std::vector<SplatLayout> sl(n);
@@ -768,7 +775,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
     const int sw = it.src[0].width, sh = it.src[0].height, K = it.K, D = it.tsdf.num_bins;
     const uint32_t npix = (uint32_t)(it.tgt.width * it.tgt.height);
     VolumeShape &vs = shapes[i];
-    vs.V = (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
+    vs.V = item_vec(it);
     vs.cpp = (uint32_t)(D / vs.V);
     vs.ppb = std::max(1u, (uint32_t)threads / vs.cpp);
     vs.threads = vs.ppb * vs.cpp;
@@ -804,7 +811,10 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
           raster.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
       }
     }
-    const int g = vs.V == 4 ? 0 : (vs.V == 2 ? 1 : 2);
+    IntegrateArgs probe{};  // only for the view count class and the reciprocal's range
+    make_integrate_args(probe, it.src, it.K, it.tgt, it.tsdf, vs, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    const int g = integ_class(vs.V, K, probe.exact_only != 0);
     for (uint32_t t = 0; t < vs.nblocks; ++t)
       integ[g].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
   }
@@ -813,8 +823,8 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   auto put = [&](size_t bytes) { const size_t o = off; off += up256(bytes ? bytes : 1); return o; };
   const size_t o_conf = put(sizeof(WorkItem) * conf.size()), o_bin = put(sizeof(WorkItem) * bin.size()),
                o_raster = put(sizeof(WorkItem) * raster.size());
-  size_t o_integ[3];
-  for (int g = 0; g < 3; ++g) o_integ[g] = put(sizeof(WorkItem) * integ[g].size());
+  size_t o_integ[kIntegClasses];
+  for (int g = 0; g < kIntegClasses; ++g) o_integ[g] = put(sizeof(WorkItem) * integ[g].size());
   const size_t o_sitems = put(4 * splat_items.size());
 
   gg_batch *b = new gg_batch();
@@ -863,7 +873,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   P.n_bin = (uint32_t)bin.size();
   P.d_raster = (WorkItem *)(dv + o_raster);
   P.n_raster = (uint32_t)raster.size();
-  for (int g = 0; g < 3; ++g) {
+  for (int g = 0; g < kIntegClasses; ++g) {
     P.d_integ[g] = (WorkItem *)(dv + o_integ[g]);
     P.n_integ[g] = (uint32_t)integ[g].size();
   }
@@ -880,7 +890,9 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   cp(o_conf, conf.data(), sizeof(WorkItem) * conf.size());
   cp(o_bin, bin.data(), sizeof(WorkItem) * bin.size());
   cp(o_raster, raster.data(), sizeof(WorkItem) * raster.size());
-  for (int g = 0; g < 3; ++g) cp(o_integ[g], integ[g].data(), sizeof(WorkItem) * integ[g].size());
+  for (int g = 0; g < kIntegClasses; ++g)
+    cp(o_integ[g], integ[g].data(), sizeof(WorkItem) * integ[g].size());
+  if (rc == GG_OK) rc = batch_occupancy(P);
   cp(o_sitems, splat_items.data(), 4 * splat_items.size());
   // capture every phase into one graph
   hipStream_t cs = nullptr;

@@ -103,26 +103,10 @@ __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__re
   });
 }
 
-// Fusion: one workgroup tile of one item per work entry; the view count
-// selects a specialisation (same operation order as the plain kernel).
-template <int V>
-__device__ __forceinline__ void batch_integrate_one(const IntegrateArgs &a, uint32_t tile,
-                                                    float *smem) {
-  if (a.exact_only) {
-    integrate_tile<V, 0, true>(a, tile, smem);
-    return;
-  }
-  switch (a.K) {
-    case 2: integrate_tile<V, 2, false>(a, tile, smem); break;
-    case 3: integrate_tile<V, 3, false>(a, tile, smem); break;
-    case 4: integrate_tile<V, 4, false>(a, tile, smem); break;
-    case 6: integrate_tile<V, 6, false>(a, tile, smem); break;
-    case 8: integrate_tile<V, 8, false>(a, tile, smem); break;
-    default: integrate_tile<V, 0, false>(a, tile, smem); break;
-  }
-}
-
-template <int V>
+// Fusion: one workgroup tile of one item per work entry, every entry of a
+// launch in the same specialisation as the plain kernel (so the same code
+// and register budget).
+template <int V, int KC, bool kExact>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
                                                                uint32_t n, uint32_t chunk,
@@ -130,15 +114,34 @@ __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *
   extern __shared__ float smem[];
   for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
-    batch_integrate_one<V>(items[wi.item].integ, work_tile(wi), smem);
+    integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
   });
+}
+
+template <int C>
+static void launch_integ_class(const BatchPlan &P, uint32_t n, int grid, uint32_t chunk,
+                               size_t shm, hipStream_t s) {
+  hipLaunchKernelGGL((batch_integrate_kernel<vec_of_class(C), views_of_class(C), exact_class(C)>),
+                     dim3(grid), dim3(P.integ_threads), shm, s, P.d_items, P.d_integ[C], n, chunk,
+                     P.d_ctr + kLightCounters + C);
+}
+
+template <int C>
+static void dispatch_integ_class(int c, const BatchPlan &P, uint32_t n, int grid, uint32_t chunk,
+                                 size_t shm, hipStream_t s) {
+  if constexpr (C < kIntegClasses) {
+    if (c == C)
+      launch_integ_class<C>(P, n, grid, chunk, shm, s);
+    else
+      dispatch_integ_class<C + 1>(c, P, n, grid, chunk, shm, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // plan
 
 static int persistent_grid(uint32_t n, int per_cu, int cus) {
-  const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+  const uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
   return (int)(n < g ? (n ? n : 1) : g);
 }
 
@@ -148,19 +151,38 @@ static uint32_t chunk_of(uint32_t n, int grid) {
   return c ? (uint32_t)c : 1u;
 }
 
+// Resident workgroups per CU of the light phases: their persistent grids
+// fill the device exactly.
+int batch_occupancy(BatchPlan &P) {
+  int a = 0, b = 0, c = 0;
+  if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_conf_kernel, 256, 0),
+                         "batch occupancy"))
+    return rc;
+  if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &b, batch_bin_kernel<true>, 256, 0), "batch occupancy"))
+    return rc;
+  if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, batch_raster_kernel, 256,
+                                                                      0), "batch occupancy"))
+    return rc;
+  P.occ_conf = a > 0 ? a : 1;
+  P.occ_bin = b > 0 ? b : 1;
+  P.occ_raster = c > 0 ? c : 1;
+  return GG_OK;
+}
+
 int batch_record(BatchPlan &P, hipStream_t s) {
   const int cus = P.cus, per = P.blocks_per_cu;
   // tile counts of every item and the phases' work counters
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
   hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
   if (P.n_conf) {
-    const int g = persistent_grid(P.n_conf, per, cus);
+    const int g = persistent_grid(P.n_conf, P.occ_conf, cus);
     hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
                        chunk_of(P.n_conf, g), P.d_ctr + 0);
   }
   if (P.n_bin) {
-    const int gb = persistent_grid(P.n_bin, per, cus);
-    const int gr = persistent_grid(P.n_raster, per, cus);
+    const int gb = persistent_grid(P.n_bin, P.occ_bin, cus);
+    const int gr = persistent_grid(P.n_raster, P.occ_raster, cus);
     hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
                        P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
@@ -170,23 +192,12 @@ int batch_record(BatchPlan &P, hipStream_t s) {
     hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, s, P.d_items, P.d_raster,
                        P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3);
   }
-  for (int g = 0; g < 3; ++g) {
-    const uint32_t n = P.n_integ[g];
+  const size_t shm = sizeof(float) * 2 * P.integ_threads + sizeof(int) * P.integ_threads;
+  for (int c = 0; c < kIntegClasses; ++c) {
+    const uint32_t n = P.n_integ[c];
     if (!n) continue;
-    const int V = g == 0 ? 4 : (g == 1 ? 2 : 1);
-    const uint32_t threads = P.integ_threads;
-    const size_t shm = sizeof(float) * 2 * threads + sizeof(int) * threads;
-    const int gi = persistent_grid(n, per, cus);
-    const uint32_t ch = chunk_of(n, gi);
-    if (V == 4)
-      hipLaunchKernelGGL(batch_integrate_kernel<4>, dim3(gi), dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
-    else if (V == 2)
-      hipLaunchKernelGGL(batch_integrate_kernel<2>, dim3(gi), dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
-    else
-      hipLaunchKernelGGL(batch_integrate_kernel<1>, dim3(gi), dim3(threads), shm, s, P.d_items,
-                         P.d_integ[g], n, ch, P.d_ctr + 4 + g);
+    const int g = persistent_grid(n, per, cus);
+    dispatch_integ_class<0>(c, P, n, g, chunk_of(n, g), shm, s);
   }
   return check_hip(hipGetLastError(), "batch phases");
 }

@@ -7,7 +7,36 @@
 namespace gg {
 
 constexpr int kConfTileFloats = kConfLH * kConfLW;
-constexpr int kBatchCounters = 8;
+
+// Fusion work is split into classes that each run one specialisation of the
+// plain kernel's device function: bins per thread (8, 4, 2, 1) times view
+// count (1, 2, 3, 4, 6, 8 compile-time, other counts at run time, or every
+// sample by IEEE division).
+constexpr int kVecClasses = 4, kViewClasses = 8;
+constexpr int kIntegClasses = kVecClasses * kViewClasses;
+constexpr int kLightCounters = 4;  // confidence, bin count, bin fill, raster
+constexpr int kBatchCounters = kLightCounters + kIntegClasses;
+
+__host__ __device__ constexpr int vec_of_class(int c) { return 8 >> (c / kViewClasses); }
+__host__ __device__ constexpr int views_of_class(int c) {
+  return (c % kViewClasses) < 4 ? (c % kViewClasses) + 1
+                                : ((c % kViewClasses) == 4 ? 6 : ((c % kViewClasses) == 5 ? 8 : 0));
+}
+__host__ __device__ constexpr bool exact_class(int c) { return c % kViewClasses == 7; }
+
+inline int integ_class(int V, int K, bool exact_only) {
+  const int vi = V == 8 ? 0 : (V == 4 ? 1 : (V == 2 ? 2 : 3));
+  int kc = 6;  // runtime view count
+  if (exact_only)
+    kc = 7;
+  else if (K >= 1 && K <= 4)
+    kc = K - 1;
+  else if (K == 6)
+    kc = 4;
+  else if (K == 8)
+    kc = 5;
+  return vi * kViewClasses + kc;
+}
 
 // Everything one item's phases need, in device memory (read with scalar
 // loads: the descriptor address is uniform per work entry).
@@ -37,12 +66,13 @@ struct BatchPlan {
   int32_t n_items = 0;
   int cus = 256, blocks_per_cu = 4;
   uint32_t integ_threads = 256;
+  int occ_conf = 1, occ_bin = 1, occ_raster = 1;  // resident workgroups per CU
   // device memory owned by the plan
   void *dev = nullptr;
   size_t dev_bytes = 0;
   BatchItem *d_items = nullptr;
-  WorkItem *d_conf = nullptr, *d_bin = nullptr, *d_raster = nullptr, *d_integ[3] = {};
-  uint32_t n_conf = 0, n_bin = 0, n_raster = 0, n_integ[3] = {};
+  WorkItem *d_conf = nullptr, *d_bin = nullptr, *d_raster = nullptr, *d_integ[kIntegClasses] = {};
+  uint32_t n_conf = 0, n_bin = 0, n_raster = 0, n_integ[kIntegClasses] = {};
   uint32_t *d_splat_items = nullptr;
   uint32_t n_splat_items = 0;
   uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
@@ -53,5 +83,6 @@ struct BatchPlan {
 };
 
 int batch_record(BatchPlan &P, hipStream_t s);
+int batch_occupancy(BatchPlan &P);
 
 }  // namespace gg

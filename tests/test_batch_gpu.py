@@ -102,3 +102,21 @@ def test_batch_mixed_items_carry_and_mask():
     torch.cuda.synchronize()
     _check(base, refs)
     plan.close()
+
+
+@pytest.mark.parametrize("vec", [8, 2])
+def test_batch_bins_per_thread(vec):
+    """Other fusion specialisations (bins per thread) in the batch: still the
+    plain results, which do not depend on that choice either."""
+    items = _items(n=8)
+    refs = [_plain(it) for it in items]
+    lib = gg._lib.lib()
+    gg._lib.check(lib.gg_set_volume_vector(vec))
+    try:
+        plan = gg.BatchPlan(items)
+        plan.launch()
+        torch.cuda.synchronize()
+        _check(items, refs)
+        plan.close()
+    finally:
+        lib.gg_set_volume_vector(0)
