@@ -164,9 +164,10 @@ def extract(F, W, tsdf, prec=32):
     return depth, b
 
 
-def splat(src, depth, rgb, tgt, sp, prec=32):
+def splat(src, depth, rgb, tgt, sp, mask=None, prec=32):
     """Per-view splat outputs: win_idx (K,Ht,Wt) int32, depth, rgb (K,3,Ht,Wt),
-    alpha, tape (K,3,Ht,Wt)."""
+    alpha, tape (K,3,Ht,Wt); with ``mask`` (K,Hs,Ws) also the splatted masks
+    (K,Ht,Wt) and their maximum over the views (Ht,Wt)."""
     rt = _rt(prec)
     K = len(src)
     Ht, Wt = tgt.height, tgt.width
@@ -177,12 +178,51 @@ def splat(src, depth, rgb, tgt, sp, prec=32):
     tape = np.zeros((K, 3, Ht, Wt), rt)
     d = _f32(depth)
     c = np.ascontiguousarray(rgb, np.uint8)
+    m = None if mask is None else _f32(mask)
+    om = None if mask is None else np.zeros((K, Ht, Wt), rt)
+    omax = None if mask is None else np.zeros((Ht, Wt), rt)
     tc = cam(tgt)
-    rc = lib(prec).orc_splat(cams(src), K, _p(d), _p(c), C.byref(tc), C.byref(splat_params(sp)),
-                             _p(win), _p(od), _p(orgb), _p(oa), _p(tape))
+    rc = lib(prec).orc_splat_masked(cams(src), K, _p(d), _p(c), C.byref(tc),
+                                    C.byref(splat_params(sp)), _p(win), _p(od), _p(orgb), _p(oa),
+                                    _p(tape), _p(m), _p(om), _p(omax))
     if rc != 0:
         raise RuntimeError(f"orc_splat failed: {rc}")
-    return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=tape)
+    out = dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=tape)
+    if mask is not None:
+        out["mask"] = om
+        out["mask_max"] = omax
+    return out
+
+
+def difference_mask(rgb, rgb_prev, factor=4, beta=0.6, lambda_t=0.7, prec=32):
+    """Soft difference masks (Eq. 1) of (H,W,3) or (K,H,W,3) uint8 frames."""
+    a = np.ascontiguousarray(rgb, np.uint8)
+    b = np.ascontiguousarray(rgb_prev, np.uint8)
+    if a.shape != b.shape or a.shape[-1] != 3:
+        raise ValueError("rgb and rgb_prev must be (..., H, W, 3) of one shape")
+    H, W = a.shape[-3], a.shape[-2]
+    fa = a.reshape(-1, H, W, 3)
+    fb = b.reshape(-1, H, W, 3)
+    out = np.zeros((fa.shape[0], H, W), _rt(prec))
+    for k in range(fa.shape[0]):
+        rc = lib(prec).orc_difference_mask(_p(fa[k]), _p(fb[k]), W, H, int(factor),
+                                           C.c_float(beta), C.c_float(lambda_t), _p(out[k]))
+        if rc != 0:
+            raise RuntimeError(f"orc_difference_mask failed: {rc}")
+    return out.reshape(a.shape[:-1])
+
+
+def temporal_filter(depth, mask, prev=None, prec=32):
+    """Temporally filtered depth (Eq. 2); ``prev`` None on the first frame."""
+    rt = _rt(prec)
+    d = _f32(depth)
+    m = np.ascontiguousarray(mask, rt)
+    if m.shape != d.shape:
+        raise ValueError("mask and depth must have one shape")
+    pv = None if prev is None else np.ascontiguousarray(prev, rt)
+    out = np.zeros(d.shape, rt)
+    lib(prec).orc_temporal_filter(_p(d), _p(m), _p(pv), C.c_size_t(d.size), _p(out))
+    return out
 
 
 def splat_backward(src, depth, rgb, tgt, sp, g_rgb, g_depth, g_alpha, prec=32):

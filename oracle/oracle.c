@@ -22,7 +22,12 @@
  *                       weight of Suppl. A.2 carried per voxel.
  *   orc_extract      -- the sign change along the ray of Suppl. A.1.
  *   orc_splat        -- forward rendering of per-pixel Gaussians of §3.1 and
- *                       Suppl. A.3 as a z-buffered splat.
+ *                       Suppl. A.3 as a z-buffered splat; orc_splat_masked
+ *                       also carries a per-pixel scalar (the difference
+ *                       mask) and its maximum over the views (Suppl. A.2).
+ *   orc_difference_mask -- the soft colour-difference mask of Eq. 1 at
+ *                       quarter resolution, max-pooled and upsampled (§3.2).
+ *   orc_temporal_filter -- the temporally filtered depth of Eq. 2 (§3.2).
  *   *_backward       -- the adjoints of the above with respect to input depth
  *                       and colour.
  *
@@ -408,9 +413,15 @@ static uint32_t f32_bits(float f) {
   return u;
 }
 
-int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
-              const orc_camera *tgt, const orc_splat_params *sp, int32_t *win_idx,
-              real *out_depth, real *out_rgb, real *out_alpha, real *tape) {
+/* mask (nullable, K x Hs x Ws): a per-source-pixel scalar blended over the
+ * band like one colour channel, sum G m / sum G, into out_mask (nullable,
+ * K x Ht x Wt; 0 where no splat covers); out_mask_max (nullable, Ht x Wt)
+ * is its maximum over the K views (Suppl. A.2: the channel-wise maximum of
+ * the splatted difference masks; reading: 0 where no view covers). */
+int orc_splat_masked(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
+                     const orc_camera *tgt, const orc_splat_params *sp, int32_t *win_idx,
+                     real *out_depth, real *out_rgb, real *out_alpha, real *tape,
+                     const float *mask, real *out_mask, real *out_mask_max) {
   const int Ws = src[0].width, Hs = src[0].height, Wt = tgt->width, Ht = tgt->height;
   const size_t ns = (size_t)Ws * Hs, nt = (size_t)Wt * Ht;
   const real rmax2 = (real)sp->r_max_px * (real)sp->r_max_px;
@@ -419,7 +430,10 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
   real *nrm = (real *)malloc(sizeof(real) * nt), *prod = (real *)malloc(sizeof(real) * nt);
   real *lsum = (real *)malloc(sizeof(real) * nt), *ones = (real *)malloc(sizeof(real) * nt);
   real *zwin = (real *)malloc(sizeof(real) * nt);
-  if (!zbuf || !nrm || !prod || !lsum || !ones || !zwin) return -2;
+  real *msum = (real *)malloc(sizeof(real) * nt);
+  if (!zbuf || !nrm || !prod || !lsum || !ones || !zwin || !msum) return -2;
+  if (out_mask_max)
+    for (size_t p = 0; p < nt; ++p) out_mask_max[p] = 0;
   for (int k = 0; k < K; ++k) {
     real H[9], c[3];
     relproj(&src[k], tgt, H, c);
@@ -433,6 +447,7 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
       prod[p] = 1;
       lsum[p] = 0;
       ones[p] = 0;
+      msum[p] = 0;
       prgb[p] = prgb[nt + p] = prgb[2 * nt + p] = 0;
     }
     /* pass 1: z-test */
@@ -477,6 +492,7 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
             nrm[p] = nrm[p] + G;
             for (int ch = 0; ch < 3; ++ch)
               prgb[ch * nt + p] = prgb[ch * nt + p] + G * ((real)ck[q * 3 + ch] / (real)255);
+            if (mask) msum[p] = msum[p] + G * (real)mask[ns * k + q];
             prod[p] = prod[p] * ((real)1 - G);
             if (G < (real)1)
               lsum[p] = lsum[p] + RLOG((real)1 - G);
@@ -496,6 +512,11 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
         for (int ch = 0; ch < 3; ++ch) prgb[ch * nt + p] = prgb[ch * nt + p] / nrm[p];
         out_alpha[o] = (real)1 - prod[p];
       }
+      if (mask) {
+        const real m = zbuf[p] == UINT64_MAX ? (real)0 : msum[p] / nrm[p];
+        if (out_mask) out_mask[o] = m;
+        if (out_mask_max && m > out_mask_max[p]) out_mask_max[p] = m;
+      }
       if (tape) {
         tape[nt * 3 * k + p] = nrm[p];
         tape[nt * 3 * k + nt + p] = lsum[p];
@@ -509,7 +530,110 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
   free(lsum);
   free(ones);
   free(zwin);
+  free(msum);
   return 0;
+}
+
+int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
+              const orc_camera *tgt, const orc_splat_params *sp, int32_t *win_idx,
+              real *out_depth, real *out_rgb, real *out_alpha, real *tape) {
+  return orc_splat_masked(src, K, depth, rgb, tgt, sp, win_idx, out_depth, out_rgb, out_alpha,
+                          tape, NULL, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------
+ * Soft difference mask of one view between consecutive frames (Eq. 1, §3.2):
+ * M = min(|I^t - I^{t-1}| / lambda_t + beta, 1), computed at quarter
+ * resolution, max-pooled over 3 x 3 and upsampled bilinearly to full size.
+ *
+ * Readings: "quarter resolution" is a factor x factor box (factor = 4)
+ * mean of the colours c = u8 / 255, the box clipped at the image border
+ * (Wq = ceil(W / factor)); |I^t - I^{t-1}| of an RGB image is the mean over
+ * its three channels of the absolute difference; the max-pool window is
+ * clipped at the border; upsampling samples the low-resolution image at the
+ * full-resolution pixel centre, x = (i + 1/2) / factor - 1/2, clamped to
+ * [0, Wq - 1] (likewise y).
+ * Operation order: per box the channel sums of u8 are exact integers, so
+ * dI = (sum over channels of |S^t - S^{t-1}|) / (765 n) is one rounding
+ * (n pixels in the box); then t = dI / lambda_t, M = min(t + beta, 1).
+ * Bilinear: x0 = floor(x), x1 = min(x0 + 1, Wq - 1), fx = x - x0;
+ * top = m00 + fx (m10 - m00), bottom = m01 + fx (m11 - m01),
+ * M = top + fy (bottom - top), no fused multiply-adds.
+ * rgb, rgb_prev: H x W x 3 u8.  mask: H x W.
+ * ---------------------------------------------------------------------- */
+int orc_difference_mask(const uint8_t *rgb, const uint8_t *rgb_prev, int W, int H, int factor,
+                        float beta, float lambda_t, real *mask) {
+  const int Wq = (W + factor - 1) / factor, Hq = (H + factor - 1) / factor;
+  real *low = (real *)malloc(sizeof(real) * Wq * Hq);
+  real *pool = (real *)malloc(sizeof(real) * Wq * Hq);
+  if (!low || !pool) return -2;
+  for (int b = 0; b < Hq; ++b)
+    for (int a = 0; a < Wq; ++a) {
+      long st[3] = {0, 0, 0}, sp[3] = {0, 0, 0};
+      int n = 0;
+      for (int j = b * factor; j < (b + 1) * factor && j < H; ++j)
+        for (int i = a * factor; i < (a + 1) * factor && i < W; ++i) {
+          for (int ch = 0; ch < 3; ++ch) {
+            st[ch] += rgb[((size_t)j * W + i) * 3 + ch];
+            sp[ch] += rgb_prev[((size_t)j * W + i) * 3 + ch];
+          }
+          ++n;
+        }
+      const long d = labs(st[0] - sp[0]) + labs(st[1] - sp[1]) + labs(st[2] - sp[2]);
+      const real dI = (real)d / (real)(765 * n);
+      const real t = dI / (real)lambda_t;
+      low[(size_t)b * Wq + a] = RMIN(t + (real)beta, (real)1);
+    }
+  for (int b = 0; b < Hq; ++b)
+    for (int a = 0; a < Wq; ++a) {
+      real m = low[(size_t)b * Wq + a];
+      for (int bb = b - 1; bb <= b + 1; ++bb)
+        for (int aa = a - 1; aa <= a + 1; ++aa)
+          if (aa >= 0 && aa < Wq && bb >= 0 && bb < Hq && low[(size_t)bb * Wq + aa] > m)
+            m = low[(size_t)bb * Wq + aa];
+      pool[(size_t)b * Wq + a] = m;
+    }
+  for (int j = 0; j < H; ++j)
+    for (int i = 0; i < W; ++i) {
+      real x = ((real)i + (real)0.5) / (real)factor - (real)0.5;
+      real y = ((real)j + (real)0.5) / (real)factor - (real)0.5;
+      if (x < 0) x = 0;
+      if (y < 0) y = 0;
+      if (x > (real)(Wq - 1)) x = (real)(Wq - 1);
+      if (y > (real)(Hq - 1)) y = (real)(Hq - 1);
+      const int x0 = (int)floor((double)x), y0 = (int)floor((double)y);
+      const int x1 = x0 + 1 < Wq ? x0 + 1 : Wq - 1, y1 = y0 + 1 < Hq ? y0 + 1 : Hq - 1;
+      const real fx = x - (real)x0, fy = y - (real)y0;
+      const real m00 = pool[(size_t)y0 * Wq + x0], m10 = pool[(size_t)y0 * Wq + x1];
+      const real m01 = pool[(size_t)y1 * Wq + x0], m11 = pool[(size_t)y1 * Wq + x1];
+      const real top = m00 + fx * (m10 - m00);
+      const real bot = m01 + fx * (m11 - m01);
+      mask[(size_t)j * W + i] = top + fy * (bot - top);
+    }
+  free(low);
+  free(pool);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Temporally filtered depth (Eq. 2, §3.2): Dd^t = M D^t + (1 - M) Dd^{t-1},
+ * evaluated as fma(M, D^t, (1 - M) Dd^{t-1}).  Readings: a hole in D^t
+ * stays a hole (0, so the fusion drops it); where there is no usable
+ * previous filtered depth (first frame: prev NULL, or a hole) Dd^t = D^t.
+ * ---------------------------------------------------------------------- */
+void orc_temporal_filter(const float *depth, const real *mask, const real *prev, size_t n,
+                         real *out) {
+  for (size_t p = 0; p < n; ++p) {
+    const float D = depth[p];
+    if (!depth_ok(D)) {
+      out[p] = 0;
+    } else if (!prev || !(prev[p] > 0 && prev[p] < INFINITY)) {
+      out[p] = (real)D;
+    } else {
+      const real a = (real)1 - mask[p];
+      out[p] = RFMA(mask[p], (real)D, a * prev[p]);
+    }
+  }
 }
 
 /* ------------------------------------------------------------------------

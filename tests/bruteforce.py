@@ -123,9 +123,10 @@ def extract(F, W, prm):
     return depth, b
 
 
-def zbuffer(src, depth, rgb, tgt, sp, margin=1e-6):
+def zbuffer(src, depth, rgb, tgt, sp, margin=1e-6, mask=None):
     """O(N^2) splat: every source pixel against every target pixel.
-    Returns win (K, Ht, Wt), depth, rgb (K,3,Ht,Wt), alpha, ambiguous mask."""
+    Returns win (K, Ht, Wt), depth, rgb (K,3,Ht,Wt), alpha, ambiguous mask;
+    with ``mask`` (K, Hs, Ws) also the band blend of the mask (K, Ht, Wt)."""
     K = len(src)
     Ht, Wt = tgt.height, tgt.width
     bj, bi = np.meshgrid(np.arange(Ht), np.arange(Wt), indexing="ij")
@@ -134,6 +135,7 @@ def zbuffer(src, depth, rgb, tgt, sp, margin=1e-6):
     zw = np.zeros((K, Ht * Wt))
     col = np.zeros((K, 3, Ht * Wt))
     alpha = np.zeros((K, Ht * Wt))
+    msk = np.zeros((K, Ht * Wt))
     amb = np.zeros((K, Ht * Wt), bool)
     for k in range(K):
         Hs, Ws = depth[k].shape
@@ -175,7 +177,37 @@ def zbuffer(src, depth, rgb, tgt, sp, margin=1e-6):
         for ch in range(3):
             col[k, ch] = np.where(has, (G * c[None, :, ch]).sum(1) / np.where(has, n, 1), 0)
         alpha[k] = np.where(has, 1 - np.prod(np.where(band, 1 - G, 1.0), axis=1), 0)
+        if mask is not None:
+            m = np.asarray(mask[k], np.float64).ravel()
+            msk[k] = np.where(has, (G * m[None]).sum(1) / np.where(has, n, 1), 0)
         del best
     sh = (K, Ht, Wt)
-    return win.reshape(sh), zw.reshape(sh), col.reshape(K, 3, Ht, Wt), alpha.reshape(sh), \
-        amb.reshape(sh)
+    out = (win.reshape(sh), zw.reshape(sh), col.reshape(K, 3, Ht, Wt), alpha.reshape(sh),
+           amb.reshape(sh))
+    return out if mask is None else out + (msk.reshape(sh),)
+
+
+def difference_mask(rgb, rgb_prev, factor, beta, lam):
+    """Eq. 1 mask of one (H, W, 3) frame pair in FP64 with array operations:
+    box means by reduceat, the 3x3 max-pool as a maximum of nine shifted
+    copies (-inf padding), bilinear upsampling by index arrays."""
+    a = np.asarray(rgb, np.float64) / 255.0
+    b = np.asarray(rgb_prev, np.float64) / 255.0
+    H, W = a.shape[:2]
+    rs, cs = np.arange(0, H, factor), np.arange(0, W, factor)
+    cnt = np.add.reduceat(np.add.reduceat(np.ones((H, W)), rs, 0), cs, 1)
+    ma = np.add.reduceat(np.add.reduceat(a, rs, 0), cs, 1) / cnt[..., None]
+    mb = np.add.reduceat(np.add.reduceat(b, rs, 0), cs, 1) / cnt[..., None]
+    low = np.minimum(np.abs(ma - mb).mean(-1) / lam + beta, 1.0)
+    Hq, Wq = low.shape
+    pad = np.pad(low, 1, constant_values=-np.inf)
+    pool = np.max([pad[1 + dy:1 + dy + Hq, 1 + dx:1 + dx + Wq]
+                   for dy in (-1, 0, 1) for dx in (-1, 0, 1)], axis=0)
+    x = np.clip((np.arange(W) + 0.5) / factor - 0.5, 0, Wq - 1)
+    y = np.clip((np.arange(H) + 0.5) / factor - 0.5, 0, Hq - 1)
+    x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
+    x1, y1 = np.minimum(x0 + 1, Wq - 1), np.minimum(y0 + 1, Hq - 1)
+    fx, fy = (x - x0)[None, :], (y - y0)[:, None]
+    top = pool[y0][:, x0] * (1 - fx) + pool[y0][:, x1] * fx
+    bot = pool[y1][:, x0] * (1 - fx) + pool[y1][:, x1] * fx
+    return top * (1 - fy) + bot * fy

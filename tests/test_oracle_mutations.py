@@ -15,6 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # (name, original text, mutated text, pin files expected to catch it)
 PINS = "tests/test_oracle_pins.py"
 GRADS = "tests/test_oracle_gradients.py"
+TEMPORAL = "tests/test_oracle_temporal.py"
 MUTANTS = [
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
@@ -54,6 +55,25 @@ MUTANTS = [
     ("grad_neighbour_term", "g_depth_in[ns * k + n] -= gnu * (real)2 * dd;", "", GRADS),
     ("grad_alpha_term", "dLdG += g_alpha[o] * others;", "", GRADS),
     ("grad_footprint_term", "d2 * dsdD / (sig * g.s2)", "0", GRADS),
+    ("mask_no_beta", "RMIN(t + (real)beta, (real)1)", "RMIN(t, (real)1)", TEMPORAL),
+    ("mask_lambda_multiplies", "const real t = dI / (real)lambda_t;",
+     "const real t = dI * (real)lambda_t;", TEMPORAL),
+    ("mask_unclamped", "RMIN(t + (real)beta, (real)1)", "(t + (real)beta)", TEMPORAL),
+    ("mask_no_pool", "pool[(size_t)b * Wq + a] = m;",
+     "pool[(size_t)b * Wq + a] = low[(size_t)b * Wq + a];", TEMPORAL),
+    ("mask_corner_sampling", "real x = ((real)i + (real)0.5) / (real)factor - (real)0.5;",
+     "real x = (real)i / (real)factor;", TEMPORAL),
+    ("mask_weights_swapped", "const real top = m00 + fx * (m10 - m00);",
+     "const real top = m00 + fy * (m10 - m00);", TEMPORAL),
+    ("mask_box_count", "const real dI = (real)d / (real)(765 * n);",
+     "const real dI = (real)d / (real)(765 * factor * factor);", TEMPORAL),
+    ("filter_weights_swapped", "out[p] = RFMA(mask[p], (real)D, a * prev[p]);",
+     "out[p] = RFMA(a, (real)D, mask[p] * prev[p]);", TEMPORAL),
+    ("filter_hole_kept", "    if (!depth_ok(D)) {\n      out[p] = 0;",
+     "    if (!depth_ok(D) && 0) {\n      out[p] = 0;", TEMPORAL),
+    ("mask_splat_unnormalised", "msum[p] / nrm[p];", "msum[p];", TEMPORAL),
+    ("mask_max_not_max", "if (out_mask_max && m > out_mask_max[p]) out_mask_max[p] = m;",
+     "if (out_mask_max) out_mask_max[p] = m;", TEMPORAL),
 ]
 
 
