@@ -36,20 +36,48 @@ __global__ void batch_bins_kernel(const BatchItem *__restrict__ items) {
   }
 }
 
-// Dynamic work distribution in chunks: each workgroup takes the next
-// `chunk` consecutive entries of the phase's list from a counter the graph
-// zeroes first.  Entries differ in cost by orders of magnitude (items differ
-// in size, view count and bins), so a static split leaves long tails; one
-// atomic per entry, on the other hand, serialises on the counter.  The host
-// sizes chunks to about eight per workgroup.  Which workgroup runs an entry
-// never changes its result.
-__device__ __forceinline__ uint32_t next_chunk(uint32_t *ctr, uint32_t chunk, uint32_t *slot) {
-  __syncthreads();  // the previous chunk is done with the slot
-  if (threadIdx.x == 0) *slot = atomicAdd(ctr, chunk);
-  __syncthreads();
-  // uniform across the workgroup: the entries' descriptors then load
-  // through the scalar unit into SGPRs instead of once per lane
-  return __builtin_amdgcn_readfirstlane(*slot);
+// Dynamic work distribution in chunks, XCD-aware.  Entries differ in cost by
+// orders of magnitude (items differ in size, view count and bins), so a
+// static split leaves long tails; one atomic per entry, on the other hand,
+// serialises on the counter, so workgroups take chunks of `chunk`
+// consecutive entries (the host sizes them to about eight per workgroup).
+// Workgroups are dispatched round-robin over the 8 XCDs (blockIdx & 7 is
+// the XCD, as in xcd_tile), and consecutive entries of a list are
+// neighbouring tiles of one item that share source lines: each XCD first
+// drains its own contiguous eighth of the list, through its own counter,
+// so those lines stay in its L2, then helps the other XCDs.  Which
+// workgroup runs an entry never changes its result.
+struct WorkCursor {
+  uint32_t part;  // the part (of kXcds) being drained
+  uint32_t left;  // parts not yet found empty
+};
+
+__device__ __forceinline__ uint32_t part_lo(uint32_t n, uint32_t p) {
+  return (uint32_t)(((uint64_t)n * p) / kXcds);
+}
+
+// First entry of the next chunk this workgroup takes, and its end; false
+// when every part is drained.  The counters (kXcds per phase) start at 0.
+__device__ __forceinline__ bool next_chunk(uint32_t *ctr, uint32_t n, uint32_t chunk,
+                                           WorkCursor &c, uint32_t *slot, uint32_t &w0,
+                                           uint32_t &w1) {
+  while (c.left) {
+    const uint32_t lo = part_lo(n, c.part), hi = part_lo(n, c.part + 1);
+    __syncthreads();  // the previous chunk is done with the slot
+    if (threadIdx.x == 0) *slot = gatomic_add(&ctr[c.part], chunk);
+    __syncthreads();
+    // uniform across the workgroup: the entries' descriptors then load
+    // through the scalar unit into SGPRs instead of once per lane
+    const uint32_t got = __builtin_amdgcn_readfirstlane(*slot);
+    if (got < hi - lo) {
+      w0 = lo + got;
+      w1 = hi - w0 < chunk ? hi : w0 + chunk;
+      return true;
+    }
+    c.part = (c.part + 1) % kXcds;
+    --c.left;
+  }
+  return false;
 }
 
 // Runs body(w) for every entry w < n this workgroup takes.
@@ -57,10 +85,10 @@ template <typename Body>
 __device__ __forceinline__ void for_each_entry(uint32_t n, uint32_t chunk, uint32_t *ctr,
                                                Body &&body) {
   __shared__ uint32_t slot;
-  for (uint32_t w0; (w0 = next_chunk(ctr, chunk, &slot)) < n;) {
-    const uint32_t w1 = n - w0 < chunk ? n : w0 + chunk;
+  WorkCursor c{blockIdx.x % kXcds, kXcds};
+  uint32_t w0, w1;
+  while (next_chunk(ctr, n, chunk, c, &slot, w0, w1))
     for (uint32_t w = w0; w < w1; ++w) body(w);
-  }
 }
 
 __global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__restrict__ items,
@@ -123,7 +151,7 @@ static void launch_integ_class(const BatchPlan &P, uint32_t n, int grid, uint32_
                                size_t shm, hipStream_t s) {
   hipLaunchKernelGGL((batch_integrate_kernel<vec_of_class(C), views_of_class(C), exact_class(C)>),
                      dim3(grid), dim3(P.integ_threads), shm, s, P.d_items, P.d_integ[C], n, chunk,
-                     P.d_ctr + kLightCounters + C);
+                     P.d_ctr + (kLightCounters + C) * kXcds);
 }
 
 template <int C>
@@ -178,19 +206,19 @@ int batch_record(BatchPlan &P, hipStream_t s) {
   if (P.n_conf) {
     const int g = persistent_grid(P.n_conf, P.occ_conf, cus);
     hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
-                       chunk_of(P.n_conf, g), P.d_ctr + 0);
+                       chunk_of(P.n_conf, g), P.d_ctr + 0 * kXcds);
   }
   if (P.n_bin) {
     const int gb = persistent_grid(P.n_bin, P.occ_bin, cus);
     const int gr = persistent_grid(P.n_raster, P.occ_raster, cus);
     hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1);
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1 * kXcds);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
                        P.d_splat_items);
     hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2);
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2 * kXcds);
     hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, s, P.d_items, P.d_raster,
-                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3);
+                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3 * kXcds);
   }
   const size_t shm = sizeof(float) * 2 * P.integ_threads + sizeof(int) * P.integ_threads;
   for (int c = 0; c < kIntegClasses; ++c) {

@@ -15,7 +15,8 @@ constexpr int kConfTileFloats = kConfLH * kConfLW;
 constexpr int kVecClasses = 4, kViewClasses = 8;
 constexpr int kIntegClasses = kVecClasses * kViewClasses;
 constexpr int kLightCounters = 4;  // confidence, bin count, bin fill, raster
-constexpr int kBatchCounters = kLightCounters + kIntegClasses;
+constexpr int kXcds = 8;           // each phase keeps one counter per XCD
+constexpr int kBatchCounters = (kLightCounters + kIntegClasses) * kXcds;
 
 __host__ __device__ constexpr int vec_of_class(int c) { return 8 >> (c / kViewClasses); }
 __host__ __device__ constexpr int views_of_class(int c) {
@@ -77,7 +78,8 @@ struct BatchPlan {
   uint32_t n_splat_items = 0;
   uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
   size_t zero_words = 0;
-  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters (zeroed per launch)
+  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters (zeroed per launch):
+                                 // kXcds per phase
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
