@@ -187,6 +187,61 @@ def batched_speedup(gg, torch, dev, procs, tune=True):
             "batched_mpix_s": round(pixels / tb / 1e3, 1)}
 
 
+def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
+    """The paper's full temporal path on the video workload (§3.2, Suppl.
+    A.2): per frame the colour-difference masks of the K views and their
+    filtered depths, the splat carrying the masks (maximum over views), and
+    the fusion of the filtered depths with that maximum weighting the carried
+    volume; all inputs resident, state carried in place."""
+    nf, K, H, Wd = depth.shape[0], depth.shape[1], depth.shape[2], depth.shape[3]
+    D = tp.num_bins
+    F = torch.zeros((H, Wd, D), dtype=torch.float32, device=dev)
+    Wv = torch.zeros_like(F)
+    filt = depth[0].clone()
+    mask = torch.empty((K, H, Wd), device=dev)
+    wsm = torch.empty(gg.workspace_size(5, K, Wd, H, Wd, H, 4), dtype=torch.uint8, device=dev)
+    ws_s = torch.empty(gg.workspace_size(1, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8, device=dev)
+    ws_t = torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
+    so = dict(win_idx=torch.empty((K, H, Wd), dtype=torch.int32, device=dev),
+              depth=torch.empty((K, H, Wd), device=dev), rgb=torch.empty((K, 3, H, Wd), device=dev),
+              alpha=torch.empty((K, H, Wd), device=dev), tape=torch.empty((K, 3, H, Wd), device=dev),
+              mask=torch.empty((K, H, Wd), device=dev), mask_max=torch.empty((H, Wd), device=dev))
+
+    def step(i):
+        f, g = (i + 1) % nf, i % nf  # frame t and t - 1 (the sequence wraps)
+        gg.difference_masks(rgb[f], rgb[g], depth=depth[f], depth_prev=filt, mask=mask,
+                            filtered=filt, ws=wsm)
+        gg.splat_views(src, filt, rgb[f], tgt, sp, mask=mask, out=so, ws=ws_s)
+        gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv,
+                          mask=so["mask_max"], ws=ws_t)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    gg.timing_reset()
+    gg.timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(warmup + i)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gg.timing_enable(False)
+    kt = {}
+    for name in ("difference_masks", "splat_raster", "integrate"):
+        ms, n = gg.timing_read(name)
+        kt[name] = round(ms / max(steps, 1), 4)
+    ms = el * 1e3 / steps
+    # algorithmic bytes of the mask pass: two colour frames and the depth
+    # read, the mask and filtered depth written, the previous filtered depth
+    # read (per source pixel and view)
+    mb = K * H * Wd * (3 + 3 + 4 + 4 + 4 + 4)
+    return {"workload": "video ring K=4 1280x720 D=128, masks + filter + mask splat + fusion",
+            "ms_per_frame": round(ms, 4), "mpix_s": round(H * Wd / ms / 1e3, 2),
+            "kernel_ms_per_frame": kt,
+            "difference_masks_gb_s": round(mb / (kt["difference_masks"] * 1e-3) / 1e9, 1)
+            if kt["difference_masks"] > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +251,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-temporal", action="store_true")
     ap.add_argument("--procs", type=int, default=0,
                     help="input-generation worker processes (0: min(16, cores))")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -293,8 +349,13 @@ def main():
         r, tf, tb = bwd_fwd_ratio(gg, torch, dev)
         out["bwd_fwd"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3), "bwd_ms": round(tb, 3),
                           "workload": "differentiation 640x360 K=4 D=96"}
+    del F, Wv, sout
+    torch.cuda.empty_cache()
+    if not args.no_temporal:
+        out["temporal_path"] = temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb,
+                                             min(args.steps, 30), 3)
     if not args.no_batch:
-        del depth, rgb, F, Wv, ws_s, ws_t, sout
+        del depth, rgb, ws_s, ws_t
         torch.cuda.empty_cache()
         out["batched"] = batched_speedup(gg, torch, dev, procs)
     if not args.no_cpu_baseline:

@@ -30,7 +30,8 @@
  *   readable through gg_last_error() (thread-local).  Invalid arguments are
  *   detected before anything is enqueued.  Nothing throws across the ABI.
  * Aliasing: outputs never alias inputs, except F / W, which may alias
- *   F_prev / W_prev (in-place temporal update).
+ *   F_prev / W_prev (in-place temporal update), and depth_filtered, which
+ *   may alias depth_filtered_prev.
  * Determinism: every output is bitwise reproducible run to run; integer
  *   outputs (winner indices, bins) and the volume F / W are bitwise equal to
  *   the plain FP32 definition (no contraction, correctly rounded divide and
@@ -86,12 +87,20 @@ typedef struct gg_tsdf_params {
   float weight_cap;      /* eta of Suppl. A.2, cap on the carried weight, >= 0           */
 } gg_tsdf_params;
 
+/* Colour-difference masks between consecutive frames (Eq. 1, §3.2). */
+typedef struct gg_mask_params {
+  float beta;     /* offset of the mask (Eq. 1: 0.6), in [0, 1]                       */
+  float lambda_t; /* colour-change scale (Eq. 1: 0.7), > 0                            */
+  int32_t factor; /* the mask is formed at 1/factor resolution (§3.2: 4), 1 .. 16     */
+} gg_mask_params;
+
 /* Operations for gg_workspace_size(). */
 enum {
   GG_OP_SPLAT = 1,
   GG_OP_SPLAT_BACKWARD = 2,
   GG_OP_TSDF_INTEGRATE = 3,
-  GG_OP_TSDF_INTEGRATE_BACKWARD = 4
+  GG_OP_TSDF_INTEGRATE_BACKWARD = 4,
+  GG_OP_DIFFERENCE_MASKS = 5 /* src_w x src_h frames, num_bins = the mask factor  */
 };
 
 /* Bytes of workspace `op` needs for K source views of src_w x src_h pixels, a
@@ -133,6 +142,22 @@ int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8
                 float *out_depth, float *out_rgb, float *out_alpha, float *out_tape, void *ws,
                 size_t ws_bytes, void *stream);
 
+/* splat_views plus one per-pixel scalar of the source views (the
+ * difference masks of Eq. 1) carried to the target like a colour channel
+ * (Suppl. A.2): out_mask = sum G m / sum G over the band of each target
+ * pixel, 0 where no splat covers it, and out_mask_max its maximum over the
+ * K views (the channel-wise maximum that weights the temporal carry of
+ * tsdf_integrate).  mask float K x src_h x src_w; out_mask float
+ * K x tgt_h x tgt_w or NULL; out_mask_max float tgt_h x tgt_w or NULL (at
+ * least one of the two).  The other outputs are exactly those of
+ * splat_views; the workspace is splat_views'.  The mask sums use the same
+ * 64-bit fixed point as the colours. */
+int splat_views_masked(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                       const gg_camera *tgt, const gg_splat_params *prm, const float *mask,
+                       int32_t *win_idx, float *out_depth, float *out_rgb, float *out_alpha,
+                       float *out_tape, float *out_mask, float *out_mask_max, void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* Adjoint of splat_views with respect to source depth and colour, for the
  * loss L = <g_rgb, out_rgb> + <g_depth, out_depth> + <g_alpha, out_alpha>.
  * Coverage, band and winner are held fixed (piecewise differentiation).
@@ -148,6 +173,37 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
                          const float *out_tape, const float *g_rgb, const float *g_depth,
                          const float *g_alpha, float *g_depth_in, float *g_rgb_in, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * difference_masks -- soft colour-difference masks between consecutive frames
+ * of K views (Eq. 1, §3.2) and, optionally, the temporally filtered depth of
+ * Eq. 2.
+ *
+ * Per view, at 1/factor resolution: each low-resolution pixel is the
+ * factor x factor box of full-resolution pixels (clipped at the border,
+ * n pixels); with S the box's integer sums of each u8 channel,
+ *   dI = (|S_r - S_r'| + |S_g - S_g'| + |S_b - S_b'|) / (765 n)
+ * (the channel mean of |I - I'|, colours u8 / 255), M = min(dI / lambda_t +
+ * beta, 1); then the maximum over the 3 x 3 neighbourhood (clipped); then
+ * bilinear upsampling at the full-resolution pixel centres,
+ * x = (i + 0.5) / factor - 0.5 clamped to [0, W / factor rounded up - 1]
+ * (likewise y), top = m00 + fx (m10 - m00), bottom likewise, mask = top +
+ * fy (bottom - top).  Every step is FP32 in this order (no contraction).
+ * Filter (Eq. 2), where depth is given: filtered = fma(M, D, (1 - M) * prev);
+ * a hole in D gives 0; where prev is NULL (first frame) or a hole, D.
+ *
+ * rgb, rgb_prev  uint8 K x height x width x 3 (frames t and t - 1)
+ * prm [host].  mask float K x height x width (output).
+ * depth float K x height x width or NULL (no filtering); depth_filtered_prev
+ * float K x height x width or NULL; depth_filtered float K x height x width
+ * (required with depth; may alias depth_filtered_prev).
+ * ws: gg_workspace_size(GG_OP_DIFFERENCE_MASKS, K, width, height, width, height,
+ *   prm->factor, NULL).
+ * ------------------------------------------------------------------------- */
+int difference_masks(int32_t K, int32_t width, int32_t height, const uint8_t *rgb,
+                     const uint8_t *rgb_prev, const gg_mask_params *prm, float *mask,
+                     const float *depth, const float *depth_filtered_prev,
+                     float *depth_filtered, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * tsdf_integrate -- fuse K depth maps into the target's frustum volume

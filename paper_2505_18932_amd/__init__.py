@@ -1,15 +1,18 @@
 """MI355X (gfx950) geometry stage of online multi-view video synthesis
 (arXiv 2505.18932): z-buffered pixel-Gaussian splatting, frustum-volume TSDF
-fusion with a running temporal weight, zero-crossing extraction, adjoints and
-a batched path, as hand-written HIP kernels behind a C ABI (include/ggeom.h).
+fusion with a running temporal weight, zero-crossing extraction, colour-
+difference masks with the temporally filtered depth, adjoints and a batched
+path, as hand-written HIP kernels behind a C ABI (include/ggeom.h).
 """
 from . import _lib, autograd
-from .ops import (BatchPlan, camera, cameras, relative_projection, splat_params, splat_views,
+from .ops import (BatchPlan, camera, cameras, difference_masks, mask_params,
+                  relative_projection, splat_params, splat_views,
                   splat_views_backward, timing_enable, timing_read, timing_reset,
                   tsdf_extract_depth, tsdf_extract_depth_backward, tsdf_integrate,
                   tsdf_integrate_backward, tsdf_params, workspace_size)
 
-__all__ = ["BatchPlan", "camera", "cameras", "relative_projection", "splat_params", "splat_views",
+__all__ = ["BatchPlan", "camera", "cameras", "difference_masks", "mask_params",
+           "relative_projection", "splat_params", "splat_views",
            "splat_views_backward", "timing_enable", "timing_read", "timing_reset",
            "tsdf_extract_depth", "tsdf_extract_depth_backward", "tsdf_integrate",
            "tsdf_integrate_backward", "tsdf_params", "workspace_size", "_lib", "autograd"]

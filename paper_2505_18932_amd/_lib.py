@@ -21,6 +21,7 @@ GG_OP_SPLAT = 1
 GG_OP_SPLAT_BACKWARD = 2
 GG_OP_TSDF_INTEGRATE = 3
 GG_OP_TSDF_INTEGRATE_BACKWARD = 4
+GG_OP_DIFFERENCE_MASKS = 5
 
 
 class GGCamera(C.Structure):
@@ -39,6 +40,10 @@ class GGTsdfParams(C.Structure):
                 ("trunc", C.c_float), ("trunc_in_bins", C.c_int32),
                 ("conf_tau", C.c_float), ("conf_scale", C.c_float), ("conf_window", C.c_int32),
                 ("decay", C.c_float), ("weight_cap", C.c_float)]
+
+
+class GGMaskParams(C.Structure):
+    _fields_ = [("beta", C.c_float), ("lambda_t", C.c_float), ("factor", C.c_int32)]
 
 
 class GGBatchItem(C.Structure):
@@ -66,8 +71,12 @@ SZ = C.c_size_t
 SIGNATURES = {
     "gg_workspace_size": (SZ, [C.c_int, I32, I32, I32, I32, I32, I32, SPP]),
     "splat_views": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, SZ, P]),
+    "splat_views_masked": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, SZ,
+                                     P]),
     "splat_views_backward": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, P,
                                        SZ, P]),
+    "difference_masks": (C.c_int, [I32, I32, I32, P, P, C.POINTER(GGMaskParams), P, P, P, P, P,
+                                   SZ, P]),
     "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_extract_depth": (C.c_int, [CAM, TSP, P, P, P, P, P]),
     "tsdf_extract_depth_backward": (C.c_int, [CAM, TSP, P, P, P, P, P, P]),

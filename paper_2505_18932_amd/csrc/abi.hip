@@ -194,6 +194,13 @@ struct SplatLayout {
   size_t count, offset, cursor, list, total;
 };
 
+// Workspace of difference_masks: the low-resolution mask and its 3 x 3
+// maximum, K planes each.
+static size_t mask_ws_bytes(int32_t K, int32_t w, int32_t h, int32_t factor) {
+  const size_t wq = (size_t)((w + factor - 1) / factor), hq = (size_t)((h + factor - 1) / factor);
+  return 2 * up256(sizeof(float) * wq * hq * (size_t)K);
+}
+
 static SplatLayout splat_layout(int K, int sw, int sh, int tw, int th, const gg_splat_params *sp) {
   SplatLayout L{};
   L.ntx = (uint32_t)((tw + kTile - 1) / kTile);
@@ -322,6 +329,9 @@ size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_
     case GG_OP_TSDF_INTEGRATE_BACKWARD:
       if (num_bins < 2) return 0;
       return tsdf_layout(K, src_w, src_h, num_bins, true).total;
+    case GG_OP_DIFFERENCE_MASKS:  // num_bins carries gg_mask_params.factor
+      if (num_bins < 1 || num_bins > 16) return 0;
+      return mask_ws_bytes(K, src_w, src_h, num_bins);
     default:
       return 0;
   }
@@ -405,6 +415,76 @@ int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8
   a.out_alpha = out_alpha;
   a.out_tape = out_tape;
   return launch_splat_forward(a, (hipStream_t)stream);
+}
+
+int splat_views_masked(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                       const gg_camera *tgt, const gg_splat_params *prm, const float *mask,
+                       int32_t *win_idx, float *out_depth, float *out_rgb, float *out_alpha,
+                       float *out_tape, float *out_mask, float *out_mask_max, void *ws,
+                       size_t ws_bytes, void *stream) {
+  const char *W = "splat_views_masked";
+  if (int rc = check_sources(src, K, W)) return rc;
+  if (int rc = check_camera(tgt, W)) return rc;
+  if (int rc = check_splat(prm, W)) return rc;
+  if (!depth || !rgb || !mask || !win_idx || !out_depth || !out_rgb || !out_alpha)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", W);
+  if (!out_mask && !out_mask_max)
+    return fail(GG_ERR_INVALID, "%s: need out_mask or out_mask_max", W);
+  const int sw = src[0].width, sh = src[0].height;
+  const SplatLayout L = splat_layout(K, sw, sh, tgt->width, tgt->height, prm);
+  if ((size_t)K * sw * sh * splat_tiles_per_splat(prm->r_max_px) > 0xffffffffull)
+    return fail(GG_ERR_UNSUPPORTED, "%s: too many source pixels", W);
+  if (int rc = check_ws(ws, ws_bytes, L.total, W)) return rc;
+  SplatArgs a{};
+  make_splat_args(a, src, K, depth, rgb, *tgt, *prm, L, (char *)ws);
+  a.win_idx = win_idx;
+  a.out_depth = out_depth;
+  a.out_rgb = out_rgb;
+  a.out_alpha = out_alpha;
+  a.out_tape = out_tape;
+  a.mask_in = mask;
+  a.out_mask = out_mask;
+  a.out_mask_max = out_mask_max;
+  return launch_splat_forward(a, (hipStream_t)stream);
+}
+
+int difference_masks(int32_t K, int32_t width, int32_t height, const uint8_t *rgb,
+                     const uint8_t *rgb_prev, const gg_mask_params *prm, float *mask,
+                     const float *depth, const float *depth_filtered_prev,
+                     float *depth_filtered, void *ws, size_t ws_bytes, void *stream) {
+  const char *N = "difference_masks";
+  if (K < 1 || K > GG_MAX_VIEWS)
+    return fail(GG_ERR_INVALID, "%s: K = %d outside 1..%d", N, K, GG_MAX_VIEWS);
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GG_ERR_INVALID, "%s: size %dx%d outside 1..16384", N, width, height);
+  if (!prm) return fail(GG_ERR_INVALID, "%s: params NULL", N);
+  if (!(prm->beta >= 0.0f && prm->beta <= 1.0f) || !(prm->lambda_t > 0.0f) ||
+      !finite_f(prm->lambda_t) || prm->factor < 1 || prm->factor > 16)
+    return fail(GG_ERR_INVALID, "%s: need beta in [0, 1], lambda_t > 0, factor in 1..16", N);
+  if (!rgb || !rgb_prev || !mask) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  if ((depth == nullptr) != (depth_filtered == nullptr))
+    return fail(GG_ERR_INVALID, "%s: depth and depth_filtered go together", N);
+  if (depth_filtered_prev && !depth)
+    return fail(GG_ERR_INVALID, "%s: depth_filtered_prev needs depth", N);
+  if (int rc = check_ws(ws, ws_bytes, mask_ws_bytes(K, width, height, prm->factor), N)) return rc;
+  MaskArgs a{};
+  a.rgb = rgb;
+  a.rgb_prev = rgb_prev;
+  a.K = K;
+  a.W = width;
+  a.H = height;
+  a.factor = prm->factor;
+  a.Wq = (width + prm->factor - 1) / prm->factor;
+  a.Hq = (height + prm->factor - 1) / prm->factor;
+  a.low = (float *)ws;
+  a.pool = (float *)((char *)ws + up256(sizeof(float) * (size_t)a.Wq * a.Hq * K));
+  a.mask = mask;
+  a.depth = depth;
+  a.prev = depth_filtered_prev;
+  a.filtered = depth_filtered;
+  a.beta = prm->beta;
+  a.lambda_t = prm->lambda_t;
+  return launch_difference_masks(a, (hipStream_t)stream);
 }
 
 int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,

@@ -250,6 +250,10 @@ struct SplatArgs {
   uint32_t list_cap;
   int32_t *win_idx;
   float *out_depth, *out_rgb, *out_alpha, *out_tape;
+  // difference-mask channel (nullable)
+  const float *mask_in;   // K x Ns
+  float *out_mask;        // K x Nt
+  float *out_mask_max;    // Nt, zeroed by the launcher, maximum over views as float bits
   // backward
   const float *g_rgb, *g_depth, *g_alpha, *fw_rgb, *fw_depth, *fw_tape;
   const int32_t *fw_win;
@@ -257,6 +261,21 @@ struct SplatArgs {
 };
 
 uint32_t splat_tiles_per_splat(float r_max);
+
+// ---------------------------------------------------------------------------
+// difference masks and filtered depth (temporal.hip)
+
+struct MaskArgs {
+  const uint8_t *rgb, *rgb_prev;  // K x H x W x 3
+  float *low, *pool;              // K x Hq x Wq (workspace)
+  float *mask;                    // K x H x W
+  const float *depth, *prev;      // K x H x W; depth null: no filter; prev null: first frame
+  float *filtered;
+  int32_t K, W, H, Wq, Hq, factor;
+  float beta, lambda_t;
+};
+
+int launch_difference_masks(const MaskArgs &a, hipStream_t s);
 int launch_splat_forward(SplatArgs &a, hipStream_t s);
 int launch_splat_backward(const SplatArgs &a, hipStream_t s);
 

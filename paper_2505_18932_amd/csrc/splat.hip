@@ -73,6 +73,12 @@ int launch_splat_forward(SplatArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(splat_bin_kernel<true>, gsrc, dim3(256), 0, s, a);
     if (int rc = check_hip(hipGetLastError(), "splat_bin_kernel<fill>")) return rc;
   }
+  if (a.out_mask_max) {
+    KernelTimer t("splat_zero", s);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(min((a.nt + 255) / 256, 1024u)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t *>(a.out_mask_max), a.nt);
+    if (int rc = check_hip(hipGetLastError(), "zero_u32_kernel")) return rc;
+  }
   KernelTimer t("splat_raster", s);
   hipLaunchKernelGGL(splat_raster_kernel, dim3(a.ntiles, a.K), dim3(kTile * kTile), 0, s, a);
   return check_hip(hipGetLastError(), "splat_raster_kernel");

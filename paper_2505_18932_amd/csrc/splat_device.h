@@ -176,7 +176,7 @@ constexpr double kFixL = 4294967296.0;     // 2^32: sums of log(1 - G)
 struct RasterLds {
   unsigned long long zkey[kTile * kTile];
   unsigned long long sG[kTile * kTile], sR[kTile * kTile], sGr[kTile * kTile], sB[kTile * kTile],
-      sL[kTile * kTile];
+      sL[kTile * kTile], sM[kTile * kTile];
   uint32_t sOnes[kTile * kTile];
 };
 
@@ -189,6 +189,16 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
   const size_t p = (size_t)py * a.Wt + px;
   const size_t o = (size_t)k * a.nt + p;
   const unsigned long long wk = zkey[t];
+  if (a.mask_in) {
+    // the mask channel, like the colours; its maximum over the views as
+    // float bits (non-negative floats order as unsigned integers)
+    const float m = wk == ~0ull ? 0.0f : (float)((double)(long long)lds.sM[t] /
+                                                 (double)(long long)lds.sG[t]);
+    if (a.out_mask) gmem(a.out_mask)[o] = m;
+    if (a.out_mask_max)
+      __hip_atomic_fetch_max(reinterpret_cast<GG_GLOBAL uint32_t *>(gmem(a.out_mask_max) + p),
+                             __float_as_uint(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   GG_GLOBAL float *rgb = gmem(a.out_rgb + (size_t)k * 3 * a.nt);
   GG_GLOBAL int32_t *win = gmem(a.win_idx);
   GG_GLOBAL float *dep = gmem(a.out_depth), *alp = gmem(a.out_alpha);
@@ -224,13 +234,13 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
 __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t tile,
                                             RasterLds &lds) {
   unsigned long long *zkey = lds.zkey, *sG = lds.sG, *sR = lds.sR, *sGr = lds.sGr, *sB = lds.sB,
-                     *sL = lds.sL;
+                     *sL = lds.sL, *sM = lds.sM;
   uint32_t *sOnes = lds.sOnes;
   const int tyi = (int)(tile / (uint32_t)a.ntx), txi = (int)tile - tyi * a.ntx;
   const int ax0 = txi * kTile, by0 = tyi * kTile;
   const uint32_t t = threadIdx.x;
   zkey[t] = ~0ull;
-  sG[t] = sR[t] = sGr[t] = sB[t] = sL[t] = 0ull;
+  sG[t] = sR[t] = sGr[t] = sB[t] = sL[t] = sM[t] = 0ull;
   sOnes[t] = 0u;
   __syncthreads();
   const size_t ti = (size_t)k * a.ntiles + tile;
@@ -277,6 +287,10 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
         atomicAdd(&sR[lp], (unsigned long long)llrint((double)(G * c0) * kFixG));
         atomicAdd(&sGr[lp], (unsigned long long)llrint((double)(G * c1) * kFixG));
         atomicAdd(&sB[lp], (unsigned long long)llrint((double)(G * c2) * kFixG));
+        if (a.mask_in) {
+          const float m = gmem(a.mask_in)[(size_t)k * a.ns + q];
+          atomicAdd(&sM[lp], (unsigned long long)llrint((double)(G * m) * kFixG));
+        }
         if (G < 1.0f)
           atomicAdd(&sL[lp], (unsigned long long)llrint((double)logf(1.0f - G) * kFixL));
         else

@@ -48,6 +48,14 @@ def splat_params(p) -> L.GGSplatParams:
     return L.GGSplatParams(p["sigma_px"], p["band_rel"], p["z_min"], p["r_max_px"])
 
 
+def mask_params(p=None) -> L.GGMaskParams:
+    """Difference-mask parameters; defaults are the paper's (Eq. 1, §3.2)."""
+    if isinstance(p, L.GGMaskParams):
+        return p
+    p = p or {}
+    return L.GGMaskParams(p.get("beta", 0.6), p.get("lambda_t", 0.7), int(p.get("factor", 4)))
+
+
 def tsdf_params(p) -> L.GGTsdfParams:
     if isinstance(p, L.GGTsdfParams):
         return p
@@ -114,9 +122,11 @@ def _wh(cams_arr):
 
 
 def splat_views(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *, tape=True,
-                out=None, ws=None, stream=None):
+                mask=None, out=None, ws=None, stream=None):
     """Forward splat of K views into the target (see include/ggeom.h).
-    Returns dict(win_idx, depth, rgb, alpha, tape)."""
+    Returns dict(win_idx, depth, rgb, alpha, tape); with ``mask`` (K, H, W)
+    float32 (difference masks) also mask (K, Ht, Wt) and mask_max (Ht, Wt)
+    through splat_views_masked."""
     dev = _device(depth)
     sa, tg, sp = cameras(src), camera(tgt), splat_params(params)
     K = len(sa)
@@ -139,10 +149,49 @@ def splat_views(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *, tap
         else None
     need = workspace_size(L.GG_OP_SPLAT, K, sw, sh, tw, th, 2, sp)
     wsb, wsn = _ws(need, dev, ws)
-    L.check(L.lib().splat_views(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
-                                _ptr(win), _ptr(od), _ptr(orgb), _ptr(oa), _ptr(ot), _ptr(wsb),
-                                wsn, _stream(dev, stream)))
-    return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=ot)
+    if mask is None:
+        L.check(L.lib().splat_views(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
+                                    _ptr(win), _ptr(od), _ptr(orgb), _ptr(oa), _ptr(ot),
+                                    _ptr(wsb), wsn, _stream(dev, stream)))
+        return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=ot)
+    _need(mask, torch.float32, (K, sh, sw), "mask", dev)
+    om = buf("mask", (K, th, tw), torch.float32)
+    omax = buf("mask_max", (th, tw), torch.float32)
+    L.check(L.lib().splat_views_masked(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
+                                       _ptr(mask), _ptr(win), _ptr(od), _ptr(orgb), _ptr(oa),
+                                       _ptr(ot), _ptr(om), _ptr(omax), _ptr(wsb), wsn,
+                                       _stream(dev, stream)))
+    return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=ot, mask=om, mask_max=omax)
+
+
+def difference_masks(rgb: torch.Tensor, rgb_prev: torch.Tensor, params=None, *, depth=None,
+                     depth_prev=None, mask=None, filtered=None, ws=None, stream=None):
+    """Soft colour-difference masks (K, H, W) between frames t and t - 1
+    (Eq. 1) and, with ``depth``, the temporally filtered depth (Eq. 2;
+    ``depth_prev`` None on the first frame; ``filtered`` may be
+    ``depth_prev`` for an in-place update).  Returns (mask, filtered)."""
+    dev = _device(rgb)
+    mp = mask_params(params)
+    if rgb.dim() != 4 or rgb.shape[-1] != 3:
+        raise ValueError("rgb must be (K, H, W, 3)")
+    K, H, W = (int(v) for v in rgb.shape[:3])
+    _need(rgb, torch.uint8, (K, H, W, 3), "rgb", dev)
+    _need(rgb_prev, torch.uint8, (K, H, W, 3), "rgb_prev", dev)
+    om = torch.empty((K, H, W), dtype=torch.float32, device=dev) if mask is None else \
+        _need(mask, torch.float32, (K, H, W), "mask", dev)
+    of = None
+    if depth is not None:
+        _need(depth, torch.float32, (K, H, W), "depth", dev)
+        if depth_prev is not None:
+            _need(depth_prev, torch.float32, (K, H, W), "depth_prev", dev)
+        of = torch.empty((K, H, W), dtype=torch.float32, device=dev) if filtered is None else \
+            _need(filtered, torch.float32, (K, H, W), "filtered", dev)
+    need = workspace_size(L.GG_OP_DIFFERENCE_MASKS, K, W, H, W, H, mp.factor)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().difference_masks(K, W, H, _ptr(rgb), _ptr(rgb_prev), C.byref(mp), _ptr(om),
+                                     _ptr(depth), _ptr(depth_prev), _ptr(of), _ptr(wsb), wsn,
+                                     _stream(dev, stream)))
+    return om, of
 
 
 def splat_views_backward(src, depth, rgb, tgt, params, fwd, g_rgb=None, g_depth=None,

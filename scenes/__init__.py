@@ -530,6 +530,14 @@ def config2(seed=0):
                 splat=splat_params(), tsdf=tsdf_params(num_bins=128, trunc=4.0))
 
 
+def small_video(seed=0, width=96, height=64, k=3, bins=32):
+    """A small version of the video workload (ring rig, moving spheres) for
+    tests of the temporal path."""
+    seq = RingSequence(7, seed, 16, 1.0, width, height, k, MovingSpheres(seed, 5))
+    return dict(name="small video", seq=seq, src=seq.src, tgt=seq.tgt,
+                splat=splat_params(), tsdf=tsdf_params(num_bins=bins, trunc=4.0))
+
+
 def config5(seed=0):
     """Large streaming: K=8 of a 16-camera ring (radius 1.5 m), 1920x1080,
     D=256, truncation 4 bins, 20 moving spheres + 2 rotating boxes."""

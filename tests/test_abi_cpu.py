@@ -90,6 +90,52 @@ def test_splat_rejects_invalid_arguments():
     assert rc == L.GG_ERR_INVALID
 
 
+def test_masked_splat_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    sp = ops.splat_params(scenes.splat_params())
+
+    def call(mask=FAKE, om=FAKE, omax=FAKE, nws=1 << 40):
+        return lib.splat_views_masked(src, 2, FAKE, FAKE, C.byref(tgt), C.byref(sp), mask, FAKE,
+                                      FAKE, FAKE, FAKE, None, om, omax, FAKE, nws, None)
+    rc, msg = _err(call(mask=None))
+    assert rc == L.GG_ERR_INVALID and "NULL" in msg
+    rc, msg = _err(call(om=None, omax=None))
+    assert rc == L.GG_ERR_INVALID and "out_mask" in msg
+    assert call(nws=16) == L.GG_ERR_WORKSPACE
+
+
+def test_difference_masks_reject_invalid_arguments():
+    lib = L.lib()
+    good = ops.mask_params()
+
+    def call(K=2, w=64, h=48, prm=good, rgb=FAKE, prev=FAKE, m=FAKE, d=None, dp=None, f=None,
+             ws=FAKE, nws=1 << 40):
+        return lib.difference_masks(K, w, h, rgb, prev, C.byref(prm) if prm is not None else None,
+                                    m, d, dp, f, ws, nws, None)
+    assert call(K=0) == L.GG_ERR_INVALID
+    assert call(K=17) == L.GG_ERR_INVALID
+    assert call(w=0) == L.GG_ERR_INVALID
+    assert call(h=20000) == L.GG_ERR_INVALID
+    assert call(prm=None) == L.GG_ERR_INVALID
+    assert call(prm=ops.mask_params(dict(lambda_t=0.0))) == L.GG_ERR_INVALID
+    assert call(prm=ops.mask_params(dict(beta=1.5))) == L.GG_ERR_INVALID
+    assert call(prm=ops.mask_params(dict(factor=0))) == L.GG_ERR_INVALID
+    assert call(prm=ops.mask_params(dict(factor=17))) == L.GG_ERR_INVALID
+    assert call(rgb=None) == L.GG_ERR_INVALID
+    assert call(m=None) == L.GG_ERR_INVALID
+    assert call(d=FAKE) == L.GG_ERR_INVALID  # depth without an output
+    assert call(dp=FAKE) == L.GG_ERR_INVALID  # previous filtered depth without depth
+    rc, msg = _err(call(nws=16))
+    assert rc == L.GG_ERR_WORKSPACE and "need" in msg
+    assert call(ws=None) == L.GG_ERR_WORKSPACE
+    # workspace size: two K x ceil(H/f) x ceil(W/f) float planes, 256-aligned
+    n = ops.workspace_size(L.GG_OP_DIFFERENCE_MASKS, 2, 65, 47, 65, 47, 4)
+    per = 4 * 2 * 17 * 12
+    assert n == 2 * ((per + 255) // 256 * 256)
+    assert ops.workspace_size(L.GG_OP_DIFFERENCE_MASKS, 2, 65, 47, 65, 47, 0) == 0
+
+
 def test_tsdf_rejects_invalid_arguments():
     lib = L.lib()
     src, tgt = _cams()

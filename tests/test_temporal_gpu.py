@@ -1,0 +1,153 @@
+"""The temporal path on the GPU against the oracle: difference masks (Eq. 1)
+and the filtered depth (Eq. 2) bitwise, the mask splat and its maximum over
+the views (Suppl. A.2) to the forward float tolerance, and the fusion of the
+filtered depths with the splatted mask as its temporal weight."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2505_18932_amd as gg
+import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def close(got, ref, rtol=1e-5, what=""):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    floor = 1e-3 * max(np.abs(ref).max(), 1e-30)
+    bad = np.abs(got - ref) > rtol * np.maximum(np.abs(ref), floor)
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance"
+
+
+def _pair(seed, K, H, W):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, 256, (K, H, W, 3), dtype=np.uint8)
+    b = a.copy()
+    for k in range(K):
+        for _ in range(5):
+            y, x = rng.integers(0, H), rng.integers(0, W)
+            h, w = rng.integers(1, 12), rng.integers(1, 12)
+            b[k, y:y + h, x:x + w] = rng.integers(0, 256, (min(h, H - y), min(w, W - x), 3))
+    return b, a
+
+
+@pytest.mark.parametrize("K,H,W,factor", [(2, 23, 41, 4), (1, 5, 130, 3), (1, 1, 1, 4),
+                                          (3, 16, 16, 1), (2, 37, 53, 2), (4, 90, 160, 4),
+                                          (1, 7, 9, 16)])
+def test_difference_masks_bitwise(K, H, W, factor):
+    b, a = _pair(K * 100 + H, K, H, W)
+    m, _ = gg.difference_masks(torch.from_numpy(b).to(DEV), torch.from_numpy(a).to(DEV),
+                               dict(factor=factor))
+    torch.cuda.synchronize()
+    ref = oracle.difference_mask(b, a, factor=factor)
+    assert np.array_equal(bits(m.cpu().numpy()), bits(ref))
+
+
+def test_filtered_depth_bitwise_over_frames():
+    """Three frames of a small video: the filter starts from the first
+    frame's depth, then blends; in place on the second step."""
+    c = scenes.small_video(seed=1)
+    fr = [c["seq"].frame(t) for t in range(3)]
+    prev_gpu = None
+    prev_ref = None
+    state = None
+    for t in range(1, 3):
+        d, rgb = fr[t]
+        _, rgb0 = fr[t - 1]
+        dd = torch.from_numpy(d).to(DEV)
+        if t == 1:
+            m, f = gg.difference_masks(torch.from_numpy(rgb).to(DEV),
+                                       torch.from_numpy(rgb0).to(DEV), depth=dd)
+            state = f
+        else:
+            m, f = gg.difference_masks(torch.from_numpy(rgb).to(DEV),
+                                       torch.from_numpy(rgb0).to(DEV), depth=dd,
+                                       depth_prev=state, filtered=state)
+            assert f.data_ptr() == state.data_ptr()
+        torch.cuda.synchronize()
+        mref = oracle.difference_mask(rgb, rgb0)
+        fref = oracle.temporal_filter(d, mref, prev_ref)
+        assert np.array_equal(bits(m.cpu().numpy()), bits(mref)), t
+        assert np.array_equal(bits(f.cpu().numpy()), bits(fref)), t
+        prev_ref = fref
+        prev_gpu = f
+    assert prev_gpu is not None
+
+
+def test_filter_holes():
+    K, H, W = 2, 20, 24
+    b, a = _pair(7, K, H, W)
+    rng = np.random.default_rng(7)
+    d = rng.uniform(0.5, 5, (K, H, W)).astype(np.float32)
+    d[rng.random(d.shape) < 0.1] = 0
+    d[0, 0, :3] = np.inf
+    p = rng.uniform(0.5, 5, (K, H, W)).astype(np.float32)
+    p[rng.random(p.shape) < 0.1] = 0
+    m, f = gg.difference_masks(torch.from_numpy(b).to(DEV), torch.from_numpy(a).to(DEV),
+                               depth=torch.from_numpy(d).to(DEV),
+                               depth_prev=torch.from_numpy(p).to(DEV))
+    torch.cuda.synchronize()
+    mref = oracle.difference_mask(b, a)
+    fref = oracle.temporal_filter(d, mref, p)
+    assert np.array_equal(bits(f.cpu().numpy()), bits(fref))
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_mask_splat_matches_oracle(seed):
+    c = scenes.small_video(seed=seed, width=80, height=48, k=3)
+    d, rgb = c["seq"].frame(1)
+    _, rgb0 = c["seq"].frame(0)
+    mref = oracle.difference_mask(rgb, rgb0)
+    depth, crgb = torch.from_numpy(d).to(DEV), torch.from_numpy(rgb).to(DEV)
+    out = gg.splat_views(c["src"], depth, crgb, c["tgt"], c["splat"],
+                         mask=torch.from_numpy(mref).to(DEV))
+    plain = gg.splat_views(c["src"], depth, crgb, c["tgt"], c["splat"])
+    torch.cuda.synchronize()
+    for key in ("win_idx", "depth", "rgb", "alpha", "tape"):
+        assert torch.equal(out[key].view(torch.int32), plain[key].view(torch.int32)), key
+    ref = oracle.splat(c["src"], d, rgb, c["tgt"], c["splat"], mask=mref)
+    close(out["mask"].cpu().numpy(), ref["mask"], what="mask")
+    close(out["mask_max"].cpu().numpy(), ref["mask_max"], what="mask_max")
+    # the maximum is the maximum of the GPU's own per-view masks, exactly
+    assert torch.equal(out["mask_max"], out["mask"].max(0).values)
+
+
+def test_temporal_path_end_to_end():
+    """Frame t of a small video through the whole temporal path: masks and
+    filtered depth, the mask splat, then fusion of the filtered depths with
+    the splatted mask weighting the carried volume.  Given the GPU's splatted
+    mask the volume and extraction are bitwise the oracle's."""
+    c = scenes.small_video(seed=3, width=64, height=40, k=3, bins=24)
+    fr = [c["seq"].frame(t) for t in range(2)]
+    src, tgt, sp, tp = c["src"], c["tgt"], c["splat"], c["tsdf"]
+    d0, rgb0 = fr[0]
+    d1, rgb1 = fr[1]
+    F0, W0, _, _ = gg.tsdf_integrate(src, torch.from_numpy(d0).to(DEV), tgt, tp)
+    m, filt = gg.difference_masks(torch.from_numpy(rgb1).to(DEV), torch.from_numpy(rgb0).to(DEV),
+                                  depth=torch.from_numpy(d1).to(DEV),
+                                  depth_prev=torch.from_numpy(d0).to(DEV))
+    sp_out = gg.splat_views(src, filt, torch.from_numpy(rgb1).to(DEV), tgt, sp, mask=m)
+    F1, W1, dep, b = gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F0, W_prev=W0,
+                                       mask=sp_out["mask_max"])
+    torch.cuda.synchronize()
+    mref = oracle.difference_mask(rgb1, rgb0)
+    fref = oracle.temporal_filter(d1, mref, d0.astype(np.float32))
+    assert np.array_equal(bits(filt.cpu().numpy()), bits(fref))
+    Fr0, Wr0 = oracle.integrate(src, d0, tgt, tp)
+    Fr1, Wr1 = oracle.integrate(src, fref, tgt, tp, mask=sp_out["mask_max"].cpu().numpy(),
+                                F_prev=Fr0, W_prev=Wr0)
+    D = int(tp["num_bins"])
+    assert np.array_equal(bits(F1.cpu().numpy().reshape(-1, D)), bits(Fr1))
+    assert np.array_equal(bits(W1.cpu().numpy().reshape(-1, D)), bits(Wr1))
+    dr, br = oracle.extract(Fr1, Wr1, tp)
+    assert np.array_equal(b.cpu().numpy().ravel(), br)
+    # the mask did weight the carry: somewhere it is below one and above beta
+    mm = sp_out["mask_max"].cpu().numpy()
+    assert (mm > 0.6).any() and (mm < 1.0).any()
