@@ -69,15 +69,16 @@ def recorded_traffic():
     return float(b.group(1))
 
 
-def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=4):
+def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
     """The CPU oracle (plain C, OpenMP) on the same workload: whole frames
-    (splat + fusion with carry + extraction) until the time budget is used."""
+    (splat + fusion with carry + extraction) in sequence until the time
+    budget is used (a bounded sample of the sequence)."""
     import oracle
 
     t0 = time.perf_counter()
     F = W = None
     frames = 0
-    while frames < max_frames:
+    while frames < min(max_frames, len(depth)):
         oracle.splat(c["src"], depth[frames], rgb[frames], c["tgt"], c["splat"])
         F, W = oracle.integrate(c["src"], depth[frames], c["tgt"], c["tsdf"], F_prev=F, W_prev=W)
         oracle.extract(F, W, c["tsdf"])
