@@ -152,6 +152,28 @@ def integrate(src, depth, tgt, tsdf, mask=None, F_prev=None, W_prev=None, pixels
     return F, W
 
 
+def raymarch(src, depth, tgt, tsdf, dprev=None, acc=None, mask=None, prec=32):
+    """Volume-free march of every target ray: (depth, acc_next, samples),
+    each (Ht, Wt); ``dprev`` / ``acc`` (the previous output depth and its
+    accumulated weight) switch on the temporal term, ``mask`` weights it."""
+    rt = _rt(prec)
+    K = len(src)
+    Ht, Wt = tgt.height, tgt.width
+    d = _f32(depth)
+    od = np.zeros((Ht, Wt), rt)
+    oa = np.zeros((Ht, Wt), rt)
+    st = np.zeros((Ht, Wt), np.int32)
+    dp = None if dprev is None else np.ascontiguousarray(dprev, rt)
+    ac = None if acc is None else np.ascontiguousarray(acc, rt)
+    m = None if mask is None else _f32(mask)
+    tc = cam(tgt)
+    rc = lib(prec).orc_raymarch(cams(src), K, _p(d), C.byref(tc), C.byref(tsdf_params(tsdf)),
+                                _p(dp), _p(ac), _p(m), _p(od), _p(oa), _p(st))
+    if rc != 0:
+        raise RuntimeError(f"orc_raymarch failed: {rc}")
+    return od, oa, st
+
+
 def extract(F, W, tsdf, prec=32):
     rt = _rt(prec)
     D = int(tsdf["num_bins"])

@@ -21,6 +21,10 @@
  *                       cut s_k < -tau => omega_k = 0) plus the temporal
  *                       weight of Suppl. A.2 carried per voxel.
  *   orc_extract      -- the sign change along the ray of Suppl. A.1.
+ *   orc_raymarch     -- the volume-free form of the same fusion: the march
+ *                       along each target ray with step 0.8 s and three
+ *                       bisections of Suppl. A.1, with the previous output
+ *                       depth as one more input (Suppl. A.2).
  *   orc_splat        -- forward rendering of per-pixel Gaussians of §3.1 and
  *                       Suppl. A.3 as a z-buffered splat; orc_splat_masked
  *                       also carries a per-pixel scalar (the difference
@@ -309,6 +313,151 @@ int orc_integrate(const orc_camera *src, int K, const float *depth, const real *
   free(tb);
   free(Hk);
   free(ck);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Volume-free TSDF raymarch (Suppl. A.1: advance along the ray by 0.8 s until
+ * s changes sign, then three bisection steps; Suppl. A.2: the previous
+ * output depth as one more input with the temporal weight).
+ *
+ * Fused value at target depth z on the ray of target pixel (x, y): the views
+ * in order with the projection, sampling, sign, occlusion and clamp rules of
+ * orc_integrate, tau(z) = trunc du z^2 (trunc in bins) or trunc:
+ * S = sum omega_k min(s_k, tau), Wo = sum omega_k over kept samples; then,
+ * where the pixel has a previous depth Dp > 0 and omega_tmp > 0, one more
+ * sample s = Dp - z with weight omega_tmp (same occlusion cut and clamp).
+ * Wt = Wo (+ omega_tmp when kept); s(z) = S / Wt, no value (unobserved)
+ * where Wt = 0.  Temporal weight (Suppl. A.2): omega_tmp =
+ * min((decay acc) m, cap), m = max(1 - M, 0) (1 without a mask), acc the
+ * pixel's accumulated weight from the previous frame.
+ *
+ * March (readings; the paper gives the step rule only): with
+ * step_min(z) = (du z) z, the width of one inverse-depth bin at z,
+ *   observed, s > 0 : z <- z + max(0.8 s, step_min(z))
+ *   observed, s <= 0: a surface if the previous sample was observed with
+ *                     s > 0, else z <- z + step_min(z)
+ *   unobserved      : z <- z + 0.8 tau(z)
+ * from z = z_near while z <= z_far (at most 4 D + 16 samples); no surface:
+ * depth 0, acc_next 0.  Bracket [a, b], s(a) > 0 >= s(b); three bisections
+ * m = a + (b - a) * 0.5, a = m if s(m) is observed and > 0, else b = m;
+ * depth = a + (b - a) * 0.5.  acc_next = omega_tmp + Wo at that depth (the
+ * accumulated weight of Suppl. A.2 for the next frame).
+ * dprev, acc, mask: Ht x Wt or NULL (no temporal term without dprev and
+ * acc).  out_depth, out_acc (nullable), out_steps (nullable: samples taken
+ * before the bisection): Ht x Wt.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  real S, Wo, Wt;
+} orc_fused;
+
+static orc_fused fused_at(real z, real tau, int K, real (*h)[3], real (*ck)[3], const float *depth,
+                          const real *conf, int Ws, int Hs, real wtmp, real Dp) {
+  const size_t ns = (size_t)Ws * Hs;
+  orc_fused f = {0, 0, 0};
+  for (int k = 0; k < K; ++k) {
+    real X[3];
+    point_at(h[k], ck[k], z, X);
+    if (!(X[2] > 0)) continue;
+    const real inv = (real)1 / X[2];
+    const real u = X[0] * inv, v = X[1] * inv;
+    if (!(u >= 0 && u < (real)Ws && v >= 0 && v < (real)Hs)) continue;
+    const size_t q = (size_t)(int)v * Ws + (size_t)(int)u;
+    const float Dk = depth[ns * k + q];
+    if (!depth_ok(Dk)) continue;
+    const real s = (real)Dk - X[2];
+    if (s < -tau) continue;
+    const real w = conf[ns * k + q];
+    f.S = RFMA(w, RMIN(s, tau), f.S);
+    f.Wo = f.Wo + w;
+  }
+  f.Wt = f.Wo;
+  if (wtmp > 0 && Dp > 0) {
+    const real s = Dp - z;
+    if (!(s < -tau)) {
+      f.S = RFMA(wtmp, RMIN(s, tau), f.S);
+      f.Wt = f.Wt + wtmp;
+    }
+  }
+  return f;
+}
+
+int orc_raymarch(const orc_camera *src, int K, const float *depth, const orc_camera *tgt,
+                 const orc_tsdf_params *p, const real *dprev, const real *acc, const float *mask,
+                 real *out_depth, real *out_acc, int32_t *out_steps) {
+  const int D = p->num_bins;
+  const int Ws = src[0].width, Hs = src[0].height;
+  const size_t ns = (size_t)Ws * Hs;
+  if (K < 1 || K > 16 || D < 2) return -1;
+  real *conf = (real *)malloc(sizeof(real) * ns * K);
+  if (!conf) return -2;
+  for (int k = 0; k < K; ++k) orc_confidence(depth + ns * k, Ws, Hs, p, conf + ns * k);
+  real Hk[16][9], ck[16][3];
+  for (int k = 0; k < K; ++k) relproj(tgt, &src[k], Hk[k], ck[k]);
+  const real un = (real)1 / (real)p->z_near, uf = (real)1 / (real)p->z_far;
+  const real du = (un - uf) / (real)(D - 1);
+  const real zn = (real)p->z_near, zf = (real)p->z_far;
+  const real cap = (real)p->weight_cap, decay = (real)p->decay;
+  const int max_samples = 4 * D + 16;
+  const int npix = tgt->width * tgt->height;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int n = 0; n < npix; ++n) {
+    const int x = n % tgt->width, y = n / tgt->width;
+    real h[16][3];
+    for (int k = 0; k < K; ++k) ray_of(Hk[k], (real)x + (real)0.5, (real)y + (real)0.5, h[k]);
+    real wtmp = 0, Dp = 0;
+    if (dprev && acc) {
+      const real m = mask ? RMAX((real)1 - (real)mask[n], (real)0) : (real)1;
+      wtmp = RMIN((decay * acc[n]) * m, cap);
+      Dp = dprev[n];
+    }
+#define TAU_AT(zz) (p->trunc_in_bins ? ((real)p->trunc * du) * ((zz) * (zz)) : (real)p->trunc)
+    real z = zn, zprev = 0;
+    int prev_pos = 0, found = 0, steps = 0;
+    while (z <= zf && steps < max_samples) {
+      const real tau = TAU_AT(z);
+      const orc_fused f = fused_at(z, tau, K, h, ck, depth, conf, Ws, Hs, wtmp, Dp);
+      ++steps;
+      const real smin = (du * z) * z;
+      if (f.Wt > 0) {
+        const real s = f.S / f.Wt;
+        if (s > 0) {
+          zprev = z;
+          prev_pos = 1;
+          z = z + RMAX((real)0.8 * s, smin);
+        } else if (prev_pos) {
+          found = 1;
+          break;
+        } else {
+          prev_pos = 0;
+          z = z + smin;
+        }
+      } else {
+        prev_pos = 0;
+        z = z + (real)0.8 * tau;
+      }
+    }
+    real dep = 0, an = 0;
+    if (found) {
+      real a = zprev, b = z;
+      for (int it = 0; it < 3; ++it) {
+        const real mid = a + (b - a) * (real)0.5;
+        const orc_fused f = fused_at(mid, TAU_AT(mid), K, h, ck, depth, conf, Ws, Hs, wtmp, Dp);
+        if (f.Wt > 0 && f.S / f.Wt > 0)
+          a = mid;
+        else
+          b = mid;
+      }
+      dep = a + (b - a) * (real)0.5;
+      const orc_fused f = fused_at(dep, TAU_AT(dep), K, h, ck, depth, conf, Ws, Hs, wtmp, Dp);
+      an = wtmp + f.Wo;
+    }
+#undef TAU_AT
+    out_depth[n] = dep;
+    if (out_acc) out_acc[n] = an;
+    if (out_steps) out_steps[n] = steps;
+  }
+  free(conf);
   return 0;
 }
 

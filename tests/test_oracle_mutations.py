@@ -16,6 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = "tests/test_oracle_pins.py"
 GRADS = "tests/test_oracle_gradients.py"
 TEMPORAL = "tests/test_oracle_temporal.py"
+MARCH = "tests/test_oracle_raymarch.py"
 MUTANTS = [
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
@@ -74,6 +75,19 @@ MUTANTS = [
     ("mask_splat_unnormalised", "msum[p] / nrm[p];", "msum[p];", TEMPORAL),
     ("mask_max_not_max", "if (out_mask_max && m > out_mask_max[p]) out_mask_max[p] = m;",
      "if (out_mask_max) out_mask_max[p] = m;", TEMPORAL),
+    ("march_full_step", "z = z + RMAX((real)0.8 * s, smin);", "z = z + RMAX(s * (real)1.6, smin);",
+     MARCH),
+    ("march_no_min_step", "z = z + RMAX((real)0.8 * s, smin);", "z = z + (real)0.8 * s;", MARCH),
+    ("march_two_bisections", "for (int it = 0; it < 3; ++it) {", "for (int it = 0; it < 2; ++it) {",
+     MARCH),
+    ("march_bisection_flipped", "        if (f.Wt > 0 && f.S / f.Wt > 0)\n          a = mid;",
+     "        if (f.Wt > 0 && f.S / f.Wt > 0)\n          b = mid;", MARCH),
+    ("march_bracket_end", "      dep = a + (b - a) * (real)0.5;", "      dep = b;", MARCH),
+    ("march_temporal_sign", "    const real s = Dp - z;", "    const real s = z - Dp;", MARCH),
+    ("march_temporal_no_cap", "wtmp = RMIN((decay * acc[n]) * m, cap);", "wtmp = (decay * acc[n]) * m;",
+     MARCH),
+    ("march_acc_without_tmp", "      an = wtmp + f.Wo;", "      an = f.Wo;", MARCH),
+    ("march_unnormalised", "        const real s = f.S / f.Wt;", "        const real s = f.S;", MARCH),
 ]
 
 
