@@ -243,6 +243,44 @@ def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
             if kt["difference_masks"] > 0 else None}
 
 
+def raymarch_path(gg, torch, dev, src, tgt, tp, depth, steps, warmup):
+    """The paper's own volume-free fusion (Suppl. A.1 march, Suppl. A.2
+    temporal input) on the video workload: per frame one march of every
+    target ray, the previous output depth and its accumulated weight carried
+    (ping-pong buffers); inputs resident."""
+    nf, K, H, Wd = depth.shape[0], depth.shape[1], depth.shape[2], depth.shape[3]
+    ws = torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, tp.num_bins), dtype=torch.uint8,
+                     device=dev)
+    dbuf = [torch.zeros((H, Wd), device=dev) for _ in range(2)]
+    abuf = [torch.zeros((H, Wd), device=dev) for _ in range(2)]
+
+    def step(i):
+        a, b = i % 2, (i + 1) % 2
+        gg.tsdf_raymarch(src, depth[i % nf], tgt, tp, depth_prev=dbuf[a], acc_prev=abuf[a],
+                         out_depth=dbuf[b], out_acc=abuf[b], ws=ws)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    gg.timing_reset()
+    gg.timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(warmup + i)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gg.timing_enable(False)
+    rm, n = gg.timing_read("raymarch")
+    cf, _ = gg.timing_read("conf")
+    _, _, st = gg.tsdf_raymarch(src, depth[0], tgt, tp, steps=True, ws=ws)
+    ms = el * 1e3 / steps
+    return {"workload": "video ring K=4 1280x720, march bounds as D=128, temporal input carried",
+            "ms_per_frame": round(ms, 4), "mpix_s": round(H * Wd / ms / 1e3, 2),
+            "kernel_ms_per_frame": {"raymarch": round(rm / max(n, 1), 4),
+                                    "conf": round(cf / max(n, 1), 4)},
+            "samples_per_ray_mean": round(float(st.float().mean()), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +291,7 @@ def main():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-temporal", action="store_true")
+    ap.add_argument("--no-raymarch", action="store_true")
     ap.add_argument("--procs", type=int, default=0,
                     help="input-generation worker processes (0: min(16, cores))")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -355,6 +394,8 @@ def main():
     if not args.no_temporal:
         out["temporal_path"] = temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb,
                                              min(args.steps, 30), 3)
+    if not args.no_raymarch:
+        out["raymarch"] = raymarch_path(gg, torch, dev, src, tgt, tp, depth, min(args.steps, 30), 3)
     if not args.no_batch:
         del depth, rgb, ws_s, ws_t
         torch.cuda.empty_cache()

@@ -175,6 +175,41 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
                          size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * tsdf_raymarch -- the volume-free form of the fusion (Suppl. A.1): per
+ * target pixel, the fused signed distance is evaluated on the fly along the
+ * ray and the first sign change is located by marching and bisection; the
+ * previous output depth enters as one more input (Suppl. A.2).  No volume.
+ *
+ * Fused value at target depth z (the sampling, sign, occlusion and clamp of
+ * tsdf_integrate, with tau(z) = trunc du z^2 if trunc_in_bins else trunc):
+ *   S = sum_k omega_k min(s_k, tau), Wo = sum_k omega_k over kept samples,
+ *   views in order; then, where depth_prev(p) > 0 and omega_tmp > 0, one more
+ *   sample s = depth_prev(p) - z with weight omega_tmp (same rules);
+ *   omega_tmp = min((decay * acc_prev(p)) * max(1 - M(p), 0), weight_cap).
+ *   Wt = Wo (+ omega_tmp if kept); s(z) = S / Wt, unobserved where Wt = 0.
+ * March from z = z_near while z <= z_far (at most 4 D + 16 samples), with
+ *   step_min(z) = (du z) z (one inverse-depth bin): observed s > 0: z +=
+ *   max(0.8 s, step_min); observed s <= 0 after an observed s > 0: surface
+ *   bracketed; observed s <= 0 otherwise: z += step_min; unobserved: z +=
+ *   0.8 tau(z).  Three bisections of the bracket [a, b] (a = mid where s(mid)
+ *   is observed and > 0, else b = mid); depth = a + (b - a) * 0.5.
+ *   No surface: depth 0, acc 0.  out_acc = omega_tmp + Wo at the depth (the
+ *   accumulated weight of Suppl. A.2 for the next frame's acc_prev).
+ * All FP32 in this order (no contraction): bitwise reproducible.
+ *
+ * src, K, depth, tgt, prm: as tsdf_integrate (num_bins sets du and the
+ * sample cap).  depth_prev, acc_prev: float tgt_h x tgt_w, both or neither
+ * (no temporal term).  temporal_mask: float tgt_h x tgt_w or NULL (M = 0);
+ * needs depth_prev.  out_depth float tgt_h x tgt_w; out_acc float
+ * tgt_h x tgt_w or NULL; out_steps int32 tgt_h x tgt_w or NULL (samples
+ * before the bisection).  ws: gg_workspace_size(GG_OP_TSDF_INTEGRATE, ...).
+ * ------------------------------------------------------------------------- */
+int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
+                  const gg_tsdf_params *prm, const float *depth_prev, const float *acc_prev,
+                  const float *temporal_mask, float *out_depth, float *out_acc,
+                  int32_t *out_steps, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * difference_masks -- soft colour-difference masks between consecutive frames
  * of K views (Eq. 1, §3.2) and, optionally, the temporally filtered depth of
  * Eq. 2.

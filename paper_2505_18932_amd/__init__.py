@@ -9,10 +9,11 @@ from .ops import (BatchPlan, camera, cameras, difference_masks, mask_params,
                   relative_projection, splat_params, splat_views,
                   splat_views_backward, timing_enable, timing_read, timing_reset,
                   tsdf_extract_depth, tsdf_extract_depth_backward, tsdf_integrate,
-                  tsdf_integrate_backward, tsdf_params, workspace_size)
+                  tsdf_integrate_backward, tsdf_params, tsdf_raymarch, workspace_size)
 
 __all__ = ["BatchPlan", "camera", "cameras", "difference_masks", "mask_params",
            "relative_projection", "splat_params", "splat_views",
            "splat_views_backward", "timing_enable", "timing_read", "timing_reset",
            "tsdf_extract_depth", "tsdf_extract_depth_backward", "tsdf_integrate",
-           "tsdf_integrate_backward", "tsdf_params", "workspace_size", "_lib", "autograd"]
+           "tsdf_integrate_backward", "tsdf_params", "tsdf_raymarch", "workspace_size", "_lib",
+           "autograd"]

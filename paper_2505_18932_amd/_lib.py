@@ -78,6 +78,7 @@ SIGNATURES = {
     "difference_masks": (C.c_int, [I32, I32, I32, P, P, C.POINTER(GGMaskParams), P, P, P, P, P,
                                    SZ, P]),
     "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
+    "tsdf_raymarch": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_extract_depth": (C.c_int, [CAM, TSP, P, P, P, P, P]),
     "tsdf_extract_depth_backward": (C.c_int, [CAM, TSP, P, P, P, P, P, P]),
     "tsdf_integrate_backward": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, SZ, P]),

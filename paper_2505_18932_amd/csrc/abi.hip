@@ -628,6 +628,54 @@ int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg
   return launch_integrate(a, vs.V, vs.threads, s);
 }
 
+int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
+                  const gg_tsdf_params *prm, const float *depth_prev, const float *acc_prev,
+                  const float *temporal_mask, float *out_depth, float *out_acc,
+                  int32_t *out_steps, void *ws, size_t ws_bytes, void *stream) {
+  const char *N = "tsdf_raymarch";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!depth || !out_depth) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  if ((depth_prev == nullptr) != (acc_prev == nullptr))
+    return fail(GG_ERR_INVALID, "%s: depth_prev and acc_prev go together", N);
+  if (temporal_mask && !depth_prev)
+    return fail(GG_ERR_INVALID, "%s: temporal_mask needs depth_prev and acc_prev", N);
+  const int sw = src[0].width, sh = src[0].height, D = prm->num_bins;
+  const TsdfLayout L = tsdf_layout(K, sw, sh, D, false);
+  if (int rc = check_ws(ws, ws_bytes, L.total, N)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  float2 *table = (float2 *)((char *)ws + L.table);
+  if (int rc = launch_conf(conf_args(depth, table, sw, sh, K, prm), s)) return rc;
+  RaymarchArgs a{};
+  fill_views(src, K, tgt, a.views);
+  a.table = table;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.ns = (uint32_t)(sw * sh);
+  a.npix = (uint32_t)(tgt->width * tgt->height);
+  a.wt_div = make_fastdiv((uint32_t)tgt->width);
+  a.z_near = prm->z_near;
+  a.z_far = prm->z_far;
+  // bin width in inverse depth, formed as the bins are
+  const float un = 1.0f / prm->z_near, uf = 1.0f / prm->z_far;
+  a.du = (un - uf) / (float)(D - 1);
+  a.trunc = prm->trunc;
+  a.trunc_in_bins = prm->trunc_in_bins;
+  a.decay = prm->decay;
+  a.cap = prm->weight_cap;
+  a.max_samples = 4 * D + 16;
+  a.dprev = depth_prev;
+  a.acc = acc_prev;
+  a.mask = temporal_mask;
+  a.out_depth = out_depth;
+  a.out_acc = out_acc;
+  a.out_steps = out_steps;
+  a.exact_only = fast_reciprocal_safe(a.views, K, *tgt, prm->z_far) ? 0 : 1;
+  return launch_raymarch(a, s);
+}
+
 int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
                        const float *W, float *out_depth, int32_t *out_bin, void *stream) {
   const char *N = "tsdf_extract_depth";

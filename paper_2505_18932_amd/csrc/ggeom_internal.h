@@ -213,6 +213,25 @@ struct TsdfBackArgs {
   float tw2, n2, scale;
 };
 
+// Volume-free raymarch (raymarch.hip).
+struct RaymarchArgs {
+  Proj views[GG_MAX_VIEWS];  // target -> view k
+  const float2 *table;       // K x Ns view table
+  int32_t K, Ws, Hs;
+  uint32_t ns, npix;
+  FastDiv wt_div;            // by Wt
+  float z_near, z_far, du, trunc;
+  int32_t trunc_in_bins;
+  float decay, cap;
+  int32_t max_samples;
+  const float *dprev, *acc, *mask;  // Ht x Wt or null (dprev and acc together)
+  float *out_depth, *out_acc;
+  int32_t *out_steps;
+  int32_t exact_only;
+};
+
+int launch_raymarch(const RaymarchArgs &a, hipStream_t s);
+
 int launch_bins(const gg_tsdf_params &p, float2 *bins, hipStream_t s);
 int launch_conf(const ConfArgs &a, hipStream_t s);
 int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_t s);

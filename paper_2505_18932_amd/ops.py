@@ -254,6 +254,33 @@ def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None,
     return F, W, od, ob
 
 
+def tsdf_raymarch(src, depth, tgt, params, *, depth_prev=None, acc_prev=None, mask=None,
+                  steps=False, out_depth=None, out_acc=None, ws=None, stream=None):
+    """Volume-free march of every target ray (see include/ggeom.h).
+    Returns (depth, acc_next, steps or None); ``depth_prev`` / ``acc_prev``
+    (both or neither) switch on the temporal input, ``mask`` weights it."""
+    dev = _device(depth)
+    sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    th, tw = tg.height, tg.width
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    for name, t in (("depth_prev", depth_prev), ("acc_prev", acc_prev), ("mask", mask)):
+        if t is not None:
+            _need(t, torch.float32, (th, tw), name, dev)
+    od = torch.empty((th, tw), dtype=torch.float32, device=dev) if out_depth is None else \
+        _need(out_depth, torch.float32, (th, tw), "out_depth", dev)
+    oa = torch.empty((th, tw), dtype=torch.float32, device=dev) if out_acc is None else \
+        _need(out_acc, torch.float32, (th, tw), "out_acc", dev)
+    st = torch.empty((th, tw), dtype=torch.int32, device=dev) if steps else None
+    need = workspace_size(L.GG_OP_TSDF_INTEGRATE, K, sw, sh, tw, th, tp.num_bins)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().tsdf_raymarch(sa, K, _ptr(depth), C.byref(tg), C.byref(tp), _ptr(depth_prev),
+                                  _ptr(acc_prev), _ptr(mask), _ptr(od), _ptr(oa), _ptr(st),
+                                  _ptr(wsb), wsn, _stream(dev, stream)))
+    return od, oa, st
+
+
 def tsdf_extract_depth(tgt, params, F, W, *, stream=None):
     dev = _device(F)
     tg, tp = camera(tgt), tsdf_params(params)

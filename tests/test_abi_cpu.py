@@ -136,6 +136,22 @@ def test_difference_masks_reject_invalid_arguments():
     assert ops.workspace_size(L.GG_OP_DIFFERENCE_MASKS, 2, 65, 47, 65, 47, 0) == 0
 
 
+def test_raymarch_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    tp = ops.tsdf_params(scenes.tsdf_params(num_bins=32))
+
+    def call(d=FAKE, dp=None, ac=None, m=None, od=FAKE, nws=1 << 40, prm=tp):
+        return lib.tsdf_raymarch(src, 2, d, C.byref(tgt), C.byref(prm), dp, ac, m, od, None, None,
+                                 FAKE, nws, None)
+    assert call(d=None) == L.GG_ERR_INVALID
+    assert call(od=None) == L.GG_ERR_INVALID
+    assert call(dp=FAKE) == L.GG_ERR_INVALID  # depth_prev without acc_prev
+    assert call(m=FAKE) == L.GG_ERR_INVALID   # mask without the temporal input
+    assert call(prm=ops.tsdf_params(scenes.tsdf_params(num_bins=1))) == L.GG_ERR_INVALID
+    assert call(nws=8) == L.GG_ERR_WORKSPACE
+
+
 def test_tsdf_rejects_invalid_arguments():
     lib = L.lib()
     src, tgt = _cams()

@@ -1,0 +1,71 @@
+"""The volume-free raymarch on the GPU against the oracle, bitwise: depth,
+accumulated weight and sample count per pixel, for compile-time and run-time
+view counts, with and without the temporal input, odd sizes, and the path
+where every sample takes IEEE division."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2505_18932_amd as gg
+import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def check(c, dprev=None, acc=None, mask=None):
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+    d, a, st = gg.tsdf_raymarch(c["src"], torch.from_numpy(c["depth"]).to(DEV), c["tgt"], c["tsdf"],
+                                depth_prev=t(dprev), acc_prev=t(acc), mask=t(mask), steps=True)
+    torch.cuda.synchronize()
+    rd, ra, rs = oracle.raymarch(c["src"], c["depth"], c["tgt"], c["tsdf"], dprev=dprev, acc=acc,
+                                 mask=mask)
+    assert np.array_equal(st.cpu().numpy(), rs), "sample counts"
+    assert np.array_equal(bits(d.cpu().numpy()), bits(rd)), "depth"
+    assert np.array_equal(bits(a.cpu().numpy()), bits(ra)), "acc"
+    return rd
+
+
+def test_tiny_config_bitwise():
+    c = scenes.config1()
+    rd = check(c)
+    assert (rd > 0).mean() > 0.99
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_view_counts(k):
+    c = scenes.small_ring(seed=k, width=53, height=29, k=k, bins=48, noise=0.01, holes=0.05)
+    check(c)
+
+
+def test_temporal_input_and_mask():
+    c = scenes.small_video(seed=4, width=64, height=40, k=3, bins=40)
+    d0, _ = c["seq"].frame(0)
+    d1, _ = c["seq"].frame(1)
+    c0 = dict(c, depth=d0)
+    c1 = dict(c, depth=d1)
+    prev = oracle.raymarch(c0["src"], d0, c0["tgt"], c0["tsdf"])
+    rng = np.random.default_rng(0)
+    mask = rng.uniform(0.6, 1.0, prev[0].shape).astype(np.float32)
+    mask[:10] = 0.0  # full carry on some rows
+    check(c1, dprev=prev[0], acc=prev[1])
+    check(c1, dprev=prev[0], acc=prev[1], mask=mask)
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (17, 1), (1, 23), (33, 17)])
+def test_odd_sizes(wh):
+    c = scenes.small_ring(seed=9, width=wh[0], height=wh[1], k=2, bins=24)
+    check(c)
+
+
+def test_division_everywhere():
+    """A depth range beyond the fast reciprocal's (z_far ~ 1e30): every sample
+    takes IEEE division; still bitwise."""
+    c = scenes.small_ring(seed=11, width=24, height=16, k=2, bins=12)
+    c["tsdf"] = dict(c["tsdf"], z_far=1e30)
+    check(c)
