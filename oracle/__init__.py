@@ -174,6 +174,31 @@ def raymarch(src, depth, tgt, tsdf, dprev=None, acc=None, mask=None, prec=32):
     return od, oa, st
 
 
+def network_inputs(src, tgt, tsdf_depth, rgb, depth, alpha, prec=32):
+    """(9K+1, Ht, Wt) input stack of the blending network."""
+    rt = _rt(prec)
+    K = len(src)
+    Ht, Wt = tgt.height, tgt.width
+    out = np.zeros((9 * K + 1, Ht, Wt), rt)
+    tc = cam(tgt)
+    rc = lib(prec).orc_network_inputs(cams(src), K, C.byref(tc), _p(_f32(tsdf_depth)), _p(_f32(rgb)),
+                                      _p(_f32(depth)), _p(_f32(alpha)), _p(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_network_inputs failed: {rc}")
+    return out
+
+
+def blend(rgb, depth, alpha, w, w_bg, rgb_bg, prec=32):
+    """Eq. 4-5: blended (3, H, W) image and (H, W) depth."""
+    rt = _rt(prec)
+    K, _, H, W = rgb.shape
+    orgb = np.zeros((3, H, W), rt)
+    od = np.zeros((H, W), rt)
+    lib(prec).orc_blend(K, W, H, _p(_f32(rgb)), _p(_f32(depth)), _p(_f32(alpha)), _p(_f32(w)),
+                        _p(_f32(w_bg)), _p(_f32(rgb_bg)), _p(orgb), _p(od))
+    return orgb, od
+
+
 def extract(F, W, tsdf, prec=32):
     rt = _rt(prec)
     D = int(tsdf["num_bins"])

@@ -21,6 +21,9 @@
  *                       cut s_k < -tau => omega_k = 0) plus the temporal
  *                       weight of Suppl. A.2 carried per voxel.
  *   orc_extract      -- the sign change along the ray of Suppl. A.1.
+ *   orc_network_inputs, orc_blend -- the geometry maps the blending network
+ *                       takes (§3.3 and the supplement's network inputs) and
+ *                       the blend of Eq. 4-5 for given weights.
  *   orc_raymarch     -- the volume-free form of the same fusion: the march
  *                       along each target ray with step 0.8 s and three
  *                       bisections of Suppl. A.1, with the previous output
@@ -459,6 +462,173 @@ int orc_raymarch(const orc_camera *src, int K, const float *depth, const orc_cam
   }
   free(conf);
   return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Inputs of the blending network (§3.3; the supplement's list of network
+ * inputs): a (9K + 1) x H x W stack of planes,
+ *   [0, 3K)      forward-rendered images I_k (3 planes per view, view-major),
+ *   [3K, 4K)     forward-rendered depths D_k (the splat's winner depths),
+ *   [4K, 5K)     alphas alpha_k,
+ *   5K           the TSDF depth D^t,
+ *   [5K+1, 6K+1) dot(input-view ray direction, TSDF normal),
+ *   [6K+1, 7K+1) dot(input-view ray direction, target ray direction),
+ *   [7K+1, 8K+1) distance between input and target camera centres,
+ *   [8K+1, 9K+1) dot(input and target optical axes).
+ * Readings: the surface point X(p) is target pixel p back-projected at D^t(p)
+ * (X = C_t + D a with a = R_t^T K_t^-1 (px, py, 1), evaluated affine in D as
+ * fma(D, a_r, C_r)); the normal is the normalised cross product of the
+ * horizontal and vertical differences of neighbouring surface points
+ * (central where both neighbours have a depth, else one-sided, else none),
+ * oriented towards the target camera; the input-view ray direction is
+ * (X - C_k) / |X - C_k|; the target ray direction a / |a|.  Pixels without a
+ * TSDF depth (or a normal) get 0 in the dot-product planes.  Centres, axes,
+ * distances and the matrix R_t^T K_t^-1 are formed in FP64 from the FP32
+ * cameras and rounded once.  Sums of three products are evaluated left to
+ * right without fused multiply-adds; cross products as a b - c d.
+ * ---------------------------------------------------------------------- */
+static void cam_centre_d(const orc_camera *c, double C[3]) {
+  for (int r = 0; r < 3; ++r) {
+    double v = 0;
+    for (int k = 0; k < 3; ++k) v -= (double)c->R[3 * k + r] * (double)c->t[k];
+    C[r] = v;
+  }
+}
+
+static real dot3(const real a[3], const real b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+int orc_network_inputs(const orc_camera *src, int K, const orc_camera *tgt, const float *tsdf_depth,
+                       const float *rgb, const float *depth, const float *alpha, real *out) {
+  const int W = tgt->width, H = tgt->height;
+  const size_t n = (size_t)W * H;
+  if (K < 1 || K > 16) return -1;
+  double Ct[3], Ck[16][3];
+  cam_centre_d(tgt, Ct);
+  for (int k = 0; k < K; ++k) cam_centre_d(&src[k], Ck[k]);
+  /* M = R_t^T K_t^-1 (FP64, then FP32 once) */
+  double Ki[9] = {1.0 / (double)tgt->fx, 0, -(double)tgt->cx / (double)tgt->fx,
+                  0, 1.0 / (double)tgt->fy, -(double)tgt->cy / (double)tgt->fy, 0, 0, 1};
+  real M[9], C[3], Cs[16][3], dist[16], axd[16];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += (double)tgt->R[3 * k + r] * Ki[3 * k + c];
+      M[3 * r + c] = (real)v;
+    }
+    C[r] = (real)Ct[r];
+  }
+  for (int k = 0; k < K; ++k) {
+    double d2 = 0, ax = 0;
+    for (int r = 0; r < 3; ++r) {
+      Cs[k][r] = (real)Ck[k][r];
+      d2 += (Ck[k][r] - Ct[r]) * (Ck[k][r] - Ct[r]);
+      ax += (double)src[k].R[6 + r] * (double)tgt->R[6 + r];
+    }
+    dist[k] = (real)sqrt(d2);
+    axd[k] = (real)ax;
+  }
+  /* copies of the rendered planes and the TSDF depth */
+  for (size_t i = 0; i < 3 * (size_t)K * n; ++i) out[i] = (real)rgb[i];
+  for (size_t i = 0; i < (size_t)K * n; ++i) {
+    out[3 * K * n + i] = (real)depth[i];
+    out[4 * K * n + i] = (real)alpha[i];
+  }
+  for (size_t i = 0; i < n; ++i) out[5 * K * n + i] = (real)tsdf_depth[i];
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < H; ++j)
+    for (int i = 0; i < W; ++i) {
+      const size_t p = (size_t)j * W + i;
+      real a[3], X[3], nrm[3] = {0, 0, 0};
+      ray_of(M, (real)i + (real)0.5, (real)j + (real)0.5, a);
+      const real D = (real)tsdf_depth[p];
+      const int ok = D > 0;
+      int has_n = 0;
+      if (ok) {
+        point_at(a, C, D, X);
+        real P[4][3];
+        int v[4];
+        const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+        for (int e = 0; e < 4; ++e) {
+          v[e] = ni[e] >= 0 && ni[e] < W && nj[e] >= 0 && nj[e] < H &&
+                 tsdf_depth[(size_t)nj[e] * W + ni[e]] > 0;
+          if (v[e]) {
+            real b[3];
+            ray_of(M, (real)ni[e] + (real)0.5, (real)nj[e] + (real)0.5, b);
+            point_at(b, C, (real)tsdf_depth[(size_t)nj[e] * W + ni[e]], P[e]);
+          }
+        }
+        real tx[3], ty[3];
+        int hx = 1, hy = 1;
+        for (int r = 0; r < 3; ++r) {
+          tx[r] = v[0] && v[1] ? P[1][r] - P[0][r] : v[1] ? P[1][r] - X[r] : v[0] ? X[r] - P[0][r] : 0;
+          ty[r] = v[2] && v[3] ? P[3][r] - P[2][r] : v[3] ? P[3][r] - X[r] : v[2] ? X[r] - P[2][r] : 0;
+        }
+        if (!(v[0] || v[1])) hx = 0;
+        if (!(v[2] || v[3])) hy = 0;
+        if (hx && hy) {
+          real c3[3] = {tx[1] * ty[2] - tx[2] * ty[1], tx[2] * ty[0] - tx[0] * ty[2],
+                        tx[0] * ty[1] - tx[1] * ty[0]};
+          const real len = RSQRT(dot3(c3, c3));
+          if (len > 0) {
+            for (int r = 0; r < 3; ++r) nrm[r] = c3[r] / len;
+            const real tc[3] = {C[0] - X[0], C[1] - X[1], C[2] - X[2]};
+            if (dot3(nrm, tc) < 0)
+              for (int r = 0; r < 3; ++r) nrm[r] = -nrm[r];
+            has_n = 1;
+          }
+        }
+      }
+      const real alen = RSQRT(dot3(a, a));
+      const real dt[3] = {a[0] / alen, a[1] / alen, a[2] / alen};
+      for (int k = 0; k < K; ++k) {
+        real dn = 0, dd = 0;
+        if (ok) {
+          real r3[3] = {X[0] - Cs[k][0], X[1] - Cs[k][1], X[2] - Cs[k][2]};
+          const real rl = RSQRT(dot3(r3, r3));
+          if (rl > 0) {
+            for (int r = 0; r < 3; ++r) r3[r] = r3[r] / rl;
+            if (has_n) dn = dot3(r3, nrm);
+            dd = dot3(r3, dt);
+          }
+        }
+        out[(5 * (size_t)K + 1 + k) * n + p] = dn;
+        out[(6 * (size_t)K + 1 + k) * n + p] = dd;
+        out[(7 * (size_t)K + 1 + k) * n + p] = dist[k];
+        out[(8 * (size_t)K + 1 + k) * n + p] = axd[k];
+      }
+    }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * The blend of Eq. 4-5 for given weights: I_FG = sum_k I_k alpha_k w_k /
+ * sum_k alpha_k w_k (reading of the printed fraction: the denominator sums
+ * over the views; I_FG = 0 where it is 0), I = (1 - w_BG) I_FG + w_BG I_BG;
+ * the depths D_k blend with the same weights (the blended depth of Eq. 6).
+ * Order: aw = alpha_k w_k; num = fma(I_k, aw, num), den = den + aw over k
+ * in order; I = fma(w_BG, I_BG, (1 - w_BG) I_FG).
+ * rgb K x 3 x H x W, depth / alpha / w K x H x W, w_bg H x W, rgb_bg
+ * 3 x H x W; out_rgb 3 x H x W, out_depth H x W.
+ * ---------------------------------------------------------------------- */
+void orc_blend(int K, int W, int H, const float *rgb, const float *depth, const float *alpha,
+               const float *w, const float *w_bg, const float *rgb_bg, real *out_rgb,
+               real *out_depth) {
+  const size_t n = (size_t)W * H;
+  for (size_t p = 0; p < n; ++p) {
+    real num[4] = {0, 0, 0, 0}, den = 0;
+    for (int k = 0; k < K; ++k) {
+      const real aw = (real)alpha[k * n + p] * (real)w[k * n + p];
+      for (int c = 0; c < 3; ++c) num[c] = RFMA((real)rgb[(3 * k + c) * n + p], aw, num[c]);
+      num[3] = RFMA((real)depth[k * n + p], aw, num[3]);
+      den = den + aw;
+    }
+    const real wb = (real)w_bg[p];
+    for (int c = 0; c < 3; ++c) {
+      const real fg = den > 0 ? num[c] / den : (real)0;
+      out_rgb[c * n + p] = RFMA(wb, (real)rgb_bg[c * n + p], ((real)1 - wb) * fg);
+    }
+    out_depth[p] = den > 0 ? num[3] / den : (real)0;
+  }
 }
 
 /* ------------------------------------------------------------------------

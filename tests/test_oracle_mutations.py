@@ -17,6 +17,7 @@ PINS = "tests/test_oracle_pins.py"
 GRADS = "tests/test_oracle_gradients.py"
 TEMPORAL = "tests/test_oracle_temporal.py"
 MARCH = "tests/test_oracle_raymarch.py"
+NET = "tests/test_oracle_netinputs.py"
 MUTANTS = [
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
@@ -88,6 +89,18 @@ MUTANTS = [
      MARCH),
     ("march_acc_without_tmp", "      an = wtmp + f.Wo;", "      an = f.Wo;", MARCH),
     ("march_unnormalised", "        const real s = f.S / f.Wt;", "        const real s = f.S;", MARCH),
+    ("net_normal_unoriented", "            if (dot3(nrm, tc) < 0)", "            if (0)", NET),
+    ("net_cross_order", "tx[0] * ty[1] - tx[1] * ty[0]}", "tx[1] * ty[0] - tx[0] * ty[1]}", NET),
+    ("net_ray_from_target", "real r3[3] = {X[0] - Cs[k][0], X[1] - Cs[k][1], X[2] - Cs[k][2]};",
+     "real r3[3] = {X[0] - C[0], X[1] - C[1], X[2] - C[2]};", NET),
+    ("net_one_sided_only", "tx[r] = v[0] && v[1] ? P[1][r] - P[0][r]", "tx[r] = 0 ? P[1][r] - P[0][r]",
+     NET),
+    ("net_axis_row", "ax += (double)src[k].R[6 + r] * (double)tgt->R[6 + r];",
+     "ax += (double)src[k].R[3 + r] * (double)tgt->R[6 + r];", NET),
+    ("blend_no_alpha", "const real aw = (real)alpha[k * n + p] * (real)w[k * n + p];",
+     "const real aw = (real)w[k * n + p];", NET),
+    ("blend_bg_swapped", "RFMA(wb, (real)rgb_bg[c * n + p], ((real)1 - wb) * fg);",
+     "RFMA((real)1 - wb, (real)rgb_bg[c * n + p], wb * fg);", NET),
 ]
 
 
