@@ -281,6 +281,41 @@ def raymarch_path(gg, torch, dev, src, tgt, tp, depth, steps, warmup):
             "samples_per_ray_mean": round(float(st.float().mean()), 2)}
 
 
+def network_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps):
+    """The blending network's input stack and the Eq. 4-5 blend (with
+    synthetic weights) on one frame of the video workload; algorithmic HBM
+    bytes per launch over the kernels' mean times."""
+    K, H, Wd = depth.shape[1], depth.shape[2], depth.shape[3]
+    so = gg.splat_views(src, depth[0], rgb[0], tgt, sp)
+    _, _, dep, _ = gg.tsdf_integrate(src, depth[0], tgt, tp)
+    w = torch.rand((K, H, Wd), device=dev)
+    wb = torch.rand((H, Wd), device=dev)
+    bg = torch.rand((3, H, Wd), device=dev)
+    out = torch.empty((9 * K + 1, H, Wd), device=dev)
+    for _ in range(3):
+        gg.network_inputs(src, tgt, dep, so, out=out)
+        gg.blend_views(so["rgb"], so["depth"], so["alpha"], w, wb, bg)
+    torch.cuda.synchronize()
+    gg.timing_reset()
+    gg.timing_enable(True)
+    for _ in range(steps):
+        gg.network_inputs(src, tgt, dep, so, out=out)
+        gg.blend_views(so["rgb"], so["depth"], so["alpha"], w, wb, bg)
+    torch.cuda.synchronize()
+    gg.timing_enable(False)
+    ni, n = gg.timing_read("network_inputs")
+    bl, _ = gg.timing_read("blend")
+    ni, bl = ni / max(n, 1), bl / max(n, 1)
+    px = H * Wd
+    # network inputs: read 5K planes + the TSDF depth (5 taps, cached), write 9K + 1 planes
+    b_ni = px * 4 * (5 * K + 1 + 9 * K + 1)
+    # blend: read 6K + 4 planes, write 4
+    b_bl = px * 4 * (6 * K + 4 + 4)
+    return {"workload": "video ring K=4 1280x720, one frame",
+            "network_inputs_ms": round(ni, 4), "network_inputs_gb_s": round(b_ni / ni / 1e6, 1),
+            "blend_ms": round(bl, 4), "blend_gb_s": round(b_bl / bl / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +327,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-temporal", action="store_true")
     ap.add_argument("--no-raymarch", action="store_true")
+    ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--procs", type=int, default=0,
                     help="input-generation worker processes (0: min(16, cores))")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -396,6 +432,8 @@ def main():
                                              min(args.steps, 30), 3)
     if not args.no_raymarch:
         out["raymarch"] = raymarch_path(gg, torch, dev, src, tgt, tp, depth, min(args.steps, 30), 3)
+    if not args.no_network:
+        out["network_inputs"] = network_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, 20)
     if not args.no_batch:
         del depth, rgb, ws_s, ws_t
         torch.cuda.empty_cache()

@@ -210,6 +210,43 @@ int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_
                   int32_t *out_steps, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * network_inputs -- the input stack of the blending network (§3.3 and the
+ * supplement's list of network inputs), (9K + 1) planes of tgt_h x tgt_w:
+ *   [0, 3K) rgb (the splat's out_rgb), [3K, 4K) depth (its out_depth),
+ *   [4K, 5K) alpha (its out_alpha), 5K the TSDF depth, then per view k
+ *   5K+1+k  dot(input-view ray direction, TSDF normal),
+ *   6K+1+k  dot(input-view ray direction, target ray direction),
+ *   7K+1+k  |C_k - C_t| (camera centres), 8K+1+k dot of the optical axes.
+ * Surface point X = C_t + D a, a = R_t^T K_t^-1 (px, py, 1) (FP64-formed,
+ * rounded once; X = fma(D, a, C_t)).  Normal: the normalised cross product
+ * of the horizontal and vertical differences of neighbouring surface points
+ * (central where both neighbours have a depth > 0, else one-sided, else
+ * none), oriented towards the target.  Input-view ray: (X - C_k) / |X - C_k|;
+ * target ray: a / |a|.  Dot planes are 0 without a TSDF depth (or normal).
+ * FP32, sums of three products left to right, no contraction: bitwise
+ * reproducible.
+ * src [host] K in 1..GG_MAX_VIEWS; tgt [host]; tsdf_depth float tgt_h x
+ * tgt_w; rgb float K x 3 x tgt_h x tgt_w; depth, alpha float K x tgt_h x
+ * tgt_w; out float (9K + 1) x tgt_h x tgt_w.
+ * ------------------------------------------------------------------------- */
+int network_inputs(const gg_camera *src, int32_t K, const gg_camera *tgt,
+                   const float *tsdf_depth, const float *rgb, const float *depth,
+                   const float *alpha, float *out, void *stream);
+
+/* blend_views -- Eq. 4-5 for given weights: I_FG = sum_k I_k alpha_k w_k /
+ * sum_k alpha_k w_k (0 where the sum is 0), I = (1 - w_BG) I_FG + w_BG I_BG;
+ * the depths blend with the same weights (Eq. 6's blended depth).  Order:
+ * aw = alpha_k w_k; num = fma(x_k, aw, num), den = den + aw, k in order;
+ * I = fma(w_BG, I_BG, (1 - w_BG) I_FG).
+ * rgb float K x 3 x height x width; depth, alpha, weights float
+ * K x height x width; w_bg float height x width; rgb_bg float
+ * 3 x height x width; out_rgb float 3 x height x width; out_depth float
+ * height x width. */
+int blend_views(int32_t K, int32_t width, int32_t height, const float *rgb, const float *depth,
+                const float *alpha, const float *weights, const float *w_bg,
+                const float *rgb_bg, float *out_rgb, float *out_depth, void *stream);
+
+/* ---------------------------------------------------------------------------
  * difference_masks -- soft colour-difference masks between consecutive frames
  * of K views (Eq. 1, §3.2) and, optionally, the temporally filtered depth of
  * Eq. 2.

@@ -5,13 +5,15 @@ difference masks with the temporally filtered depth, adjoints and a batched
 path, as hand-written HIP kernels behind a C ABI (include/ggeom.h).
 """
 from . import _lib, autograd
-from .ops import (BatchPlan, camera, cameras, difference_masks, mask_params,
+from .ops import (BatchPlan, blend_views, camera, cameras, difference_masks, mask_params,
+                  network_inputs,
                   relative_projection, splat_params, splat_views,
                   splat_views_backward, timing_enable, timing_read, timing_reset,
                   tsdf_extract_depth, tsdf_extract_depth_backward, tsdf_integrate,
                   tsdf_integrate_backward, tsdf_params, tsdf_raymarch, workspace_size)
 
-__all__ = ["BatchPlan", "camera", "cameras", "difference_masks", "mask_params",
+__all__ = ["BatchPlan", "blend_views", "camera", "cameras", "difference_masks", "mask_params",
+           "network_inputs",
            "relative_projection", "splat_params", "splat_views",
            "splat_views_backward", "timing_enable", "timing_read", "timing_reset",
            "tsdf_extract_depth", "tsdf_extract_depth_backward", "tsdf_integrate",

@@ -79,6 +79,8 @@ SIGNATURES = {
                                    SZ, P]),
     "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_raymarch": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
+    "network_inputs": (C.c_int, [CAM, I32, CAM, P, P, P, P, P, P]),
+    "blend_views": (C.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, P]),
     "tsdf_extract_depth": (C.c_int, [CAM, TSP, P, P, P, P, P]),
     "tsdf_extract_depth_backward": (C.c_int, [CAM, TSP, P, P, P, P, P, P]),
     "tsdf_integrate_backward": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, SZ, P]),

@@ -676,6 +676,82 @@ int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_
   return launch_raymarch(a, s);
 }
 
+static void centre_d(const gg_camera &c, double C[3]) {
+  for (int r = 0; r < 3; ++r) {
+    double v = 0;
+    for (int k = 0; k < 3; ++k) v -= (double)c.R[3 * k + r] * (double)c.t[k];
+    C[r] = v;
+  }
+}
+
+int network_inputs(const gg_camera *src, int32_t K, const gg_camera *tgt,
+                   const float *tsdf_depth, const float *rgb, const float *depth,
+                   const float *alpha, float *out, void *stream) {
+  const char *N = "network_inputs";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (!tsdf_depth || !rgb || !depth || !alpha || !out)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  NetArgs a{};
+  double Ct[3];
+  centre_d(*tgt, Ct);
+  const double Ki[9] = {1.0 / (double)tgt->fx, 0, -(double)tgt->cx / (double)tgt->fx,
+                        0, 1.0 / (double)tgt->fy, -(double)tgt->cy / (double)tgt->fy, 0, 0, 1};
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      double v = 0;
+      for (int k = 0; k < 3; ++k) v += (double)tgt->R[3 * k + r] * Ki[3 * k + c];
+      a.M.H[3 * r + c] = (float)v;
+    }
+    a.M.c[r] = (float)Ct[r];
+  }
+  for (int k = 0; k < K; ++k) {
+    double Ck[3], d2 = 0, ax = 0;
+    centre_d(src[k], Ck);
+    for (int r = 0; r < 3; ++r) {
+      a.Cs[k][r] = (float)Ck[r];
+      d2 += (Ck[r] - Ct[r]) * (Ck[r] - Ct[r]);
+      ax += (double)src[k].R[6 + r] * (double)tgt->R[6 + r];
+    }
+    a.dist[k] = (float)std::sqrt(d2);
+    a.axd[k] = (float)ax;
+  }
+  a.K = K;
+  a.W = tgt->width;
+  a.H = tgt->height;
+  a.tsdf_depth = tsdf_depth;
+  a.rgb = rgb;
+  a.depth = depth;
+  a.alpha = alpha;
+  a.out = out;
+  return launch_network_inputs(a, (hipStream_t)stream);
+}
+
+int blend_views(int32_t K, int32_t width, int32_t height, const float *rgb, const float *depth,
+                const float *alpha, const float *weights, const float *w_bg,
+                const float *rgb_bg, float *out_rgb, float *out_depth, void *stream) {
+  const char *N = "blend_views";
+  if (K < 1 || K > GG_MAX_VIEWS)
+    return fail(GG_ERR_INVALID, "%s: K = %d outside 1..%d", N, K, GG_MAX_VIEWS);
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(GG_ERR_INVALID, "%s: size %dx%d outside 1..16384", N, width, height);
+  if (!rgb || !depth || !alpha || !weights || !w_bg || !rgb_bg || !out_rgb || !out_depth)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  BlendArgs a{};
+  a.K = K;
+  a.W = width;
+  a.H = height;
+  a.rgb = rgb;
+  a.depth = depth;
+  a.alpha = alpha;
+  a.w = weights;
+  a.w_bg = w_bg;
+  a.rgb_bg = rgb_bg;
+  a.out_rgb = out_rgb;
+  a.out_depth = out_depth;
+  return launch_blend(a, (hipStream_t)stream);
+}
+
 int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
                        const float *W, float *out_depth, int32_t *out_bin, void *stream) {
   const char *N = "tsdf_extract_depth";

@@ -232,6 +232,29 @@ struct RaymarchArgs {
 
 int launch_raymarch(const RaymarchArgs &a, hipStream_t s);
 
+// Blending-network inputs and the blend (netinputs.hip).
+struct NetArgs {
+  Proj M;                  // H: R_t^T K_t^-1 (pixel -> world ray), c: the target's centre
+  float Cs[GG_MAX_VIEWS][3];   // centres of the input cameras
+  float dist[GG_MAX_VIEWS];    // |C_k - C_t|
+  float axd[GG_MAX_VIEWS];     // optical-axis dot products
+  int32_t K, W, H;
+  const float *tsdf_depth;     // H x W
+  const float *rgb;            // K x 3 x H x W
+  const float *depth, *alpha;  // K x H x W
+  float *out;                  // (9K + 1) x H x W
+};
+
+struct BlendArgs {
+  int32_t K, W, H;
+  const float *rgb, *depth, *alpha, *w;  // K x 3 x H x W, K x H x W (x3)
+  const float *w_bg, *rgb_bg;            // H x W, 3 x H x W
+  float *out_rgb, *out_depth;            // 3 x H x W, H x W
+};
+
+int launch_network_inputs(const NetArgs &a, hipStream_t s);
+int launch_blend(const BlendArgs &a, hipStream_t s);
+
 int launch_bins(const gg_tsdf_params &p, float2 *bins, hipStream_t s);
 int launch_conf(const ConfArgs &a, hipStream_t s);
 int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_t s);

@@ -281,6 +281,42 @@ def tsdf_raymarch(src, depth, tgt, params, *, depth_prev=None, acc_prev=None, ma
     return od, oa, st
 
 
+def network_inputs(src, tgt, tsdf_depth, splat, *, out=None, stream=None):
+    """(9K+1, Ht, Wt) input stack of the blending network from the TSDF depth
+    and the splat outputs ``splat`` (dict with rgb, depth, alpha)."""
+    dev = _device(tsdf_depth)
+    sa, tg = cameras(src), camera(tgt)
+    K = len(sa)
+    th, tw = tg.height, tg.width
+    _need(tsdf_depth, torch.float32, (th, tw), "tsdf_depth", dev)
+    _need(splat["rgb"], torch.float32, (K, 3, th, tw), "rgb", dev)
+    _need(splat["depth"], torch.float32, (K, th, tw), "depth", dev)
+    _need(splat["alpha"], torch.float32, (K, th, tw), "alpha", dev)
+    o = torch.empty((9 * K + 1, th, tw), dtype=torch.float32, device=dev) if out is None else \
+        _need(out, torch.float32, (9 * K + 1, th, tw), "out", dev)
+    L.check(L.lib().network_inputs(sa, K, C.byref(tg), _ptr(tsdf_depth), _ptr(splat["rgb"]),
+                                   _ptr(splat["depth"]), _ptr(splat["alpha"]), _ptr(o),
+                                   _stream(dev, stream)))
+    return o
+
+
+def blend_views(rgb, depth, alpha, weights, w_bg, rgb_bg, *, stream=None):
+    """Eq. 4-5 with given weights: (image (3, H, W), blended depth (H, W))."""
+    dev = _device(rgb)
+    K, _, H, W = (int(v) for v in rgb.shape)
+    _need(rgb, torch.float32, (K, 3, H, W), "rgb", dev)
+    for name, t in (("depth", depth), ("alpha", alpha), ("weights", weights)):
+        _need(t, torch.float32, (K, H, W), name, dev)
+    _need(w_bg, torch.float32, (H, W), "w_bg", dev)
+    _need(rgb_bg, torch.float32, (3, H, W), "rgb_bg", dev)
+    orgb = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    od = torch.empty((H, W), dtype=torch.float32, device=dev)
+    L.check(L.lib().blend_views(K, W, H, _ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(weights),
+                                _ptr(w_bg), _ptr(rgb_bg), _ptr(orgb), _ptr(od),
+                                _stream(dev, stream)))
+    return orgb, od
+
+
 def tsdf_extract_depth(tgt, params, F, W, *, stream=None):
     dev = _device(F)
     tg, tp = camera(tgt), tsdf_params(params)

@@ -152,6 +152,22 @@ def test_raymarch_rejects_invalid_arguments():
     assert call(nws=8) == L.GG_ERR_WORKSPACE
 
 
+def test_network_inputs_and_blend_reject_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    assert lib.network_inputs(src, 0, C.byref(tgt), FAKE, FAKE, FAKE, FAKE, FAKE, None) == \
+        L.GG_ERR_INVALID
+    assert lib.network_inputs(src, 2, C.byref(tgt), None, FAKE, FAKE, FAKE, FAKE, None) == \
+        L.GG_ERR_INVALID
+    assert lib.network_inputs(src, 2, C.byref(tgt), FAKE, FAKE, FAKE, FAKE, None, None) == \
+        L.GG_ERR_INVALID
+    args = [FAKE] * 8
+    assert lib.blend_views(0, 8, 8, *args, None) == L.GG_ERR_INVALID
+    assert lib.blend_views(2, 0, 8, *args, None) == L.GG_ERR_INVALID
+    assert lib.blend_views(2, 8, 8, *([None] + args[1:]), None) == L.GG_ERR_INVALID
+    assert lib.blend_views(2, 8, 8, *(args[:7] + [None]), None) == L.GG_ERR_INVALID
+
+
 def test_tsdf_rejects_invalid_arguments():
     lib = L.lib()
     src, tgt = _cams()

@@ -1,0 +1,55 @@
+"""Blending-network inputs and the Eq. 4-5 blend on the GPU against the
+oracle, bitwise, on the outputs of the GPU splat and fusion."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2505_18932_amd as gg
+import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+@pytest.mark.parametrize("case", ["config1", "ring3", "holes"])
+def test_network_inputs_bitwise(case):
+    if case == "config1":
+        c = scenes.config1()
+    else:
+        c = scenes.small_ring(seed=5, width=61, height=37, k=3, bins=48,
+                              holes=0.0 if case == "ring3" else 0.2)
+    depth = torch.from_numpy(c["depth"]).to(DEV)
+    rgb = torch.from_numpy(c["rgb"]).to(DEV)
+    sp = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    _, _, dep, _ = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    out = gg.network_inputs(c["src"], c["tgt"], dep, sp)
+    torch.cuda.synchronize()
+    ref = oracle.network_inputs(c["src"], c["tgt"], dep.cpu().numpy(), sp["rgb"].cpu().numpy(),
+                                sp["depth"].cpu().numpy(), sp["alpha"].cpu().numpy())
+    got = out.cpu().numpy()
+    assert got.shape == ref.shape
+    bad = bits(got) != bits(ref)
+    assert not bad.any(), f"{bad.sum()} differ in planes {np.unique(np.nonzero(bad)[0])}"
+
+
+def test_blend_bitwise():
+    rng = np.random.default_rng(3)
+    K, H, W = 4, 45, 77
+    rgb = rng.uniform(0, 1, (K, 3, H, W)).astype(np.float32)
+    dep = rng.uniform(0.5, 5, (K, H, W)).astype(np.float32)
+    al = rng.uniform(0, 1, (K, H, W)).astype(np.float32)
+    al[:, :5] = 0  # no weight: background only
+    w = rng.uniform(0, 1, (K, H, W)).astype(np.float32)
+    wb = rng.uniform(0, 1, (H, W)).astype(np.float32)
+    bg = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    t = lambda a: torch.from_numpy(a).to(DEV)
+    o, d = gg.blend_views(t(rgb), t(dep), t(al), t(w), t(wb), t(bg))
+    torch.cuda.synchronize()
+    ro, rd = oracle.blend(rgb, dep, al, w, wb, bg)
+    assert np.array_equal(bits(o.cpu().numpy()), bits(ro))
+    assert np.array_equal(bits(d.cpu().numpy()), bits(rd))
