@@ -241,6 +241,40 @@ def splat(src, depth, rgb, tgt, sp, mask=None, prec=32):
     return out
 
 
+def exp_cw(x):
+    """The FP32 exp of the EWA renderer (Cody-Waite reduction, degree-6
+    Taylor polynomial) elementwise."""
+    x = np.ascontiguousarray(x, np.float32).ravel()
+    y = np.zeros_like(x)
+    lib(32).orc_exp_cw_n(_p(x), _p(y), C.c_size_t(x.size))
+    return y
+
+
+def splat_ewa(src, depth, rgb, tgt, sp, lowpass=0.3, pixels=None, prec=32):
+    """EWA pixel Gaussians composited front to back per view: rgb
+    (K,3,Ht,Wt), alpha and depth (K,Ht,Wt).  ``pixels`` (flat target indices)
+    restricts the rendering to those pixels (the rest read as not drawn)."""
+    rt = _rt(prec)
+    K = len(src)
+    Ht, Wt = tgt.height, tgt.width
+    orgb = np.zeros((K, 3, Ht, Wt), rt)
+    oa = np.zeros((K, Ht, Wt), rt)
+    od = np.zeros((K, Ht, Wt), rt)
+    d = _f32(depth)
+    c = np.ascontiguousarray(rgb, np.uint8)
+    pm = None
+    if pixels is not None:
+        pm = np.zeros(Ht * Wt, np.uint8)
+        pm[np.asarray(pixels, np.int64)] = 1
+    tc = cam(tgt)
+    rc = lib(prec).orc_splat_ewa(cams(src), K, _p(d), _p(c), C.byref(tc),
+                                 C.byref(splat_params(sp)), C.c_float(lowpass), _p(pm),
+                                 _p(orgb), _p(oa), _p(od))
+    if rc != 0:
+        raise RuntimeError(f"orc_splat_ewa failed: {rc}")
+    return dict(rgb=orgb, alpha=oa, depth=od)
+
+
 def difference_mask(rgb, rgb_prev, factor=4, beta=0.6, lambda_t=0.7, prec=32):
     """Soft difference masks (Eq. 1) of (H,W,3) or (K,H,W,3) uint8 frames."""
     a = np.ascontiguousarray(rgb, np.uint8)

@@ -32,6 +32,10 @@
  *                       Suppl. A.3 as a z-buffered splat; orc_splat_masked
  *                       also carries a per-pixel scalar (the difference
  *                       mask) and its maximum over the views (Suppl. A.2).
+ *   orc_splat_ewa    -- the same pixel Gaussians projected with EWA
+ *                       (anisotropic image-space covariance) and composited
+ *                       front to back in depth order, as the 3D Gaussian
+ *                       renderer the paper uses does (§3.1).
  *   orc_difference_mask -- the soft colour-difference mask of Eq. 1 at
  *                       quarter resolution, max-pooled and upsampled (§3.2).
  *   orc_temporal_filter -- the temporally filtered depth of Eq. 2 (§3.2).
@@ -69,6 +73,7 @@ typedef double real;
 #define RLOG log
 #define RMIN fmin
 #define RMAX fmax
+#define RABS fabs
 #define ORC_PREC 64
 #else
 typedef float real;
@@ -78,6 +83,7 @@ typedef float real;
 #define RLOG logf
 #define RMIN fminf
 #define RMAX fmaxf
+#define RABS fabsf
 #define ORC_PREC 32
 #endif
 
@@ -858,6 +864,215 @@ int orc_splat(const orc_camera *src, int K, const float *depth, const uint8_t *r
               real *out_depth, real *out_rgb, real *out_alpha, real *tape) {
   return orc_splat_masked(src, K, depth, rgb, tgt, sp, win_idx, out_depth, out_rgb, out_alpha,
                           tape, NULL, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------
+ * exp(x) in FP32 by Cody and Waite's argument reduction (1980) with a
+ * degree-6 Taylor polynomial: n = rint(x log2 e), r = x - n ln2 with ln2
+ * split into a 16-bit head and a tail (two fused multiply-adds), e^r by
+ * Horner's rule with fused multiply-adds, scaled by 2^n.  0 below x = -86
+ * (no subnormal results).  For x <= 0, within 3 ulp of e^x.  Every step is
+ * an explicitly rounded FP32 operation, so the function is reproducible
+ * bit for bit wherever it is implemented in this order.
+ * ---------------------------------------------------------------------- */
+float orc_exp_cw(float x) {
+  if (!(x >= -86.0f)) return 0.0f;
+  const float n = rintf(x * 1.44269504f);
+  float r = fmaf(-n, 0.693145752f, x);
+  r = fmaf(-n, 1.42860677e-6f, r);
+  float p = 1.0f / 720.0f;
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
+  return ldexpf(p, (int)n);
+}
+
+void orc_exp_cw_n(const float *x, float *y, size_t n) {
+  for (size_t i = 0; i < n; ++i) y[i] = orc_exp_cw(x[i]);
+}
+
+/* ------------------------------------------------------------------------
+ * EWA pixel Gaussians composited front to back (§3.1: the paper renders the
+ * per-pixel Gaussians with the 3D Gaussian splatting rasteriser).  The
+ * Gaussians are those of orc_splat: isotropic in 3D, centred on the
+ * back-projected pixel, fully opaque, coloured u8 / 255, with standard
+ * deviation sigma_px D / f_k so that their footprint in the source image is
+ * one pixel.  Here they are projected with the local affine (EWA)
+ * approximation of the perspective map instead of an isotropic disc.
+ *
+ * Readings (the paper names the renderer, not its constants):
+ *   - image covariance of the Gaussian with target mean (u, v) = (x, y) / z:
+ *     with a = (u - cx) / fx, b = (v - cy) / fy and sig = sscale (D / z)
+ *     (sscale = sigma_px fx_T / f_k, as in orc_splat),
+ *       S = sig^2 [[1 + a^2, r a b], [r a b, r^2 (1 + b^2)]] + lowpass I,
+ *     r = fy / fx: J J^T of the perspective Jacobian times the isotropic 3D
+ *     covariance, plus the renderer's 0.3 px^2 screen-space low-pass;
+ *   - opacity at a pixel centre: alpha = min(0.99, G), G = exp(power),
+ *     power = -d^T S^-1 d / 2, d = pixel centre - (u, v); terms with
+ *     power > 0 or alpha < 1/255 are skipped;
+ *   - footprints are clipped to |dx| <= r_max, |dy| <= r_max (r_max_px of
+ *     the splat parameters), which bounds the tiles a Gaussian can touch;
+ *   - per target pixel the terms are taken in ascending (z, source index)
+ *     order (z is the FP32 target depth of the mean); compositing stops
+ *     before the first term that would bring the transmittance below 1e-4;
+ *   - outputs per view: colour sum c alpha T, opacity 1 - T, and depth
+ *     sum z alpha T / (1 - T) (0 where no term was taken).
+ * Splats with z <= z_min are dropped, as in orc_splat.
+ *
+ * Operation order (FP32 build): inv = 1 / z, u = x inv, v = y inv,
+ * sig = sscale (D inv), s2 = sig sig,
+ * sxx = s2 (1 + a a) + lowpass, syy = s2 (r2 (1 + b b)) + lowpass,
+ * sxy = s2 (r (a b)) with r, r2 = (fy / fx)^2 rounded once from FP64;
+ * det = sxx syy - sxy sxy; Ah = (-0.5 syy) / det, Bn = sxy / det,
+ * Ch = (-0.5 sxx) / det; power = fma(Bn, dx dy, fma(Ah, dx dx, Ch (dy dy)));
+ * G = orc_exp_cw(power); w = alpha T; colour = fma(c, w, colour);
+ * depth sum = fma(z, w, sum); T = T (1 - alpha) (the product computed for
+ * the stopping test).
+ * out_rgb K x 3 x Ht x Wt, out_alpha and out_depth K x Ht x Wt; with
+ * pixel_mask (Ht x Wt, nullable) only the pixels it marks are rendered (the
+ * others read as nothing drawn).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint64_t key;
+  real u, v, Ah, Bn, Ch, z, c[3];
+} orc_ewa_entry;
+
+static int ewa_cmp(const void *x, const void *y) {
+  const uint64_t a = ((const orc_ewa_entry *)x)->key, b = ((const orc_ewa_entry *)y)->key;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+int orc_splat_ewa(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
+                  const orc_camera *tgt, const orc_splat_params *sp, float lowpass,
+                  const uint8_t *pixel_mask, real *out_rgb, real *out_alpha, real *out_depth) {
+  const int Ws = src[0].width, Hs = src[0].height, Wt = tgt->width, Ht = tgt->height;
+  const size_t ns = (size_t)Ws * Hs, nt = (size_t)Wt * Ht;
+  const real fx = (real)tgt->fx, fy = (real)tgt->fy, cx = (real)tgt->cx, cy = (real)tgt->cy;
+  const double rd = (double)tgt->fy / (double)tgt->fx;
+  const real ry = (real)rd, ry2 = (real)(rd * rd), lp = (real)lowpass;
+  const real rmax = (real)sp->r_max_px;
+  const real amin = (real)1 / (real)255;
+  size_t *cnt = (size_t *)malloc(sizeof(size_t) * (nt + 1));
+  if (!cnt) return -2;
+  for (int k = 0; k < K; ++k) {
+    real H[9], c[3];
+    relproj(&src[k], tgt, H, c);
+    const real sscale = (real)((double)sp->sigma_px * (double)tgt->fx / (double)src[k].fx);
+    const float *dk = depth + ns * k;
+    const uint8_t *ck = rgb + ns * 3 * k;
+    orc_ewa_entry *g = (orc_ewa_entry *)malloc(sizeof(orc_ewa_entry) * (ns ? ns : 1));
+    int *box = (int *)malloc(sizeof(int) * (ns ? ns : 1) * 4);
+    if (!g || !box) return -2;
+    /* the Gaussians of view k */
+    for (size_t q = 0; q < ns; ++q) {
+      g[q].key = UINT64_MAX;
+      const float D = dk[q];
+      if (!depth_ok(D)) continue;
+      real h[3], X[3];
+      ray_of(H, (real)(int)(q % Ws) + (real)0.5, (real)(int)(q / Ws) + (real)0.5, h);
+      point_at(h, c, (real)D, X);
+      if (!(X[2] > (real)sp->z_min)) continue;
+      const real inv = (real)1 / X[2];
+      const real u = X[0] * inv, v = X[1] * inv;
+      const real a = (u - cx) / fx, b = (v - cy) / fy;
+      const real sig = sscale * ((real)D * inv), s2 = sig * sig;
+      const real sxx = s2 * ((real)1 + a * a) + lp;
+      const real syy = s2 * (ry2 * ((real)1 + b * b)) + lp;
+      const real sxy = s2 * (ry * (a * b));
+      const real det = sxx * syy - sxy * sxy;
+      g[q].Ah = ((real)-0.5 * syy) / det;
+      g[q].Bn = sxy / det;
+      g[q].Ch = ((real)-0.5 * sxx) / det;
+      g[q].u = u;
+      g[q].v = v;
+      g[q].z = X[2];
+      for (int ch = 0; ch < 3; ++ch) g[q].c[ch] = (real)ck[q * 3 + ch] / (real)255;
+      g[q].key = ((uint64_t)f32_bits((float)X[2]) << 32) | (uint32_t)q;
+      /* a box holding every pixel that can take a term: alpha >= 1/255
+       * needs d^T S^-1 d <= 2 ln 255 < 12, which bounds |dx| by
+       * sqrt(12 sxx) and |dy| by sqrt(12 syy); the clip bounds both by
+       * r_max; one pixel of margin for the rounding of the bounds */
+      const double ud = (double)u, vd = (double)v;
+      const double rx = fmin(sqrt(12.0 * (double)sxx), (double)rmax) + 1;
+      const double rv = fmin(sqrt(12.0 * (double)syy), (double)rmax) + 1;
+      int x0 = (int)fmax(floor(ud - 0.5 - rx), -1.0), x1 = (int)fmin(ceil(ud - 0.5 + rx), 1e9);
+      int y0 = (int)fmax(floor(vd - 0.5 - rv), -1.0), y1 = (int)fmin(ceil(vd - 0.5 + rv), 1e9);
+      box[4 * q] = x0 < 0 ? 0 : x0;
+      box[4 * q + 1] = x1 > Wt - 1 ? Wt - 1 : x1;
+      box[4 * q + 2] = y0 < 0 ? 0 : y0;
+      box[4 * q + 3] = y1 > Ht - 1 ? Ht - 1 : y1;
+    }
+    /* per-pixel candidate lists (counting sort by pixel) */
+    for (size_t p = 0; p <= nt; ++p) cnt[p] = 0;
+    for (size_t q = 0; q < ns; ++q) {
+      if (g[q].key == UINT64_MAX) continue;
+      for (int y = box[4 * q + 2]; y <= box[4 * q + 3]; ++y)
+        for (int x = box[4 * q]; x <= box[4 * q + 1]; ++x)
+          if (!pixel_mask || pixel_mask[(size_t)y * Wt + x]) cnt[(size_t)y * Wt + x + 1]++;
+    }
+    for (size_t p = 0; p < nt; ++p) cnt[p + 1] += cnt[p];
+    uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (cnt[nt] ? cnt[nt] : 1));
+    size_t *cur = (size_t *)malloc(sizeof(size_t) * (nt ? nt : 1));
+    if (!lst || !cur) return -2;
+    memcpy(cur, cnt, sizeof(size_t) * nt);
+    for (size_t q = 0; q < ns; ++q) {
+      if (g[q].key == UINT64_MAX) continue;
+      for (int y = box[4 * q + 2]; y <= box[4 * q + 3]; ++y)
+        for (int x = box[4 * q]; x <= box[4 * q + 1]; ++x)
+          if (!pixel_mask || pixel_mask[(size_t)y * Wt + x])
+            lst[cur[(size_t)y * Wt + x]++] = (uint32_t)q;
+    }
+    int oom = 0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (size_t p = 0; p < nt; ++p) {
+      const size_t m = cnt[p + 1] - cnt[p];
+      orc_ewa_entry *e = (orc_ewa_entry *)malloc(sizeof(orc_ewa_entry) * (m ? m : 1));
+      if (!e) {
+        oom = 1;
+        continue;
+      }
+      for (size_t t = 0; t < m; ++t) e[t] = g[lst[cnt[p] + t]];
+      qsort(e, m, sizeof(orc_ewa_entry), ewa_cmp);
+      const real px = (real)(int)(p % Wt) + (real)0.5, py = (real)(int)(p / Wt) + (real)0.5;
+      real T = 1, col[3] = {0, 0, 0}, zs = 0;
+      for (size_t t = 0; t < m; ++t) {
+        const real dx = px - e[t].u, dy = py - e[t].v;
+        if (!(RABS(dx) <= rmax && RABS(dy) <= rmax)) continue;
+        const real power = RFMA(e[t].Bn, dx * dy, RFMA(e[t].Ah, dx * dx, e[t].Ch * (dy * dy)));
+        if (power > 0) continue;
+#ifdef ORC_DOUBLE
+        const real G = exp(power);
+#else
+        const real G = orc_exp_cw(power);
+#endif
+        const real al = RMIN((real)0.99, G);
+        if (al < amin) continue;
+        const real tt = T * ((real)1 - al);
+        if (tt < (real)1e-4) break;
+        const real w = al * T;
+        for (int ch = 0; ch < 3; ++ch) col[ch] = RFMA(e[t].c[ch], w, col[ch]);
+        zs = RFMA(e[t].z, w, zs);
+        T = tt;
+      }
+      for (int ch = 0; ch < 3; ++ch) out_rgb[(3 * (size_t)k + ch) * nt + p] = col[ch];
+      out_alpha[(size_t)k * nt + p] = (real)1 - T;
+      out_depth[(size_t)k * nt + p] = T < 1 ? zs / ((real)1 - T) : (real)0;
+      free(e);
+    }
+    free(lst);
+    free(cur);
+    free(g);
+    free(box);
+    if (oom) {
+      free(cnt);
+      return -2;
+    }
+  }
+  free(cnt);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------

@@ -18,6 +18,7 @@ GRADS = "tests/test_oracle_gradients.py"
 TEMPORAL = "tests/test_oracle_temporal.py"
 MARCH = "tests/test_oracle_raymarch.py"
 NET = "tests/test_oracle_netinputs.py"
+EWA = "tests/test_oracle_ewa.py"
 MUTANTS = [
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
@@ -101,6 +102,35 @@ MUTANTS = [
      "const real aw = (real)w[k * n + p];", NET),
     ("blend_bg_swapped", "RFMA(wb, (real)rgb_bg[c * n + p], ((real)1 - wb) * fg);",
      "RFMA((real)1 - wb, (real)rgb_bg[c * n + p], wb * fg);", NET),
+    ("exp_poly_coefficient", "p = fmaf(p, r, 1.0f / 24.0f);", "p = fmaf(p, r, 1.0f / 20.0f);",
+     EWA),
+    ("exp_reduction_tail", "r = fmaf(-n, 1.42860677e-6f, r);", "", EWA),
+    ("ewa_no_lowpass_x", "const real sxx = s2 * ((real)1 + a * a) + lp;",
+     "const real sxx = s2 * ((real)1 + a * a);", EWA),
+    ("ewa_jacobian_wrong_axis", "const real sxx = s2 * ((real)1 + a * a) + lp;",
+     "const real sxx = s2 * ((real)1 + b * b) + lp;", EWA),
+    ("ewa_cross_sign", "g[q].Bn = sxy / det;", "g[q].Bn = -sxy / det;", EWA),
+    ("ewa_conic_transposed", "g[q].Ah = ((real)-0.5 * syy) / det;",
+     "g[q].Ah = ((real)-0.5 * sxx) / det;", EWA),
+    ("ewa_focal_ratio_dropped",
+     "(real)((double)sp->sigma_px * (double)tgt->fx / (double)src[k].fx);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    orc_ewa_entry",
+     "(real)((double)sp->sigma_px);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    orc_ewa_entry",
+     EWA),
+    ("ewa_no_alpha_cap", "const real al = RMIN((real)0.99, G);", "const real al = G;", EWA),
+    ("ewa_no_alpha_floor", "if (al < amin) continue;", "", EWA),
+    ("ewa_stop_skips", "if (tt < (real)1e-4) break;", "if (tt < (real)1e-4) continue;", EWA),
+    ("ewa_no_stop", "if (tt < (real)1e-4) break;", "", EWA),
+    ("ewa_back_to_front", "return a < b ? -1 : (a > b ? 1 : 0);",
+     "return a < b ? 1 : (a > b ? -1 : 0);", EWA),
+    ("ewa_ties_reversed", "g[q].key = ((uint64_t)f32_bits((float)X[2]) << 32) | (uint32_t)q;",
+     "g[q].key = ((uint64_t)f32_bits((float)X[2]) << 32) | (uint32_t)(ns - 1 - q);", EWA),
+    ("ewa_depth_unnormalised", "T < 1 ? zs / ((real)1 - T) : (real)0;", "T < 1 ? zs : (real)0;",
+     EWA),
+    ("ewa_weight_after_update", "const real w = al * T;", "const real w = al * tt;", EWA),
+    ("ewa_no_clip", "if (!(RABS(dx) <= rmax && RABS(dy) <= rmax)) continue;", "", EWA),
+    ("ewa_corner_pixels",
+     "const real px = (real)(int)(p % Wt) + (real)0.5, py = (real)(int)(p / Wt) + (real)0.5;",
+     "const real px = (real)(int)(p % Wt), py = (real)(int)(p / Wt) + (real)0.5;", EWA),
 ]
 
 
