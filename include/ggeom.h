@@ -100,7 +100,8 @@ enum {
   GG_OP_SPLAT_BACKWARD = 2,
   GG_OP_TSDF_INTEGRATE = 3,
   GG_OP_TSDF_INTEGRATE_BACKWARD = 4,
-  GG_OP_DIFFERENCE_MASKS = 5 /* src_w x src_h frames, num_bins = the mask factor  */
+  GG_OP_DIFFERENCE_MASKS = 5, /* src_w x src_h frames, num_bins = the mask factor */
+  GG_OP_SPLAT_EWA = 6
 };
 
 /* Bytes of workspace `op` needs for K source views of src_w x src_h pixels, a
@@ -173,6 +174,43 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
                          const float *out_tape, const float *g_rgb, const float *g_depth,
                          const float *g_alpha, float *g_depth_in, float *g_rgb_in, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * splat_views_ewa -- the per-pixel Gaussians of splat_views rendered as the
+ * 3D Gaussian splatting rasteriser renders them (§3.1): projected with the
+ * local affine (EWA) approximation of the perspective map and alpha-
+ * composited front to back, each view into its own target images.
+ *
+ * Source pixel q of view k with usable depth D and target point (x_T, y_T,
+ * z_T) (dropped unless z_T > z_min) is a Gaussian with mean (u, v) =
+ * (x_T, y_T) / z_T and image covariance
+ *   S = sig^2 [[1 + a^2, r a b], [r a b, r^2 (1 + b^2)]] + lowpass I,
+ * a = (u - cx) / fx, b = (v - cy) / fy, r = fy / fx (target intrinsics),
+ * sig = sigma_px (fx_T / fx_k) (D / z_T): the perspective Jacobian applied to
+ * an isotropic 3D Gaussian of std sigma_px D / fx_k (one source pixel), plus
+ * the rasteriser's screen-space low-pass (0.3 px^2 there).  At target pixel
+ * centre p, d = p - (u, v): alpha = min(0.99, exp(-d^T S^-1 d / 2)); the term
+ * is skipped when alpha < 1/255 or when |d_x| or |d_y| exceeds r_max_px (the
+ * clip that bounds the footprint).  Per pixel the terms are taken in
+ * ascending (z_T in FP32, q) order, colour += c alpha T, depth += z_T alpha
+ * T, T *= (1 - alpha), stopping before the first term that would bring T
+ * below 1e-4.  out_rgb = the colour sum (c = rgb / 255), out_alpha = 1 - T,
+ * out_depth = depth sum / (1 - T) (0 where no term was taken).  band_rel is
+ * not used.
+ * Every step is FP32 in a fixed order with no contraction, including the
+ * exponential (Cody-Waite reduction, degree-6 Taylor polynomial, within 3
+ * ulp): the outputs are bitwise reproducible, independent of the launch.
+ *
+ * src, K, depth, rgb, tgt, prm: as splat_views.  lowpass >= 0 (px^2).
+ * out_rgb float K x 3 x tgt_h x tgt_w; out_alpha, out_depth float
+ * K x tgt_h x tgt_w: overwritten.  ws: gg_workspace_size(GG_OP_SPLAT_EWA,
+ * ...), 256-byte aligned; it holds the Gaussians' records and per-tile key
+ * lists (about 16 K src_w src_h 16-byte words for r_max_px = 8).
+ * ------------------------------------------------------------------------- */
+int splat_views_ewa(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                    const gg_camera *tgt, const gg_splat_params *prm, float lowpass,
+                    float *out_rgb, float *out_alpha, float *out_depth, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * tsdf_raymarch -- the volume-free form of the fusion (Suppl. A.1): per
@@ -415,6 +453,12 @@ int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
  * depend on it; it exists for the autotuner.  Process-wide.  Returns
  * GG_ERR_INVALID for any other value. */
 int gg_set_volume_vector(int bins_per_thread);
+
+/* Longest per-tile key list splat_views_ewa sorts in LDS in one piece
+ * (64..1024; 0 restores 1024); longer lists are sorted as runs of the
+ * largest power of two not above it, merged in global memory.  Results do
+ * not depend on it; it exists to exercise both paths.  Process-wide. */
+int gg_set_ewa_sort_limit(int keys);
 
 /* Self-check of the correctly rounded reciprocal the fusion kernels use for
  * 1/z: for every FP32 value with biased exponent in [e_lo, e_hi] (all 2^23

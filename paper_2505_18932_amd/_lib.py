@@ -22,6 +22,7 @@ GG_OP_SPLAT_BACKWARD = 2
 GG_OP_TSDF_INTEGRATE = 3
 GG_OP_TSDF_INTEGRATE_BACKWARD = 4
 GG_OP_DIFFERENCE_MASKS = 5
+GG_OP_SPLAT_EWA = 6
 
 
 class GGCamera(C.Structure):
@@ -73,6 +74,7 @@ SIGNATURES = {
     "splat_views": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, SZ, P]),
     "splat_views_masked": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, SZ,
                                      P]),
+    "splat_views_ewa": (C.c_int, [CAM, I32, P, P, CAM, SPP, C.c_float, P, P, P, P, SZ, P]),
     "splat_views_backward": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, P,
                                        SZ, P]),
     "difference_masks": (C.c_int, [I32, I32, I32, P, P, C.POINTER(GGMaskParams), P, P, P, P, P,
@@ -91,6 +93,7 @@ SIGNATURES = {
     "gg_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gg_set_volume_tile": (C.c_int, [C.c_int, C.c_int]),
     "gg_set_volume_vector": (C.c_int, [C.c_int]),
+    "gg_set_ewa_sort_limit": (C.c_int, [C.c_int]),
     "gg_selftest_reciprocal": (C.c_int, [I32, I32, P, P]),
     "gg_batch_create": (C.c_int, [C.POINTER(GGBatchItem), I32, C.POINTER(GGBatchTuning),
                                   C.POINTER(C.c_void_p)]),

@@ -12,6 +12,7 @@
 
 #include "batch_internal.h"
 #include "ggeom_internal.h"
+#include "ewa_internal.h"
 
 namespace gg {
 
@@ -222,6 +223,36 @@ static SplatLayout splat_layout(int K, int sw, int sh, int tw, int th, const gg_
   return L;
 }
 
+struct EwaLayout {
+  uint32_t ntx, nty, ntiles, cap;
+  size_t count, offset, cursor, keys, keys_alt, rec, total;
+};
+
+static EwaLayout ewa_layout(int K, int sw, int sh, int tw, int th, const gg_splat_params *sp) {
+  EwaLayout L{};
+  L.ntx = (uint32_t)((tw + kEwaTile - 1) / kEwaTile);
+  L.nty = (uint32_t)((th + kEwaTile - 1) / kEwaTile);
+  L.ntiles = L.ntx * L.nty;
+  const size_t n = (size_t)K * L.ntiles;
+  const size_t cap = (size_t)K * sw * sh * ewa_tiles_per_splat(sp->r_max_px);
+  L.cap = cap > 0xffffffffull ? 0xffffffffu : (uint32_t)cap;
+  size_t o = 0;
+  L.count = o;
+  o += up256(4 * (n + 1));
+  L.offset = o;
+  o += up256(4 * (n + 1));
+  L.cursor = o;
+  o += up256(4 * (n + 1));
+  L.keys = o;
+  o += up256(8 * cap);
+  L.keys_alt = o;
+  o += up256(8 * cap);
+  L.rec = o;
+  o += up256(32 * (size_t)K * sw * sh);
+  L.total = o;
+  return L;
+}
+
 struct TsdfLayout {
   size_t table, bins, acc, gnu, total;
 };
@@ -329,6 +360,9 @@ size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_
     case GG_OP_TSDF_INTEGRATE_BACKWARD:
       if (num_bins < 2) return 0;
       return tsdf_layout(K, src_w, src_h, num_bins, true).total;
+    case GG_OP_SPLAT_EWA:
+      if (!sp || check_splat(sp, "gg_workspace_size")) return 0;
+      return ewa_layout(K, src_w, src_h, tgt_w, tgt_h, sp).total;
     case GG_OP_DIFFERENCE_MASKS:  // num_bins carries gg_mask_params.factor
       if (num_bins < 1 || num_bins > 16) return 0;
       return mask_ws_bytes(K, src_w, src_h, num_bins);
@@ -446,6 +480,76 @@ int splat_views_masked(const gg_camera *src, int32_t K, const float *depth, cons
   a.out_mask = out_mask;
   a.out_mask_max = out_mask_max;
   return launch_splat_forward(a, (hipStream_t)stream);
+}
+
+static uint32_t g_ewa_sort_limit = kEwaSortCap;
+
+int gg_set_ewa_sort_limit(int keys) {
+  if (keys != 0 && (keys < 64 || keys > (int)kEwaSortCap))
+    return fail(GG_ERR_INVALID, "gg_set_ewa_sort_limit: %d outside 64..%u", keys, kEwaSortCap);
+  g_ewa_sort_limit = keys == 0 ? kEwaSortCap : (uint32_t)keys;
+  return GG_OK;
+}
+
+int splat_views_ewa(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
+                    const gg_camera *tgt, const gg_splat_params *prm, float lowpass,
+                    float *out_rgb, float *out_alpha, float *out_depth, void *ws,
+                    size_t ws_bytes, void *stream) {
+  const char *W = "splat_views_ewa";
+  if (int rc = check_sources(src, K, W)) return rc;
+  if (int rc = check_camera(tgt, W)) return rc;
+  if (int rc = check_splat(prm, W)) return rc;
+  if (!(lowpass >= 0.0f) || !finite_f(lowpass))
+    return fail(GG_ERR_INVALID, "%s: lowpass must be finite and >= 0", W);
+  if (!depth || !rgb || !out_rgb || !out_alpha || !out_depth)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", W);
+  const int sw = src[0].width, sh = src[0].height;
+  if ((size_t)K * sw * sh * ewa_tiles_per_splat(prm->r_max_px) > 0xffffffffull ||
+      (size_t)K * sw * sh > 0x7fffffffull)
+    return fail(GG_ERR_UNSUPPORTED, "%s: too many source pixels", W);
+  const EwaLayout L = ewa_layout(K, sw, sh, tgt->width, tgt->height, prm);
+  if (int rc = check_ws(ws, ws_bytes, L.total, W)) return rc;
+  char *w = (char *)ws;
+  EwaArgs a{};
+  for (int k = 0; k < K; ++k) {
+    relproj(src[k], *tgt, a.views[k].P);
+    a.views[k].sscale = (float)((double)prm->sigma_px * (double)tgt->fx / (double)src[k].fx);
+  }
+  const double rd = (double)tgt->fy / (double)tgt->fx;
+  a.depth = depth;
+  a.rgb = rgb;
+  a.K = K;
+  a.Ws = sw;
+  a.Hs = sh;
+  a.Wt = tgt->width;
+  a.Ht = tgt->height;
+  a.ns = (uint32_t)(sw * sh);
+  a.nt = (uint32_t)(tgt->width * tgt->height);
+  a.ws_div = make_fastdiv((uint32_t)sw);
+  a.ntx = (int)L.ntx;
+  a.nty = (int)L.nty;
+  a.ntiles = L.ntiles;
+  a.fx = tgt->fx;
+  a.fy = tgt->fy;
+  a.cx = tgt->cx;
+  a.cy = tgt->cy;
+  a.ry = (float)rd;
+  a.ry2 = (float)(rd * rd);
+  a.lowpass = lowpass;
+  a.zmin = prm->z_min;
+  a.rmax = prm->r_max_px;
+  a.tile_count = (uint32_t *)(w + L.count);
+  a.tile_offset = (uint32_t *)(w + L.offset);
+  a.tile_cursor = (uint32_t *)(w + L.cursor);
+  a.keys = (unsigned long long *)(w + L.keys);
+  a.keys_alt = (unsigned long long *)(w + L.keys_alt);
+  a.cap = L.cap;
+  a.rec = (float4 *)(w + L.rec);
+  a.sort_limit = g_ewa_sort_limit;
+  a.out_rgb = out_rgb;
+  a.out_alpha = out_alpha;
+  a.out_depth = out_depth;
+  return launch_splat_ewa(a, (hipStream_t)stream);
 }
 
 int difference_masks(int32_t K, int32_t width, int32_t height, const uint8_t *rgb,

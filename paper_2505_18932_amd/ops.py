@@ -164,6 +164,42 @@ def splat_views(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *, tap
     return dict(win_idx=win, depth=od, rgb=orgb, alpha=oa, tape=ot, mask=om, mask_max=omax)
 
 
+def splat_views_ewa(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *,
+                    lowpass=0.3, out=None, ws=None, stream=None):
+    """Front-to-back compositing of the EWA-projected per-pixel Gaussians of
+    K views into the target (see include/ggeom.h).  Returns dict(rgb (K, 3,
+    Ht, Wt), alpha, depth (K, Ht, Wt))."""
+    dev = _device(depth)
+    sa, tg, sp = cameras(src), camera(tgt), splat_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th = tg.width, tg.height
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    _need(rgb, torch.uint8, (K, sh, sw, 3), "rgb", dev)
+    o = out or {}
+
+    def buf(key, shape):
+        t = o.get(key)
+        return torch.empty(shape, dtype=torch.float32, device=dev) if t is None else \
+            _need(t, torch.float32, shape, key, dev)
+
+    orgb = buf("rgb", (K, 3, th, tw))
+    oa = buf("alpha", (K, th, tw))
+    od = buf("depth", (K, th, tw))
+    need = workspace_size(L.GG_OP_SPLAT_EWA, K, sw, sh, tw, th, 2, sp)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().splat_views_ewa(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
+                                    float(lowpass), _ptr(orgb), _ptr(oa), _ptr(od), _ptr(wsb),
+                                    wsn, _stream(dev, stream)))
+    return dict(rgb=orgb, alpha=oa, depth=od)
+
+
+def set_ewa_sort_limit(keys: int) -> None:
+    """Longest tile list splat_views_ewa sorts in LDS at once (64..1024, 0 =
+    default); results do not depend on it."""
+    L.check(L.lib().gg_set_ewa_sort_limit(int(keys)))
+
+
 def difference_masks(rgb: torch.Tensor, rgb_prev: torch.Tensor, params=None, *, depth=None,
                      depth_prev=None, mask=None, filtered=None, ws=None, stream=None):
     """Soft colour-difference masks (K, H, W) between frames t and t - 1

@@ -197,8 +197,34 @@ def test_tsdf_rejects_invalid_arguments():
         L.GG_ERR_INVALID
 
 
+def test_ewa_splat_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    sp = ops.splat_params(scenes.splat_params())
+    args = lambda K, d=FAKE, prm=sp, lp=0.3, ws=FAKE, nws=1 << 40, o=FAKE: (
+        src, K, d, FAKE, C.byref(tgt), C.byref(prm), lp, o, FAKE, FAKE, ws, nws, None)
+    assert lib.splat_views_ewa(*args(0)) == L.GG_ERR_INVALID
+    rc, msg = _err(lib.splat_views_ewa(*args(2, d=None)))
+    assert rc == L.GG_ERR_INVALID and "NULL" in msg
+    assert lib.splat_views_ewa(*args(2, o=None)) == L.GG_ERR_INVALID
+    for lp in (-0.1, float("nan"), float("inf")):
+        rc, msg = _err(lib.splat_views_ewa(*args(2, lp=lp)))
+        assert rc == L.GG_ERR_INVALID and "lowpass" in msg
+    bad = ops.splat_params(scenes.splat_params(r_max_px=0.0))
+    assert lib.splat_views_ewa(*args(2, prm=bad)) == L.GG_ERR_INVALID
+    rc, msg = _err(lib.splat_views_ewa(*args(2, nws=16)))
+    assert rc == L.GG_ERR_WORKSPACE and "need" in msg
+    assert lib.splat_views_ewa(*args(2, ws=None)) == L.GG_ERR_WORKSPACE
+    rc = lib.splat_views_ewa(*args(2, ws=C.c_void_p((1 << 20) + 8)))
+    assert rc == L.GG_ERR_WORKSPACE
+
+
 def test_launch_shape_setters_validate():
     lib = L.lib()
+    for bad in (-1, 1, 63, 1025, 4096):
+        assert lib.gg_set_ewa_sort_limit(bad) == L.GG_ERR_INVALID
+    for ok in (64, 100, 1024, 0):
+        assert lib.gg_set_ewa_sort_limit(ok) == L.GG_OK
     for bad in (-1, 3, 5, 16):
         assert lib.gg_set_volume_vector(bad) == L.GG_ERR_INVALID
     for ok in (0, 1, 2, 4, 8, 0):
@@ -217,6 +243,11 @@ def test_workspace_sizes():
         4 * 1280 * 720 * 8
     assert ops.workspace_size(L.GG_OP_TSDF_INTEGRATE_BACKWARD, 4, 1280, 720, 1280, 720, 128) > \
         ops.workspace_size(L.GG_OP_TSDF_INTEGRATE, 4, 1280, 720, 1280, 720, 128)
+    e = ops.workspace_size(L.GG_OP_SPLAT_EWA, 4, 1280, 720, 1280, 720, 2, sp)
+    # two 8-byte keys per list entry, up to 16 tiles per Gaussian at r_max 8, plus
+    # 32-byte records
+    assert e >= 4 * 1280 * 720 * (2 * 8 * 16 + 32)
+    assert ops.workspace_size(L.GG_OP_SPLAT_EWA, 4, 1280, 720, 1280, 720, 2, None) == 0
     assert ops.workspace_size(L.GG_OP_SPLAT, 0, 1280, 720, 1280, 720, 2, sp) == 0
     assert ops.workspace_size(99, 4, 1280, 720, 1280, 720, 2, sp) == 0
 
