@@ -478,6 +478,9 @@ int gg_fast_reciprocal(const float *in, float *out, int64_t n, void *stream);
  * and the number of launches of kernels whose name contains `name` (all if
  * NULL) since the last gg_timing_reset. */
 int gg_timing_enable(int on);
+/* Restrict the timing to kernels whose name contains `name` (NULL or "":
+ * all), so that a timed region brackets only the launches it reports. */
+int gg_timing_filter(const char *name);
 int gg_timing_reset(void);
 int gg_timing_read(const char *name, double *total_ms, int64_t *launches);
 

@@ -89,6 +89,7 @@ SIGNATURES = {
     "gg_last_error": (C.c_char_p, []),
     "gg_relative_projection": (C.c_int, [CAM, CAM, P, P]),
     "gg_timing_enable": (C.c_int, [C.c_int]),
+    "gg_timing_filter": (C.c_int, [C.c_char_p]),
     "gg_timing_reset": (C.c_int, []),
     "gg_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gg_set_volume_tile": (C.c_int, [C.c_int, C.c_int]),

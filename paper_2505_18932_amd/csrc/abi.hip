@@ -46,6 +46,7 @@ struct TimedLaunch {
 };
 std::mutex g_tmu;
 bool g_timing = false;
+std::string g_timing_only;  // time only kernels whose name contains this (empty: all)
 std::vector<TimedLaunch> g_launches;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -64,6 +65,7 @@ hipEvent_t take_event() {
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), stream_(s), slot_(-1) {
   std::lock_guard<std::mutex> lk(g_tmu);
   if (!g_timing) return;
+  if (!g_timing_only.empty() && !strstr(name, g_timing_only.c_str())) return;
   TimedLaunch t{name, take_event(), take_event()};
   if (!t.start || !t.stop) return;
   if (hipEventRecord(t.start, s) != hipSuccess) return;
@@ -972,6 +974,12 @@ int gg_fast_reciprocal(const float *in, float *out, int64_t n, void *stream) {
 int gg_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
   g_timing = on != 0;
+  return GG_OK;
+}
+
+int gg_timing_filter(const char *name) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing_only = name ? name : "";
   return GG_OK;
 }
 

@@ -414,7 +414,10 @@ def relative_projection(a, b):
 # kernel timing (profiling)
 
 
-def timing_enable(on=True):
+def timing_enable(on=True, only=None):
+    """Bracket kernel launches with HIP events; ``only`` restricts it to the
+    kernels whose name contains that string."""
+    L.check(L.lib().gg_timing_filter(None if only is None else only.encode()))
     L.check(L.lib().gg_timing_enable(1 if on else 0))
 
 
