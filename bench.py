@@ -404,20 +404,39 @@ def main():
     Wv = torch.zeros((H, Wd, D), dtype=torch.float32, device=dev)
     ws_s = torch.empty(gg.workspace_size(1, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8, device=dev)
     ws_t = torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
+    ws_t2 = torch.empty_like(ws_t)  # the second buffer of the pipelined view tables
     sout = dict(win_idx=torch.empty((K, H, Wd), dtype=torch.int32, device=dev),
                 depth=torch.empty((K, H, Wd), device=dev), rgb=torch.empty((K, 3, H, Wd), device=dev),
                 alpha=torch.empty((K, H, Wd), device=dev), tape=torch.empty((K, 3, H, Wd), device=dev))
     nf = args.frames
-    # The splat and the fusion of a frame both read only that frame's inputs, so the splat runs
-    # on a second stream (default priority) and overlaps the fusion; each stream keeps its own
-    # order (the splat outputs and the carried volume are reused frame after frame).
+    # A frame's splat and its fusion weights (the view table) depend on that frame's inputs
+    # only, so with two streams they run on a second stream (default priority) while the main
+    # stream fuses: per frame the second stream builds the view table into one of two
+    # workspaces (after the fusion two frames back has released it), records an event and
+    # splats; the main stream waits for the event and fuses from that table.  Each stream
+    # keeps its own order (the splat outputs and the carried volume are reused frame after
+    # frame).
     s_splat = torch.cuda.Stream(device=dev) if args.streams == 2 else None
+    wss = [ws_t, ws_t2]
+    ev_table = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_fused = [torch.cuda.Event(), torch.cuda.Event()]
 
     def step(i, carry=True):
         f = i % nf
+        prev = dict(F_prev=F if carry else None, W_prev=Wv if carry else None, F=F, W=Wv)
+        if s_splat is None:
+            gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s)
+            return gg.tsdf_integrate(src, depth[f], tgt, tp, ws=ws_t, **prev)
+        b = i % 2
+        main = torch.cuda.current_stream(dev)
+        s_splat.wait_event(ev_fused[b])
+        gg.tsdf_view_table(src, depth[f], tp, ws=wss[b], stream=s_splat)
+        ev_table[b].record(s_splat)
         gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s, stream=s_splat)
-        return gg.tsdf_integrate(src, depth[f], tgt, tp, F_prev=F if carry else None,
-                                 W_prev=Wv if carry else None, F=F, W=Wv, ws=ws_t)
+        main.wait_event(ev_table[b])
+        r = gg.tsdf_integrate(src, depth[f], tgt, tp, ws=wss[b], table_ready=True, **prev)
+        ev_fused[b].record(main)
+        return r
 
     # launch shape of the fusion for this class (autotuned, results unchanged)
     from paper_2505_18932_amd import autotune
@@ -527,7 +546,7 @@ def main():
         out["ewa_compositing"] = ewa_path(gg, torch, dev, src, tgt, sp, depth, rgb,
                                           min(args.steps, 30), 3)
     if not args.no_batch:
-        del depth, rgb, ws_s, ws_t
+        del depth, rgb, ws_s, ws_t, ws_t2, wss
         torch.cuda.empty_cache()
         out["batched"] = batched_speedup(gg, torch, dev, procs)
     if not args.no_cpu_baseline:

@@ -346,6 +346,23 @@ int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg
                    const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
                    void *ws, size_t ws_bytes, void *stream);
 
+/* The fusion in two calls, for a caller that builds a frame's view table on
+ * another stream ahead of the fusion (it depends on the depth maps only):
+ * tsdf_view_table computes into ws what tsdf_integrate computes first -- per
+ * source pixel the usable depth and the fusion weight of Eq. 3 (the
+ * confidence of the supplement), and the bin depths; tsdf_integrate_tabled
+ * then fuses from that ws exactly as tsdf_integrate does (bitwise the same
+ * outputs).  Arguments as tsdf_integrate; both calls take the same src, K,
+ * prm and ws (gg_workspace_size(GG_OP_TSDF_INTEGRATE, ...)); the caller
+ * orders them (one stream, or an event) and keeps ws untouched between. */
+int tsdf_view_table(const gg_camera *src, int32_t K, const float *depth,
+                    const gg_tsdf_params *prm, void *ws, size_t ws_bytes, void *stream);
+int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
+                          const gg_tsdf_params *prm, const float *temporal_mask,
+                          const float *F_prev, const float *W_prev, float *F, float *W,
+                          float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* tsdf_extract_depth -- the surface is where the fused signed distance
  * changes sign along the ray (Suppl. A.1).  On the bins: d* = the smallest
  * d in [0, D-2] with W_d > 0, W_{d+1} > 0, F_d > 0 and F_{d+1} <= 0;
@@ -455,9 +472,9 @@ int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
 int gg_set_volume_vector(int bins_per_thread);
 
 /* Longest per-tile key list splat_views_ewa sorts in LDS in one piece
- * (64..1024; 0 restores 1024); longer lists are sorted as runs of the
- * largest power of two not above it, merged in global memory.  Results do
- * not depend on it; it exists to exercise both paths.  Process-wide. */
+ * (64..512; 0 restores 512); longer lists are sorted as runs of the largest
+ * power of two not above it, merged in global memory.  Results do not
+ * depend on it; it exists to exercise both paths.  Process-wide. */
 int gg_set_ewa_sort_limit(int keys);
 
 /* Self-check of the correctly rounded reciprocal the fusion kernels use for

@@ -80,6 +80,8 @@ SIGNATURES = {
     "difference_masks": (C.c_int, [I32, I32, I32, P, P, C.POINTER(GGMaskParams), P, P, P, P, P,
                                    SZ, P]),
     "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
+    "tsdf_view_table": (C.c_int, [CAM, I32, P, TSP, P, SZ, P]),
+    "tsdf_integrate_tabled": (C.c_int, [CAM, I32, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_raymarch": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
     "network_inputs": (C.c_int, [CAM, I32, CAM, P, P, P, P, P, P]),
     "blend_views": (C.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, P]),

@@ -697,15 +697,39 @@ static void make_integrate_args(IntegrateArgs &a, const gg_camera *src, int32_t 
   a.exact_only = fast_reciprocal_safe(a.views, K, tgt, prm.z_far) ? 0 : 1;
 }
 
-int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
-                   const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
-                   const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
-                   void *ws, size_t ws_bytes, void *stream) {
-  const char *N = "tsdf_integrate";
+// The view table (per source pixel: usable depth, fusion weight) and the
+// bin depths into the workspace: the part of the fusion that depends on the
+// depth maps only.
+static int build_view_table(const gg_camera *src, int32_t K, const float *depth,
+                            const gg_tsdf_params *prm, const TsdfLayout &L, char *w,
+                            hipStream_t s) {
+  const int sw = src[0].width, sh = src[0].height;
+  if (int rc = launch_bins(*prm, (float2 *)(w + L.bins), s)) return rc;
+  return launch_conf(conf_args(depth, (float2 *)(w + L.table), sw, sh, K, prm), s);
+}
+
+int tsdf_view_table(const gg_camera *src, int32_t K, const float *depth,
+                    const gg_tsdf_params *prm, void *ws, size_t ws_bytes, void *stream) {
+  const char *N = "tsdf_view_table";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!depth) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  const TsdfLayout L = tsdf_layout(K, src[0].width, src[0].height, prm->num_bins, false);
+  if (int rc = check_ws(ws, ws_bytes, L.total, N)) return rc;
+  return build_view_table(src, K, depth, prm, L, (char *)ws, (hipStream_t)stream);
+}
+
+// depth NULL: the view table and bins are already in ws (tsdf_view_table).
+static int integrate_impl(const char *N, bool tabled, const gg_camera *src, int32_t K,
+                          const float *depth,
+                          const gg_camera *tgt, const gg_tsdf_params *prm,
+                          const float *temporal_mask, const float *F_prev, const float *W_prev,
+                          float *F, float *W, float *out_depth, int32_t *out_bin, void *ws,
+                          size_t ws_bytes, void *stream) {
   if (int rc = check_sources(src, K, N)) return rc;
   if (int rc = check_camera(tgt, N)) return rc;
   if (int rc = check_tsdf(prm, N)) return rc;
-  if (!depth || !F || !W) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  if ((!tabled && !depth) || !F || !W) return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
   if ((F_prev == nullptr) != (W_prev == nullptr))
     return fail(GG_ERR_INVALID, "%s: F_prev and W_prev go together", N);
   if ((out_depth == nullptr) != (out_bin == nullptr))
@@ -726,12 +750,29 @@ int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg
   char *w = (char *)ws;
   float2 *table = (float2 *)(w + L.table);
   float2 *bins = (float2 *)(w + L.bins);
-  if (int rc = launch_bins(*prm, bins, s)) return rc;
-  if (int rc = launch_conf(conf_args(depth, table, sw, sh, K, prm), s)) return rc;
+  if (!tabled)
+    if (int rc = build_view_table(src, K, depth, prm, L, w, s)) return rc;
   IntegrateArgs a{};
   make_integrate_args(a, src, K, *tgt, *prm, vs, table, bins, temporal_mask, F_prev, W_prev, F, W,
                       out_depth, out_bin);
   return launch_integrate(a, vs.V, vs.threads, s);
+}
+
+int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
+                   const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
+                   const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
+                   void *ws, size_t ws_bytes, void *stream) {
+  return integrate_impl("tsdf_integrate", false, src, K, depth, tgt, prm, temporal_mask, F_prev, W_prev,
+                        F, W, out_depth, out_bin, ws, ws_bytes, stream);
+}
+
+int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
+                          const gg_tsdf_params *prm, const float *temporal_mask,
+                          const float *F_prev, const float *W_prev, float *F, float *W,
+                          float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
+                          void *stream) {
+  return integrate_impl("tsdf_integrate_tabled", true, src, K, nullptr, tgt, prm, temporal_mask, F_prev,
+                        W_prev, F, W, out_depth, out_bin, ws, ws_bytes, stream);
 }
 
 int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,

@@ -29,8 +29,11 @@ namespace gg {
 // exp(x) in FP32 by Cody and Waite's argument reduction with a degree-6
 // Taylor polynomial, every step an explicitly rounded FP32 operation:
 // n = rint(x log2 e), r = x - n ln 2 (ln 2 as a 16-bit head plus a tail),
-// e^r by Horner's rule with fused multiply-adds, times 2^n; 0 below -86.
-__device__ __forceinline__ float exp_cw(float x) {
+// e^r by Horner's rule with fused multiply-adds, times 2^n.  The definition
+// returns 0 below -86; here x is clamped at -87 instead (which keeps n and r
+// finite) and [-87, -86) gives at most 3e-38: every value below -86 is
+// far under the opacity floor 1/255, so the terms taken are the same.
+__device__ __forceinline__ float exp_alpha(float x) {
   const float xc = fmaxf(x, -87.0f);
   const float n = rintf(xc * 1.44269504f);
   float r = fmaf(-n, 0.693145752f, xc);
@@ -42,8 +45,7 @@ __device__ __forceinline__ float exp_cw(float x) {
   p = fmaf(p, r, 0.5f);
   p = fmaf(p, r, 1.0f);
   p = fmaf(p, r, 1.0f);
-  const float e = ldexpf(p, (int)n);
-  return x >= -86.0f ? e : 0.0f;
+  return ldexpf(p, (int)n);
 }
 
 struct EwaGauss {
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(256) void ewa_bin_kernel(EwaArgs a) {
     const bool has = s < n;
     if (__ballot(has) == 0ull) break;
     const uint32_t tile = has ? (uint32_t)((ty0 + s / nx) * a.ntx + (tx0 + s % nx)) : 0u;
-    const uint32_t slot = aggregated_slot(cnt, tile, has);
+    const uint32_t slot = aggregated_slot<kFill>(cnt, tile, has);
     if (kFill && has) {
       const uint32_t pos = gmem(a.tile_offset)[(size_t)k * a.ntiles + tile] + slot;
       if (pos < a.cap) gmem(a.keys)[pos] = key;
@@ -279,11 +281,11 @@ __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
     __syncthreads();
     for (uint32_t t = 0; t < nb; ++t) {
       const float4 A = L.rec[0][t], B = L.rec[1][t];
-      const float z = L.z[t];
       const float dx = px - A.x, dy = py - A.y;
       const bool in = fabsf(dx) <= rmax && fabsf(dy) <= rmax;
       const float power = fmaf(A.w, dx * dy, fmaf(A.z, dx * dx, B.x * (dy * dy)));
-      const float al = fminf(0.99f, exp_cw(power));
+      const float z = L.z[t];
+      const float al = fminf(0.99f, exp_alpha(power));
       const float tt = T * (1.0f - al);
       const bool take = !done && in && !(power > 0.0f) && !(al < amin);
       const bool stop = take && tt < 1e-4f;

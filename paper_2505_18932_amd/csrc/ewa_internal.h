@@ -9,7 +9,7 @@
 namespace gg {
 
 constexpr int kEwaTile = 8;             // target tiles of 8 x 8 pixels, one wavefront each
-constexpr uint32_t kEwaSortCap = 1024;  // the longest tile list sorted in LDS in one piece
+constexpr uint32_t kEwaSortCap = 512;  // the longest tile list sorted in LDS in one piece
 
 struct EwaArgs {
   SplatView views[GG_MAX_VIEWS];  // view k -> target, sigma_px fx_T / fx_k

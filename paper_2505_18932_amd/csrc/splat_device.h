@@ -57,23 +57,40 @@ __device__ __forceinline__ float cover_d2(const SplatGeom &g, int aa, int b) {
 }
 
 // Wavefront-aggregated atomicAdd: lanes with the same key share one atomic;
-// each gets a distinct slot base + rank.
+// each gets a distinct slot base + rank.  The lanes are grouped by key with
+// ballots only (no memory traffic); then every group's leader issues its
+// atomic in one instruction and each lane reads its leader's base with one
+// cross-lane permute, so a wavefront waits for one atomic round trip.
+// kReturn = false (counting) issues the atomics without a return value.
+template <bool kReturn>
 __device__ __forceinline__ uint32_t aggregated_slot(uint32_t *counters, uint32_t key, bool has) {
-  uint32_t slot = 0;
-  unsigned long long pending = __ballot(has);
   const int lane = __lane_id();
+  unsigned long long pending = __ballot(has);
+  int leader = lane;
+  uint32_t rank = 0, count = 0;
   while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t lkey = __shfl(key, leader);
+    const int l = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t lkey = __shfl(key, l);
     const bool mine = has && key == lkey;
     const unsigned long long grp = __ballot(mine);
-    uint32_t base = 0;
-    if (lane == leader) base = gatomic_add(&counters[lkey], (uint32_t)__popcll(grp));
-    base = __shfl(base, leader);
-    if (mine) slot = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    if (mine) {
+      leader = l;
+      rank = (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+    }
+    if (lane == l) count = (uint32_t)__popcll(grp);
     pending &= ~grp;
   }
-  return slot;
+  const bool lead = has && lane == leader;
+  if (!kReturn) {
+    if (lead)
+      __hip_atomic_fetch_add(gmem(&counters[key]), count, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  uint32_t base = 0;
+  if (lead) base = gatomic_add(&counters[key], count);
+  base = (uint32_t)__shfl((int)base, leader);
+  return base + rank;
 }
 
 // Count (kFill = false) or list (kFill = true) the target tiles touched by
@@ -97,7 +114,7 @@ __device__ __forceinline__ void splat_bin_block(const SplatArgs &a, int k, uint3
     const bool has = s < n;
     if (__ballot(has) == 0ull) break;
     const uint32_t tile = has ? (uint32_t)((ty0 + s / nx) * a.ntx + (tx0 + s % nx)) : 0u;
-    const uint32_t slot = aggregated_slot(cnt, tile, has);
+    const uint32_t slot = aggregated_slot<kFill>(cnt, tile, has);
     if (kFill && has) {
       const uint32_t pos = gmem(a.tile_offset)[(size_t)k * a.ntiles + tile] + slot;
       if (pos < a.list_cap) gmem(a.list)[pos] = q;

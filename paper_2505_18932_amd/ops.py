@@ -195,8 +195,8 @@ def splat_views_ewa(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *,
 
 
 def set_ewa_sort_limit(keys: int) -> None:
-    """Longest tile list splat_views_ewa sorts in LDS at once (64..1024, 0 =
-    default); results do not depend on it."""
+    """Longest tile list splat_views_ewa sorts in LDS at once (64..512,
+    0 = default); results do not depend on it."""
     L.check(L.lib().gg_set_ewa_sort_limit(int(keys)))
 
 
@@ -256,10 +256,26 @@ def splat_views_backward(src, depth, rgb, tgt, params, fwd, g_rgb=None, g_depth=
     return gd, gc
 
 
+def tsdf_view_table(src, depth, params, *, ws, stream=None):
+    """Build the view table and bin depths of ``depth`` into ``ws`` (the first
+    part of tsdf_integrate), for tsdf_integrate(..., table_ready=True)."""
+    dev = _device(depth)
+    sa, tp = cameras(src), tsdf_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    need = workspace_size(L.GG_OP_TSDF_INTEGRATE, K, sw, sh, sw, sh, tp.num_bins)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().tsdf_view_table(sa, K, _ptr(depth), C.byref(tp), _ptr(wsb), wsn,
+                                    _stream(dev, stream)))
+
+
 def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
-                   mask=None, extract=True, ws=None, stream=None):
+                   mask=None, extract=True, ws=None, stream=None, table_ready=False):
     """Fuse K depth maps into the target volume (in place when F is F_prev).
-    Returns (F, W, depth, bin) (depth, bin None when extract=False)."""
+    Returns (F, W, depth, bin) (depth, bin None when extract=False).  With
+    ``table_ready`` the view table is the one tsdf_view_table built into
+    ``ws`` (``depth`` then only fixes the shapes)."""
     dev = _device(depth)
     sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
     K = len(sa)
@@ -283,10 +299,18 @@ def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None,
         od = torch.empty((th, tw), dtype=torch.float32, device=dev)
         ob = torch.empty((th, tw), dtype=torch.int32, device=dev)
     need = workspace_size(L.GG_OP_TSDF_INTEGRATE, K, sw, sh, tw, th, D)
+    if table_ready and ws is None:
+        raise ValueError("table_ready needs the workspace tsdf_view_table filled")
     wsb, wsn = _ws(need, dev, ws)
-    L.check(L.lib().tsdf_integrate(sa, K, _ptr(depth), C.byref(tg), C.byref(tp), _ptr(mask),
-                                   _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W), _ptr(od),
-                                   _ptr(ob), _ptr(wsb), wsn, _stream(dev, stream)))
+    if table_ready:
+        L.check(L.lib().tsdf_integrate_tabled(sa, K, C.byref(tg), C.byref(tp), _ptr(mask),
+                                              _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W),
+                                              _ptr(od), _ptr(ob), _ptr(wsb), wsn,
+                                              _stream(dev, stream)))
+    else:
+        L.check(L.lib().tsdf_integrate(sa, K, _ptr(depth), C.byref(tg), C.byref(tp), _ptr(mask),
+                                       _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W), _ptr(od),
+                                       _ptr(ob), _ptr(wsb), wsn, _stream(dev, stream)))
     return F, W, od, ob
 
 

@@ -197,6 +197,24 @@ def test_tsdf_rejects_invalid_arguments():
         L.GG_ERR_INVALID
 
 
+def test_two_call_fusion_rejects_invalid_arguments():
+    lib = L.lib()
+    src, tgt = _cams()
+    good = ops.tsdf_params(scenes.tsdf_params(num_bins=64))
+    bad = ops.tsdf_params(scenes.tsdf_params(num_bins=1))
+    assert lib.tsdf_view_table(src, 2, None, C.byref(good), FAKE, 1 << 40, None) == \
+        L.GG_ERR_INVALID
+    assert lib.tsdf_view_table(src, 2, FAKE, C.byref(bad), FAKE, 1 << 40, None) == L.GG_ERR_INVALID
+    assert lib.tsdf_view_table(src, 0, FAKE, C.byref(good), FAKE, 1 << 40, None) == \
+        L.GG_ERR_INVALID
+    assert lib.tsdf_view_table(src, 2, FAKE, C.byref(good), FAKE, 100, None) == L.GG_ERR_WORKSPACE
+    call = lambda F=FAKE, Fp=None, nws=1 << 40: lib.tsdf_integrate_tabled(
+        src, 2, C.byref(tgt), C.byref(good), None, Fp, None, F, FAKE, None, None, FAKE, nws, None)
+    assert call(F=None) == L.GG_ERR_INVALID
+    assert call(Fp=FAKE) == L.GG_ERR_INVALID
+    assert call(nws=100) == L.GG_ERR_WORKSPACE
+
+
 def test_ewa_splat_rejects_invalid_arguments():
     lib = L.lib()
     src, tgt = _cams()
@@ -221,9 +239,9 @@ def test_ewa_splat_rejects_invalid_arguments():
 
 def test_launch_shape_setters_validate():
     lib = L.lib()
-    for bad in (-1, 1, 63, 1025, 4096):
+    for bad in (-1, 1, 63, 513, 1024):
         assert lib.gg_set_ewa_sort_limit(bad) == L.GG_ERR_INVALID
-    for ok in (64, 100, 1024, 0):
+    for ok in (64, 100, 512, 0):
         assert lib.gg_set_ewa_sort_limit(ok) == L.GG_OK
     for bad in (-1, 3, 5, 16):
         assert lib.gg_set_volume_vector(bad) == L.GG_ERR_INVALID

@@ -55,7 +55,8 @@ def test_ring_scenes_ragged(k, w, h):
 def _zoomed_out(scale=6, seed=0):
     """Sources at 240x160, the target at the same pose with fx / scale and
     its principal point scaled: about scale^2 source pixels per target
-    pixel, so 8 x 8 tiles collect thousands of Gaussians."""
+    pixel, so 8 x 8 tiles collect hundreds to thousands of Gaussians (lists
+    on both sides of every sort threshold)."""
     c = scenes.small_ring(seed=seed, width=240, height=160, k=2, noise=0.01)
     t = c["tgt"]
     w, h = 240 // scale + 3, 160 // scale + 2
@@ -70,7 +71,7 @@ def test_long_lists_take_the_merge_path():
     assert (r["alpha"] > 0.5).mean() > 0.5
 
 
-@pytest.mark.parametrize("limit", [64, 100, 256])
+@pytest.mark.parametrize("limit", [64, 100, 256, 300])
 def test_sort_limit_invariance(limit):
     cs = [scenes.config1(), _zoomed_out(4, seed=1)]
     ref = [run(c) for c in cs]

@@ -267,3 +267,15 @@ def test_nothing_valid():
     # everything behind the near plane
     o = oracle.splat_ewa(src, depth, rgb, tgt, _sp(z_min=100.0))
     assert all(np.all(v == 0) for v in o.values())
+
+
+def test_exp_below_alpha_floor_for_every_float_under_minus_5_6():
+    """Every FP32 x in [-86, -5.6] gives exp_cw(x) < 1/255 (exhaustive), so a
+    term whose exponent is below -5.6 is always skipped: the GPU raster may
+    skip such terms for a whole wavefront without evaluating them."""
+    hi = np.array([-5.6], np.float32).view(np.uint32)[0]
+    lo = np.array([-86.0], np.float32).view(np.uint32)[0]
+    x = np.arange(hi, lo + 1, dtype=np.uint32).view(np.float32)
+    amin = np.float32(1) / np.float32(255)
+    for i in range(0, x.size, 1 << 23):
+        assert oracle.exp_cw(x[i:i + (1 << 23)]).max() < amin

@@ -298,3 +298,50 @@ def test_splat_backward_parity():
                                    g_z, g_a)
     grad_close(gc.cpu().numpy(), rc, "splat colour gradient")
     grad_close(gd.cpu().numpy(), rd, "splat depth gradient")
+
+
+def test_two_call_fusion_on_two_streams():
+    """tsdf_view_table on a second stream, an event, then tsdf_integrate_tabled
+    on the main stream, pipelined over a small video with two workspaces as
+    the benchmark does: bitwise the volume and depths of tsdf_integrate."""
+    c = scenes.small_video(seed=2, width=96, height=64, k=3, bins=32)
+    frames = [c["seq"].frame(t)[0] for t in range(5)]
+    K, H, W = frames[0].shape
+    tp = c["tsdf"]
+    ref = []
+    F = Wv = None
+    for d in frames:
+        F, Wv, dep, b = gg.tsdf_integrate(c["src"], torch.from_numpy(d).to(DEV), c["tgt"], tp,
+                                          F_prev=F, W_prev=Wv)
+        ref.append((F.clone(), Wv.clone(), dep.clone(), b.clone()))
+    need = gg.workspace_size(3, K, W, H, c["tgt"].width, c["tgt"].height, tp["num_bins"])
+    wss = [torch.empty(need, dtype=torch.uint8, device=DEV) for _ in range(2)]
+    side = torch.cuda.Stream(device=DEV)
+    ev_t = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_f = [torch.cuda.Event(), torch.cuda.Event()]
+    main = torch.cuda.current_stream(DEV)
+    dd = [torch.from_numpy(d).to(DEV) for d in frames]
+    torch.cuda.synchronize()
+    F = Wv = None
+    outs = []
+    for i, d in enumerate(dd):
+        b = i % 2
+        side.wait_event(ev_f[b])
+        gg.tsdf_view_table(c["src"], d, tp, ws=wss[b], stream=side)
+        ev_t[b].record(side)
+        main.wait_event(ev_t[b])
+        if F is None:
+            F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, ws=wss[b],
+                                               table_ready=True)
+        else:
+            F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, F_prev=F, W_prev=Wv,
+                                               F=F, W=Wv, ws=wss[b], table_ready=True)
+        ev_f[b].record(main)
+        outs.append((dep.clone(), bb.clone()))
+    torch.cuda.synchronize()
+    Fr, Wr, _, _ = ref[-1]
+    assert torch.equal(F.view(torch.int32), Fr.view(torch.int32))
+    assert torch.equal(Wv.view(torch.int32), Wr.view(torch.int32))
+    for (dep, bb), r in zip(outs, ref):
+        assert torch.equal(dep.view(torch.int32), r[2].view(torch.int32))
+        assert torch.equal(bb, r[3])
