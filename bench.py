@@ -193,7 +193,13 @@ def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
     A.2): per frame the colour-difference masks of the K views and their
     filtered depths, the splat carrying the masks (maximum over views), and
     the fusion of the filtered depths with that maximum weighting the carried
-    volume; all inputs resident, state carried in place."""
+    volume; all inputs resident, state carried in place.
+
+    Pipelined on two streams: the second stream runs a frame's masks and
+    filter, its view table and its masked splat, then signals; the main
+    stream fuses that frame while the second stream moves on to the next.
+    The view tables and splat outputs alternate between two buffers (the
+    second stream waits until the fusion two frames back is done with one)."""
     nf, K, H, Wd = depth.shape[0], depth.shape[1], depth.shape[2], depth.shape[3]
     D = tp.num_bins
     F = torch.zeros((H, Wd, D), dtype=torch.float32, device=dev)
@@ -202,42 +208,78 @@ def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
     mask = torch.empty((K, H, Wd), device=dev)
     wsm = torch.empty(gg.workspace_size(5, K, Wd, H, Wd, H, 4), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(gg.workspace_size(1, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8, device=dev)
-    ws_t = torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
-    so = dict(win_idx=torch.empty((K, H, Wd), dtype=torch.int32, device=dev),
-              depth=torch.empty((K, H, Wd), device=dev), rgb=torch.empty((K, 3, H, Wd), device=dev),
-              alpha=torch.empty((K, H, Wd), device=dev), tape=torch.empty((K, 3, H, Wd), device=dev),
-              mask=torch.empty((K, H, Wd), device=dev), mask_max=torch.empty((H, Wd), device=dev))
+    wst = [torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
+           for _ in range(2)]
+
+    def outs():
+        return dict(win_idx=torch.empty((K, H, Wd), dtype=torch.int32, device=dev),
+                    depth=torch.empty((K, H, Wd), device=dev),
+                    rgb=torch.empty((K, 3, H, Wd), device=dev),
+                    alpha=torch.empty((K, H, Wd), device=dev),
+                    tape=torch.empty((K, 3, H, Wd), device=dev),
+                    mask=torch.empty((K, H, Wd), device=dev),
+                    mask_max=torch.empty((H, Wd), device=dev))
+
+    so = [outs(), outs()]
+    side = torch.cuda.Stream(device=dev)
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+    pipelined = [True]
 
     def step(i):
         f, g = (i + 1) % nf, i % nf  # frame t and t - 1 (the sequence wraps)
+        if not pipelined[0]:
+            gg.difference_masks(rgb[f], rgb[g], depth=depth[f], depth_prev=filt, mask=mask,
+                                filtered=filt, ws=wsm)
+            gg.splat_views(src, filt, rgb[f], tgt, sp, mask=mask, out=so[0], ws=ws_s)
+            gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv,
+                              mask=so[0]["mask_max"], ws=wst[0])
+            return
+        b = i % 2
+        main = torch.cuda.current_stream(dev)
+        side.wait_event(done[b])
         gg.difference_masks(rgb[f], rgb[g], depth=depth[f], depth_prev=filt, mask=mask,
-                            filtered=filt, ws=wsm)
-        gg.splat_views(src, filt, rgb[f], tgt, sp, mask=mask, out=so, ws=ws_s)
+                            filtered=filt, ws=wsm, stream=side)
+        gg.tsdf_view_table(src, filt, tp, ws=wst[b], stream=side)
+        gg.splat_views(src, filt, rgb[f], tgt, sp, mask=mask, out=so[b], ws=ws_s, stream=side)
+        ready[b].record(side)
+        main.wait_event(ready[b])
         gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv,
-                          mask=so["mask_max"], ws=ws_t)
+                          mask=so[b]["mask_max"], ws=wst[b], table_ready=True)
+        done[b].record(main)
+
+    def timed(first):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(first + i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
 
     for i in range(warmup):
         step(i)
-    torch.cuda.synchronize()
+    ms = timed(warmup)
+    # per-kernel breakdown (every launch bracketed) and the one-stream comparison
     gg.timing_reset()
     gg.timing_enable(True)
-    t0 = time.perf_counter()
-    for i in range(steps):
-        step(warmup + i)
+    for i in range(min(steps, 10)):
+        step(warmup + steps + i)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
     gg.timing_enable(False)
+    nb = min(steps, 10)
     kt = {}
-    for name in ("difference_masks", "splat_raster", "integrate"):
-        ms, n = gg.timing_read(name)
-        kt[name] = round(ms / max(steps, 1), 4)
-    ms = el * 1e3 / steps
+    for name in ("difference_masks", "conf", "splat_raster", "integrate"):
+        t, n = gg.timing_read(name)
+        kt[name] = round(t / max(nb, 1), 4)
+    pipelined[0] = False
+    ms1 = timed(warmup + steps + nb)
     # algorithmic bytes of the mask pass: two colour frames and the depth
     # read, the mask and filtered depth written, the previous filtered depth
     # read (per source pixel and view)
     mb = K * H * Wd * (3 + 3 + 4 + 4 + 4 + 4)
     return {"workload": "video ring K=4 1280x720 D=128, masks + filter + mask splat + fusion",
             "ms_per_frame": round(ms, 4), "mpix_s": round(H * Wd / ms / 1e3, 2),
+            "one_stream_ms_per_frame": round(ms1, 4),
             "kernel_ms_per_frame": kt,
             "difference_masks_gb_s": round(mb / (kt["difference_masks"] * 1e-3) / 1e9, 1)
             if kt["difference_masks"] > 0 else None}
@@ -302,24 +344,23 @@ def ewa_path(gg, torch, dev, src, tgt, sp, depth, rgb, steps, warmup):
     el = time.perf_counter() - t0
     gg.timing_enable(False)
     kt = {}
-    for name in ("ewa_zero", "ewa_count", "ewa_scan", "ewa_fill", "ewa_raster"):
+    for name in ("ewa_zero", "ewa_count", "ewa_alloc", "ewa_fill", "ewa_raster"):
         t, n = gg.timing_read(name)
         kt[name] = round(t / max(n, 1), 4)
-    # list statistics from the workspace's per-tile offsets (after the
-    # per-tile counts, each array 256-byte padded): total entries of the last
-    # frame and the longest tile list
+    # list statistics from the workspace's per-tile counts (the first array
+    # of the EWA workspace, followed by the total): entries of the last frame
+    # and the longest tile list
     ntiles = ((Wd + 7) // 8) * ((H + 7) // 8)
     n = K * ntiles
-    pad = (4 * (n + 1) + 255) // 256 * 256
-    off = ws[pad:pad + 4 * (n + 1)].view(torch.int32).cpu().numpy().astype("int64")
+    cnt = ws[:4 * (n + 1)].view(torch.int32).cpu().numpy().astype("int64")
     ms = el * 1e3 / steps
     return {"workload": "video ring K=4 1280x720, per-view EWA compositing, lowpass 0.3",
             "ms_per_frame": round(ms, 4), "mpix_s": round(H * Wd / ms / 1e3, 2),
             "kernel_ms_per_frame": kt,
-            "list_entries": int(off[-1]), "entries_per_gaussian":
-                round(float(off[-1]) / float((depth[0] > 0).sum()), 3),
-            "tile_list_mean": round(float(off[-1]) / n, 1),
-            "tile_list_max": int((off[1:] - off[:-1]).max())}
+            "list_entries": int(cnt[n]), "entries_per_gaussian":
+                round(float(cnt[n]) / float((depth[0] > 0).sum()), 3),
+            "tile_list_mean": round(float(cnt[n]) / n, 1),
+            "tile_list_max": int(cnt[:n].max())}
 
 
 def network_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps):

@@ -1252,15 +1252,22 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   if (rc == GG_OK) rc = batch_occupancy(P);
   cp(o_sitems, splat_items.data(), 4 * splat_items.size());
   // capture every phase into one graph
-  hipStream_t cs = nullptr;
+  hipStream_t cs = nullptr, side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   if (rc == GG_OK) rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), N);
+  if (rc == GG_OK) rc = check_hip(hipStreamCreateWithFlags(&side, hipStreamNonBlocking), N);
+  if (rc == GG_OK) rc = check_hip(hipEventCreateWithFlags(&fork, hipEventDisableTiming), N);
+  if (rc == GG_OK) rc = check_hip(hipEventCreateWithFlags(&join, hipEventDisableTiming), N);
   if (rc == GG_OK) rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), N);
   if (rc == GG_OK) {
-    const int rr = batch_record(P, cs);
+    const int rr = batch_record(P, cs, side, fork, join);
     const int re = check_hip(hipStreamEndCapture(cs, &P.graph), N);
     rc = rr ? rr : re;
   }
   if (rc == GG_OK) rc = check_hip(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0), N);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (side) (void)hipStreamDestroy(side);
   if (cs) (void)hipStreamDestroy(cs);
   if (rc != GG_OK) {
     gg_batch_destroy(b);

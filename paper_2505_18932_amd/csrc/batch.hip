@@ -198,27 +198,39 @@ int batch_occupancy(BatchPlan &P) {
   return GG_OK;
 }
 
-int batch_record(BatchPlan &P, hipStream_t s) {
+int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
+                 hipEvent_t join) {
   const int cus = P.cus, per = P.blocks_per_cu;
   // tile counts of every item and the phases' work counters
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
+  // The splat phases depend on the depth maps and the zeroed counts only: with a side stream
+  // they form a second branch of the graph, beside the bins, weights and fusion of the main
+  // branch, and the two overlap; the branches join before the graph ends.
+  const bool branch = side && P.n_bin;
+  if (branch) {
+    if (int rc = check_hip(hipEventRecord(fork, s), "batch fork")) return rc;
+    if (int rc = check_hip(hipStreamWaitEvent(side, fork, 0), "batch fork")) return rc;
+  }
+  const hipStream_t ss = branch ? side : s;
+  if (P.n_bin) {
+    const int gb = persistent_grid(P.n_bin, P.occ_bin, cus);
+    const int gr = persistent_grid(P.n_raster, P.occ_raster, cus);
+    hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, ss, P.d_items, P.d_bin,
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1 * kXcds);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, ss, P.d_items,
+                       P.d_splat_items);
+    hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(gb), dim3(256), 0, ss, P.d_items, P.d_bin,
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2 * kXcds);
+    hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, ss, P.d_items, P.d_raster,
+                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3 * kXcds);
+  }
+  if (branch)
+    if (int rc = check_hip(hipEventRecord(join, side), "batch join")) return rc;
   hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
   if (P.n_conf) {
     const int g = persistent_grid(P.n_conf, P.occ_conf, cus);
     hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
                        chunk_of(P.n_conf, g), P.d_ctr + 0 * kXcds);
-  }
-  if (P.n_bin) {
-    const int gb = persistent_grid(P.n_bin, P.occ_bin, cus);
-    const int gr = persistent_grid(P.n_raster, P.occ_raster, cus);
-    hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1 * kXcds);
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, s, P.d_items,
-                       P.d_splat_items);
-    hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(gb), dim3(256), 0, s, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2 * kXcds);
-    hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, s, P.d_items, P.d_raster,
-                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3 * kXcds);
   }
   const size_t shm = sizeof(float) * 2 * P.integ_threads + sizeof(int) * P.integ_threads;
   for (int c = 0; c < kIntegClasses; ++c) {
@@ -227,6 +239,8 @@ int batch_record(BatchPlan &P, hipStream_t s) {
     const int g = persistent_grid(n, per, cus);
     dispatch_integ_class<0>(c, P, n, g, chunk_of(n, g), shm, s);
   }
+  if (branch)
+    if (int rc = check_hip(hipStreamWaitEvent(s, join, 0), "batch join")) return rc;
   return check_hip(hipGetLastError(), "batch phases");
 }
 

@@ -84,7 +84,10 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
 };
 
-int batch_record(BatchPlan &P, hipStream_t s);
+// Record every phase on s (captured into the plan's graph); with a side
+// stream and the two events the splat phases become a parallel branch.
+int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
+                 hipEvent_t join);
 int batch_occupancy(BatchPlan &P);
 
 }  // namespace gg

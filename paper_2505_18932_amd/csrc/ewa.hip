@@ -7,9 +7,10 @@
 //   count  - every source pixel builds its Gaussian (target mean, conic,
 //            colour) into a record and counts the 8 x 8 target tiles its
 //            candidate window touches (wavefront-aggregated atomics);
-//   scan   - exclusive scan of the tile counts (one workgroup);
+//   alloc  - a list segment per tile (wavefront prefix sums, one atomic per
+//            wavefront on an allocator; segments in atomic order);
 //   fill   - the same walk writes the key bits(z) << 32 | source index into
-//            each touched tile's list (in arrival order);
+//            each touched tile's segment (in arrival order);
 //   raster - one wavefront per (view, tile): the tile's keys are sorted in
 //            ascending (z, source index) order -- a bitonic sort in LDS for
 //            lists of up to sort_limit keys, else LDS-sorted runs merged
@@ -145,10 +146,30 @@ __global__ __launch_bounds__(256) void ewa_bin_kernel(EwaArgs a) {
   }
 }
 
-__global__ __launch_bounds__(1024) void ewa_scan_kernel(const uint32_t *cnt, uint32_t *off,
+// A list segment per (view, tile): each wavefront takes an exclusive prefix
+// of its 64 tiles' counts with shuffles and one atomic on the allocator
+// count[n] for its total.  Segments are laid out in atomic order (a tile
+// needs only its own range: offset and count); the fill's cursors are
+// cleared.
+__global__ __launch_bounds__(256) void ewa_alloc_kernel(uint32_t *count, uint32_t *off,
                                                         uint32_t *cursor, uint32_t n) {
-  __shared__ ScanLds lds;
-  tile_scan_block(cnt, off, cursor, n, lds);
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = __lane_id();
+  const uint32_t c = t < n ? gmem(count)[t] : 0u;
+  uint32_t inc = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)inc, d);
+    if (lane >= d) inc += v;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+  uint32_t base = 0;
+  if (lane == 63 && total) base = gatomic_add(&count[n], total);
+  base = (uint32_t)__shfl((int)base, 63);
+  if (t < n) {
+    gmem(off)[t] = base + inc - c;
+    gmem(cursor)[t] = 0u;
+  }
 }
 
 __global__ void ewa_zero_kernel(uint32_t *p, uint32_t n) {
@@ -245,8 +266,8 @@ __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
   const uint32_t ty = tile / (uint32_t)a.ntx, tx = tile - ty * (uint32_t)a.ntx;
   const int x = (int)tx * kEwaTile + (int)(lane & 7u), y = (int)ty * kEwaTile + (int)(lane >> 3);
   const size_t seg = (size_t)k * a.ntiles + tile;
-  const uint32_t off = gmem(a.tile_offset)[seg];
-  const uint32_t m = min(gmem(a.tile_offset)[seg + 1], a.cap) - min(off, a.cap);
+  const uint32_t off = min(gmem(a.tile_offset)[seg], a.cap);
+  const uint32_t m = min(gmem(a.tile_count)[seg], a.cap - off);
   const unsigned long long *list = nullptr;
   const bool in_lds = m <= a.sort_limit;
   if (m > 0) {
@@ -323,8 +344,8 @@ int launch_splat_ewa(const EwaArgs &a, hipStream_t s) {
   const dim3 gsrc((a.ns + 255) / 256, a.K);
   {
     KernelTimer t("ewa_zero", s);
-    hipLaunchKernelGGL(ewa_zero_kernel, dim3(min((n + 255) / 256, 1024u)), dim3(256), 0, s,
-                       a.tile_count, n);
+    hipLaunchKernelGGL(ewa_zero_kernel, dim3(min((n + 256) / 256, 1024u)), dim3(256), 0, s,
+                       a.tile_count, n + 1);
     if (int rc = check_hip(hipGetLastError(), "ewa_zero_kernel")) return rc;
   }
   {
@@ -333,10 +354,10 @@ int launch_splat_ewa(const EwaArgs &a, hipStream_t s) {
     if (int rc = check_hip(hipGetLastError(), "ewa_bin_kernel<count>")) return rc;
   }
   {
-    KernelTimer t("ewa_scan", s);
-    hipLaunchKernelGGL(ewa_scan_kernel, dim3(1), dim3(1024), 0, s, a.tile_count, a.tile_offset,
-                       a.tile_cursor, n);
-    if (int rc = check_hip(hipGetLastError(), "ewa_scan_kernel")) return rc;
+    KernelTimer t("ewa_alloc", s);
+    hipLaunchKernelGGL(ewa_alloc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a.tile_count,
+                       a.tile_offset, a.tile_cursor, n);
+    if (int rc = check_hip(hipGetLastError(), "ewa_alloc_kernel")) return rc;
   }
   {
     KernelTimer t("ewa_fill", s);

@@ -23,8 +23,8 @@ struct EwaArgs {
   float fx, fy, cx, cy;           // target intrinsics
   float ry, ry2;                  // fy / fx and its square, rounded once from FP64
   float lowpass, zmin, rmax;
-  uint32_t *tile_count;           // K x ntiles
-  uint32_t *tile_offset;          // K x ntiles + 1
+  uint32_t *tile_count;           // K x ntiles, then the list allocator
+  uint32_t *tile_offset;          // K x ntiles: start of each tile's list segment
   uint32_t *tile_cursor;          // K x ntiles
   unsigned long long *keys;       // list entries: bits(z) << 32 | source index
   unsigned long long *keys_alt;   // merge scratch, same layout
