@@ -31,6 +31,7 @@ import numpy as np  # noqa: E402
 import scenes  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+VALU_PEAK_TLANE = 256 * 64 * 2.4e9 / 1e12  # T lane-instructions/s: 256 CUs x 64 lanes x 2.4 GHz
 WORKLOAD = "video ring K=4 1280x720 D=128 (30 frames, carried volume)"
 
 
@@ -69,6 +70,21 @@ def recorded_traffic():
     return float(b.group(1))
 
 
+def recorded_valu_instructions():
+    """Wavefront VALU instructions per launch of the fusion kernel
+    (SQ_INSTS_VALU) from the committed counter summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "integrate_video_1280x720_K4_D128_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_sha:\s*([0-9a-f]+)", txt)
+    v = re.search(r"valu_instructions_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not v or m.group(1) != kernel_sha():
+        return None
+    return float(v.group(1))
+
+
 def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
     """The CPU oracle (plain C, OpenMP) on the same workload: whole frames
     (splat + fusion with carry + extraction) in sequence until the time
@@ -93,11 +109,39 @@ def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
                       f"extraction), {el:.1f} s"}
 
 
-def bwd_fwd_ratio(gg, torch, dev, reps=10):
-    """Backward / forward time on the differentiation workload (640x360,
-    K=4, D=96): forward = splat + fusion + extraction, backward = the three
-    adjoints for random upstream gradients."""
-    c = scenes.config3()
+def _render_view(args):
+    cam, prims = args
+    return scenes.render(cam, prims, None)
+
+
+def streaming_frame0(procs):
+    """Frame 0 of the streaming workload (1920x1080, K=8, D=256): the views
+    ray-cast in parallel, then the seeded noise and holes applied in view
+    order exactly as the sequence generator does."""
+    c = scenes.config5()
+    seq = c["seq"]
+    prims = seq.scene.prims(0)
+    jobs = [(cam, prims) for cam in seq.src]
+    if procs > 1:
+        with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
+            views = pool.map(_render_view, jobs)
+    else:
+        views = [_render_view(j) for j in jobs]
+    rng = np.random.default_rng([seq.cfg_id, seq.seed, 0])
+    depth, rgb = [], []
+    for d, col in views:
+        d, col = scenes.to_inputs(d, col, rng, seq.noise, seq.holes)
+        depth.append(d)
+        rgb.append(col)
+    return dict(src=c["src"], tgt=c["tgt"], depth=np.stack(depth), rgb=np.stack(rgb),
+                splat=c["splat"], tsdf=c["tsdf"])
+
+
+def bwd_fwd_ratio(gg, torch, dev, c=None, reps=10):
+    """Backward / forward time (default: the differentiation workload,
+    640x360, K=4, D=96): forward = splat + fusion + extraction, backward =
+    the three adjoints for random upstream gradients."""
+    c = scenes.config3() if c is None else c
     depth = torch.from_numpy(c["depth"]).to(dev)
     rgb = torch.from_numpy(c["rgb"]).to(dev)
 
@@ -429,6 +473,9 @@ def main():
     procs = args.procs or max(1, min(16, os.cpu_count() or 1))
     depth_h, rgb_h = make_frames(args.frames, procs)
     print(f"# frames generated: {depth_h.shape}", file=sys.stderr, flush=True)
+    # the large workload's first frame for its backward/forward ratio, generated (like the
+    # frames above) before anything touches the GPU
+    large = None if args.no_bwd else streaming_frame0(procs)
 
     import torch
 
@@ -550,6 +597,18 @@ def main():
             "timed_on": "one-stream pass" if serial_int_ms is not None else "timed region",
             "kernel_ms_overlapped": round(int_ms_timed, 4)}
 
+    # the fusion's second bound: VALU issue.  Peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+    # 39.3 T lane-instructions/s (FP32 without packed math, which the build disables)
+    vi = recorded_valu_instructions()
+    roof_valu = None
+    if vi is not None:
+        lane_ops = vi * 64
+        ach = lane_ops / (int_ms * 1e-3) / 1e12
+        roof_valu = {"bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TLANE,
+                     "unit": "T lane-instructions/s", "frac": round(ach / VALU_PEAK_TLANE, 4),
+                     "lane_instructions_per_launch": lane_ops,
+                     "source": "SQ_INSTS_VALU of the committed counter summary"}
+
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, device=dev)
@@ -566,6 +625,7 @@ def main():
         "config": {"workload": WORKLOAD, "K": K, "width": Wd, "height": H, "bins": D,
                    "frames_resident": nf, "fusion_tile": list(tile), "streams": args.streams},
         "roofline": roof,
+        "roofline_valu": roof_valu,
         "kernel_ms_per_step": {k: round(v[0] / max(nb, 1), 4) for k, v in kt.items()},
     }
     if serial_ms is not None:
@@ -574,6 +634,11 @@ def main():
         r, tf, tb = bwd_fwd_ratio(gg, torch, dev)
         out["bwd_fwd"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3), "bwd_ms": round(tb, 3),
                           "workload": "differentiation 640x360 K=4 D=96"}
+        r, tf, tb = bwd_fwd_ratio(gg, torch, dev, large, reps=5)
+        out["bwd_fwd_large"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3),
+                                "bwd_ms": round(tb, 3),
+                                "workload": "streaming 1920x1080 K=8 D=256, frame 0"}
+        del large
     del F, Wv, sout
     torch.cuda.empty_cache()
     if not args.no_temporal:
