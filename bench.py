@@ -109,32 +109,13 @@ def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
                       f"extraction), {el:.1f} s"}
 
 
-def _render_view(args):
-    cam, prims = args
-    return scenes.render(cam, prims, None)
-
-
 def streaming_frame0(procs):
-    """Frame 0 of the streaming workload (1920x1080, K=8, D=256): the views
-    ray-cast in parallel, then the seeded noise and holes applied in view
-    order exactly as the sequence generator does."""
+    """Frame 0 of the streaming workload (1920x1080, K=8, D=256), its views
+    ray-cast in parallel (the same frame as the sequential generator)."""
     c = scenes.config5()
-    seq = c["seq"]
-    prims = seq.scene.prims(0)
-    jobs = [(cam, prims) for cam in seq.src]
-    if procs > 1:
-        with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
-            views = pool.map(_render_view, jobs)
-    else:
-        views = [_render_view(j) for j in jobs]
-    rng = np.random.default_rng([seq.cfg_id, seq.seed, 0])
-    depth, rgb = [], []
-    for d, col in views:
-        d, col = scenes.to_inputs(d, col, rng, seq.noise, seq.holes)
-        depth.append(d)
-        rgb.append(col)
-    return dict(src=c["src"], tgt=c["tgt"], depth=np.stack(depth), rgb=np.stack(rgb),
-                splat=c["splat"], tsdf=c["tsdf"])
+    depth, rgb = c["seq"].frame(0, procs=procs)
+    return dict(src=c["src"], tgt=c["tgt"], depth=depth, rgb=rgb, splat=c["splat"],
+                tsdf=c["tsdf"])
 
 
 def bwd_fwd_ratio(gg, torch, dev, c=None, reps=10):

@@ -499,6 +499,11 @@ class MovingSpheres:
         return pr
 
 
+def _render_job(args):
+    cam, prims = args
+    return render(cam, prims, None)
+
+
 class RingSequence:
     """A K-of-N ring rig looking at a dynamic scene; frames generated on
     demand and seeded by (config, seed, frame)."""
@@ -514,10 +519,24 @@ class RingSequence:
         self.cfg_id, self.seed, self.noise, self.holes = cfg_id, seed, noise, holes
         self.caches = [dict() for _ in self.src]
 
-    def frame(self, t):
+    def frame(self, t, procs=1):
+        """Depth and colour of every view at frame t.  With procs > 1 the
+        views are ray-cast in a process pool and the seeded noise and holes
+        are then applied in view order: the same frame as procs = 1."""
         rng = np.random.default_rng([self.cfg_id, self.seed, t])
-        return make_frame(self.src, self.tgt, self.scene.prims(t), rng, self.noise, self.holes,
-                          self.caches)
+        if procs <= 1:
+            return make_frame(self.src, self.tgt, self.scene.prims(t), rng, self.noise,
+                              self.holes, self.caches)
+        import multiprocessing as mp
+        prims = self.scene.prims(t)
+        with mp.get_context("fork").Pool(min(procs, len(self.src))) as pool:
+            views = pool.map(_render_job, [(cam, prims) for cam in self.src])
+        depth, rgb = [], []
+        for d, c in views:
+            d, c = to_inputs(d, c, rng, self.noise, self.holes)
+            depth.append(d)
+            rgb.append(c)
+        return np.stack(depth), np.stack(rgb)
 
 
 def config2(seed=0):

@@ -11,3 +11,22 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs on the GPU box)")
     config.addinivalue_line("markers", "slow: long CPU test")
+
+
+@pytest.fixture(scope="session")
+def video_frames():
+    """Frames 0 and 1 of the 1280x720 K=4 ring video (rendered once per session)."""
+    import scenes
+
+    c = scenes.config2()
+    frames = [c["seq"].frame(t) for t in range(2)]
+    return c, frames
+
+
+@pytest.fixture(scope="session")
+def streaming_frame():
+    """Frame 0 of the 1920x1080 K=8 streaming workload (rendered once per session)."""
+    import scenes
+
+    c = scenes.config5()
+    return c, c["seq"].frame(0)

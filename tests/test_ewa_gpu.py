@@ -127,3 +127,18 @@ def test_one_pixel_target():
     c["tgt"] = scenes.Camera(t.fx, t.fy, float(np.float32(t.cx - 20)), float(np.float32(t.cy - 15)),
                              t.R, t.t, 1, 1)
     check(c)
+
+
+def test_streaming_frame_sampled(streaming_frame):
+    """1920x1080, K=8 (the large streaming shape): 400 sampled pixels of
+    every view against the oracle's per-pixel rendering, bitwise."""
+    c, (depth, rgb) = streaming_frame
+    c = dict(src=c["src"], tgt=c["tgt"], depth=depth, rgb=rgb, splat=c["splat"])
+    g = run(c)
+    n = c["tgt"].width * c["tgt"].height
+    pix = np.random.default_rng(5).choice(n, 400, replace=False)
+    r = oracle.splat_ewa(c["src"], depth, rgb, c["tgt"], c["splat"], pixels=pix)
+    for key in ("rgb", "alpha", "depth"):
+        a = g[key].reshape(*g[key].shape[:-2], -1)[..., pix]
+        b = r[key].reshape(*r[key].shape[:-2], -1)[..., pix]
+        assert np.array_equal(bits(a), bits(b)), key

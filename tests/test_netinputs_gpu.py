@@ -53,3 +53,17 @@ def test_blend_bitwise():
     ro, rd = oracle.blend(rgb, dep, al, w, wb, bg)
     assert np.array_equal(bits(o.cpu().numpy()), bits(ro))
     assert np.array_equal(bits(d.cpu().numpy()), bits(rd))
+
+
+def test_network_inputs_full_video_frame(video_frames):
+    """The (9K+1)-plane stack of a full 1280x720 K=4 frame, bitwise."""
+    c, frames = video_frames
+    depth = torch.from_numpy(frames[0][0]).to(DEV)
+    rgb = torch.from_numpy(frames[0][1]).to(DEV)
+    sp = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    _, _, dep, _ = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    out = gg.network_inputs(c["src"], c["tgt"], dep, sp)
+    torch.cuda.synchronize()
+    ref = oracle.network_inputs(c["src"], c["tgt"], dep.cpu().numpy(), sp["rgb"].cpu().numpy(),
+                                sp["depth"].cpu().numpy(), sp["alpha"].cpu().numpy())
+    assert np.array_equal(bits(out.cpu().numpy()), bits(ref))

@@ -69,3 +69,14 @@ def test_division_everywhere():
     c = scenes.small_ring(seed=11, width=24, height=16, k=2, bins=12)
     c["tsdf"] = dict(c["tsdf"], z_far=1e30)
     check(c)
+
+
+def test_full_video_two_frames(video_frames):
+    """1280x720, K=4, D=128 bounds: every pixel of two frames, the second
+    with the first's depth and accumulated weight as its temporal input."""
+    c, frames = video_frames
+    d0 = dict(c, depth=frames[0][0])
+    r0 = check(d0)
+    assert (r0 > 0).mean() > 0.9
+    _, acc = oracle.raymarch(c["src"], frames[0][0], c["tgt"], c["tsdf"])[:2]
+    check(dict(c, depth=frames[1][0]), dprev=r0, acc=acc)

@@ -151,3 +151,18 @@ def test_temporal_path_end_to_end():
     # the mask did weight the carry: somewhere it is below one and above beta
     mm = sp_out["mask_max"].cpu().numpy()
     assert (mm > 0.6).any() and (mm < 1.0).any()
+
+
+def test_full_video_masks_and_filter(video_frames):
+    """Masks between frames 0 and 1 of the 1280x720 K=4 video and the
+    filtered depth of frame 1 (from frame 0's depth), bitwise."""
+    c, frames = video_frames
+    (d0, c0), (d1, c1) = frames
+    m, f = gg.difference_masks(torch.from_numpy(c1).to(DEV), torch.from_numpy(c0).to(DEV),
+                               depth=torch.from_numpy(d1).to(DEV),
+                               depth_prev=torch.from_numpy(d0).to(DEV))
+    torch.cuda.synchronize()
+    mr = oracle.difference_mask(c1, c0)
+    assert np.array_equal(bits(m.cpu().numpy()), bits(mr))
+    fr = oracle.temporal_filter(d1, mr, d0)
+    assert np.array_equal(bits(f.cpu().numpy()), bits(fr))
