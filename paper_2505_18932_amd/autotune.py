@@ -101,6 +101,31 @@ def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
     return best, times
 
 
+def tune_plain_step(step, first, reps=8, warm=2):
+    """Best launch shape of the fusion for a whole step of the caller's
+    pipeline (``step(i)`` runs frame i, perhaps on several streams, where
+    the fusion shares the device with other work): each candidate is timed
+    over ``reps`` steps after ``warm`` untimed ones.  Sets the best and
+    returns (best, {candidate: ms per step}, next frame index)."""
+    times = {}
+    i = first
+    for cand in PLAIN_CANDIDATES:
+        set_plain(cand)
+        for _ in range(warm):
+            step(i)
+            i += 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step(i)
+            i += 1
+        torch.cuda.synchronize()
+        times["%d,%d,%d" % cand] = (time.perf_counter() - t0) * 1e3 / reps
+    best = tuple(int(v) for v in min(times, key=times.get).split(","))
+    set_plain(best)
+    return best, times, i
+
+
 def batch_signature(items):
     sig = sorted((len(it["src"]), ops.tsdf_params(it["tsdf"]).num_bins,
                   ops.camera(it["tgt"]).width, ops.camera(it["tgt"]).height,
