@@ -103,10 +103,21 @@ def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
             break
     el = time.perf_counter() - t0
     npix = c["tgt"].width * c["tgt"].height
+    cores = oracle.num_threads()
+    # one frame on one thread (the oracle's serial speed)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.splat(c["src"], depth[0], rgb[0], c["tgt"], c["splat"])
+    F1, W1 = oracle.integrate(c["src"], depth[0], c["tgt"], c["tsdf"])
+    oracle.extract(F1, W1, c["tsdf"])
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
     return {"value": round(frames * npix / el / 1e6, 4), "unit": "Mpix/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{frames} full frame(s) of the same sequence (splat + fusion + "
-                      f"extraction), {el:.1f} s"}
+                      f"extraction), {el:.1f} s",
+            "single_thread": {"value": round(npix / el1 / 1e6, 4), "unit": "Mpix/s",
+                              "sample": f"frame 0 without carry, {el1:.1f} s"}}
 
 
 def streaming_frame0(procs):
@@ -116,6 +127,72 @@ def streaming_frame0(procs):
     depth, rgb = c["seq"].frame(0, procs=procs)
     return dict(src=c["src"], tgt=c["tgt"], depth=depth, rgb=rgb, splat=c["splat"],
                 tsdf=c["tsdf"])
+
+
+def paper_shape_leg(gg, torch, dev, c, frames, steps=20):
+    """Context beside the paper's Table 4 (1352x1014, K=4): per frame the
+    volume path (splat + fusion + extraction, pipelined on two streams as
+    in the main measurement), the EWA compositing (the renderer the paper's
+    10 ms splatting uses) and the volume-free raymarch (the paper's own 6 ms
+    per-ray TSDF form); frames resident, cycled."""
+    src, tgt = gg.cameras(c["src"]), gg.camera(c["tgt"])
+    sp, tp = gg.splat_params(c["splat"]), gg.tsdf_params(c["tsdf"])
+    depth = torch.from_numpy(np.stack([f[0] for f in frames])).to(dev)
+    rgb = torch.from_numpy(np.stack([f[1] for f in frames])).to(dev)
+    nf, K, H, Wd = depth.shape
+    D = tp.num_bins
+    F = torch.zeros((H, Wd, D), device=dev)
+    Wv = torch.zeros_like(F)
+    wss = [torch.empty(gg.workspace_size(3, K, Wd, H, Wd, H, D), dtype=torch.uint8, device=dev)
+           for _ in range(2)]
+    ws_s = torch.empty(gg.workspace_size(1, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8, device=dev)
+    sout = gg.splat_views(src, depth[0], rgb[0], tgt, sp, ws=ws_s)
+    torch.cuda.synchronize()  # the side stream reuses these buffers
+    side = torch.cuda.Stream(device=dev)
+    ev_t = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_f = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def step(i):
+        f, b = i % nf, i % 2
+        main = torch.cuda.current_stream(dev)
+        side.wait_event(ev_f[b])
+        gg.tsdf_view_table(src, depth[f], tp, ws=wss[b], stream=side)
+        ev_t[b].record(side)
+        gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s, stream=side)
+        main.wait_event(ev_t[b])
+        gg.tsdf_integrate(src, depth[f], tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv, ws=wss[b],
+                          table_ready=True)
+        ev_f[b].record(main)
+
+    def per_frame(fn):
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            fn(3 + i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    vol = per_frame(step)
+    ws_e = torch.empty(gg.workspace_size(6, K, Wd, H, Wd, H, 2, sp), dtype=torch.uint8,
+                       device=dev)
+    torch.cuda.synchronize()
+    eo = gg.splat_views_ewa(src, depth[0], rgb[0], tgt, sp, ws=ws_e)
+    ewa = per_frame(lambda i: gg.splat_views_ewa(src, depth[i % nf], rgb[i % nf], tgt, sp,
+                                                 ws=ws_e, out=eo))
+    dbuf = [torch.zeros((H, Wd), device=dev) for _ in range(2)]
+    abuf = [torch.zeros((H, Wd), device=dev) for _ in range(2)]
+    ws_r = wss[0]
+    rm = per_frame(lambda i: gg.tsdf_raymarch(src, depth[i % nf], tgt, tp, depth_prev=dbuf[i % 2],
+                                              acc_prev=abuf[i % 2], out_depth=dbuf[(i + 1) % 2],
+                                              out_acc=abuf[(i + 1) % 2], ws=ws_r))
+    px = H * Wd
+    return {"workload": "video scene and rig at 1352x1014, K=4, D=128 (the paper's test shape)",
+            "volume_path_ms": round(vol, 4), "volume_path_mpix_s": round(px / vol / 1e3, 2),
+            "ewa_compositing_ms": round(ewa, 4), "raymarch_ms": round(rm, 4),
+            "paper_table4_ms": {"forward_splatting": 10.0, "image_based_tsdf": 6.0},
+            "note": "context only: the paper's hardware is not stated"}
 
 
 def bwd_fwd_ratio(gg, torch, dev, c=None, reps=10):
@@ -436,6 +513,7 @@ def main():
     ap.add_argument("--no-raymarch", action="store_true")
     ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--no-ewa", action="store_true")
+    ap.add_argument("--no-paper-shape", action="store_true")
     ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
                     help="2: the splat on its own stream, overlapping the fusion; 1: one stream")
     ap.add_argument("--tile", default="",
@@ -457,6 +535,10 @@ def main():
     # the large workload's first frame for its backward/forward ratio, generated (like the
     # frames above) before anything touches the GPU
     large = None if args.no_bwd else streaming_frame0(procs)
+    paper = None
+    if not args.no_paper_shape:
+        pc = scenes.paper_shape()
+        paper = (pc, [pc["seq"].frame(t, procs=procs) for t in range(4)])
 
     import torch
 
@@ -635,6 +717,10 @@ def main():
     if not args.no_ewa:
         out["ewa_compositing"] = ewa_path(gg, torch, dev, src, tgt, sp, depth, rgb,
                                           min(args.steps, 30), 3)
+    if paper is not None:
+        out["paper_shape"] = paper_shape_leg(gg, torch, dev, paper[0], paper[1])
+        del paper
+        torch.cuda.empty_cache()
     if not args.no_batch:
         del depth, rgb, ws_s, ws_t, ws_t2, wss
         torch.cuda.empty_cache()

@@ -342,6 +342,12 @@ def tsdf_backward(src, depth, tgt, tsdf, g_out, mask=None, F_prev=None, W_prev=N
     return gd
 
 
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (both builds)."""
+    for prec in (32, 64):
+        lib(prec).orc_set_threads(int(n))
+
+
 def num_threads():
     """Threads the oracle's OpenMP loops use in this process."""
     import multiprocessing

@@ -890,6 +890,15 @@ float orc_exp_cw(float x) {
   return ldexpf(p, (int)n);
 }
 
+/* Threads of the OpenMP loops (for timing the oracle on n cores). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
 void orc_exp_cw_n(const float *x, float *y, size_t n) {
   for (size_t i = 0; i < n; ++i) y[i] = orc_exp_cw(x[i]);
 }

@@ -549,6 +549,15 @@ def config2(seed=0):
                 splat=splat_params(), tsdf=tsdf_params(num_bins=128, trunc=4.0))
 
 
+def paper_shape(seed=0):
+    """The video workload's scene and rig at the paper's DyNeRF test shape,
+    1352x1014, K=4 of the 16-camera ring, D=128 (a context run beside the
+    metric's 1280x720)."""
+    seq = RingSequence(6, seed, 16, 1.0, 1352, 1014, 4, MovingSpheres(seed, 5))
+    return dict(name="paper shape", seq=seq, src=seq.src, tgt=seq.tgt,
+                splat=splat_params(), tsdf=tsdf_params(num_bins=128, trunc=4.0))
+
+
 def small_video(seed=0, width=96, height=64, k=3, bins=32):
     """A small version of the video workload (ring rig, moving spheres) for
     tests of the temporal path."""
