@@ -3,10 +3,12 @@ oracle (a flipped sign, a dropped term, a transposed operand, a wrong index)
 makes at least one pin fail.  Mutants are built into a temporary directory on
 the CPU; the repository's oracle is never modified.
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 import pytest
 
@@ -134,21 +136,45 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("name,orig,mut,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(name, orig, mut, pins, tmp_path):
+def _run_mutant(name, orig, mut, pins):
+    """Build a copy of the oracle with one mistake planted and run the pins
+    that should catch it; returns (pytest exit code, output tail)."""
     src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
-    assert src.count(orig) >= 1, "mutation site not found"
-    root = tmp_path / "root"
-    shutil.copytree(os.path.join(ROOT, "oracle"), root / "oracle",
-                    ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
-    (root / "oracle" / "oracle.c").write_text(src.replace(orig, mut, 1))
-    subprocess.run([sys.executable, str(root / "oracle" / "build.py")], check=True,
-                   capture_output=True)
-    os.symlink(os.path.join(ROOT, "scenes"), root / "scenes")
-    shutil.copytree(os.path.join(ROOT, "tests"), root / "tests",
-                    ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
-    env = dict(os.environ, PYTHONPATH=str(root), PYTHONDONTWRITEBYTECODE="1")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "-m", "not gpu", pins], cwd=root, env=env, capture_output=True, text=True)
-    assert r.returncode == 1, f"mutant {name} survived:\n{r.stdout[-2000:]}"
+    if src.count(orig) < 1:
+        return -1, "mutation site not found"
+    tmp = tempfile.mkdtemp(prefix=f"mut_{name}_")
+    try:
+        root = os.path.join(tmp, "root")
+        shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(root, "oracle"),
+                        ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
+        with open(os.path.join(root, "oracle", "oracle.c"), "w") as f:
+            f.write(src.replace(orig, mut, 1))
+        subprocess.run([sys.executable, os.path.join(root, "oracle", "build.py")], check=True,
+                       capture_output=True)
+        os.symlink(os.path.join(ROOT, "scenes"), os.path.join(root, "scenes"))
+        shutil.copytree(os.path.join(ROOT, "tests"), os.path.join(root, "tests"),
+                        ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
+        env = dict(os.environ, PYTHONPATH=root, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="2")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                            "-m", "not gpu", pins], cwd=root, env=env, capture_output=True,
+                           text=True)
+        return r.returncode, r.stdout[-2000:]
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+@pytest.fixture(scope="module")
+def mutant_results():
+    """Every mutant built and checked once, several at a time."""
+    workers = max(1, min(8, (os.cpu_count() or 2) // 2))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        futs = {m[0]: ex.submit(_run_mutant, *m) for m in MUTANTS}
+        return {k: f.result() for k, f in futs.items()}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, mutant_results):
+    rc, out = mutant_results[name]
+    assert rc != -1, "mutation site not found"
+    assert rc == 1, f"mutant {name} survived:\n{out}"
