@@ -240,7 +240,7 @@ def _batch_item(desc):
     return c["depth"], c["rgb"]
 
 
-def batched_speedup(gg, torch, dev, procs, tune=True):
+def batched_speedup(gg, torch, dev, procs, tune=True, tuning=None):
     """Batching workload: 24 target views of uneven resolution, view count and
     bin count.  One hipGraph launch of the batched plan against the 24 plain
     sequences (splat_views + tsdf_integrate per item), same outputs."""
@@ -263,7 +263,8 @@ def batched_speedup(gg, torch, dev, procs, tune=True):
                           tsdf=gg.tsdf_params(scenes.tsdf_params(num_bins=desc["d"], trunc=4.0))))
     voxels = sum(it["tgt"].width * it["tgt"].height * it["tsdf"].num_bins for it in items)
     pixels = sum(it["tgt"].width * it["tgt"].height for it in items)
-    tuning, ttimes = autotune.tune_batch(items) if tune else ((0, 0), {})
+    if tuning is None:
+        tuning, ttimes = autotune.tune_batch(items) if tune else ((0, 0), {})
     plan = gg.BatchPlan(items, *tuning)
     outs = [dict(F=it["F"], W=it["W"]) for it in items]
 
@@ -514,6 +515,9 @@ def main():
     ap.add_argument("--no-network", action="store_true")
     ap.add_argument("--no-ewa", action="store_true")
     ap.add_argument("--no-paper-shape", action="store_true")
+    ap.add_argument("--batch-tuning", default="",
+                    help="batched plan 'threads_per_workgroup,blocks_per_cu' instead of autotuning "
+                         "(profiling runs pin what the timed runs pick)")
     ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
                     help="2: the splat on its own stream, overlapping the fusion; 1: one stream")
     ap.add_argument("--tile", default="",
@@ -724,7 +728,8 @@ def main():
     if not args.no_batch:
         del depth, rgb, ws_s, ws_t, ws_t2, wss
         torch.cuda.empty_cache()
-        out["batched"] = batched_speedup(gg, torch, dev, procs)
+        bt = tuple(int(v) for v in args.batch_tuning.split(",")) if args.batch_tuning else None
+        out["batched"] = batched_speedup(gg, torch, dev, procs, tuning=bt)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, depth_h, rgb_h)
     print(json.dumps(out), flush=True)
