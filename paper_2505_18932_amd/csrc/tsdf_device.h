@@ -50,6 +50,42 @@ __device__ __forceinline__ float window_nu(const float *tile, int li, int lj, in
   return nu;
 }
 
+// nu for a pixel whose whole window lies inside the image (radius R known
+// at compile time): the same terms in the same row-major order, with holes
+// staged as NaN -- d_q - NaN is NaN and fminf(NaN, tau^2) = tau^2, which is
+// exactly a hole's term -- so no test is needed per neighbour.
+template <int R>
+__device__ __forceinline__ float window_nu_interior(const float *tile, int li, int lj, float dq,
+                                                    float tw2) {
+  const float *w = tile + (lj - R) * kConfLW + (li - R);
+  float nu = 0.0f;
+#pragma unroll
+  for (int dy = 0; dy <= 2 * R; ++dy)
+#pragma unroll
+    for (int dx = 0; dx <= 2 * R; ++dx) {
+      const float dd = dq - w[dy * kConfLW + dx];
+      nu = nu + fminf(dd * dd, tw2);
+    }
+  return nu;
+}
+
+__device__ __forceinline__ float window_nu_fast(const float *tile, int li, int lj, float dq,
+                                                const ConfArgs &a) {
+  switch (a.radius) {
+    case 0: return window_nu_interior<0>(tile, li, lj, dq, a.tw2);
+    case 1: return window_nu_interior<1>(tile, li, lj, dq, a.tw2);
+    case 2: return window_nu_interior<2>(tile, li, lj, dq, a.tw2);
+    case 3: return window_nu_interior<3>(tile, li, lj, dq, a.tw2);
+    case 4: return window_nu_interior<4>(tile, li, lj, dq, a.tw2);
+    case 5: return window_nu_interior<5>(tile, li, lj, dq, a.tw2);
+    case 6: return window_nu_interior<6>(tile, li, lj, dq, a.tw2);
+    default: return window_nu_interior<kMaxR>(tile, li, lj, dq, a.tw2);
+  }
+}
+
+// The window's tile staged in LDS; pixels without a usable depth are staged
+// as NaN (both window forms treat NaN as a hole), pixels outside the image
+// as 0 (only the bounds-checked form can reach them, and it skips them).
 __device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
                                            const ConfArgs &a) {
   const int r = a.radius;
@@ -58,7 +94,10 @@ __device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0,
     const int ly = e / tw, lx = e - ly * tw;
     const int gi = i0 - r + lx, gj = j0 - r + ly;
     float v = 0.0f;
-    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = gmem(dk)[(size_t)gj * a.Ws + gi];
+    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) {
+      v = gmem(dk)[(size_t)gj * a.Ws + gi];
+      if (!depth_ok(v)) v = __builtin_nanf("");
+    }
     // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
     // relative to the fixed centre origin
     tile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
@@ -73,12 +112,16 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
   __syncthreads();
   const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
   const int i = i0 + lx, j = j0 + ly;
+  // every window of the tile inside the image: the unchecked form
+  const bool interior = i0 >= a.radius && j0 >= a.radius &&
+                        i0 + kConfTX + a.radius <= a.Ws && j0 + kConfTY + a.radius <= a.Hs;
   if (ly < kConfTY && i < a.Ws && j < a.Hs) {
     const int li = lx + kMaxR, lj = ly + kMaxR;
     const float dq = tile[lj * kConfLW + li];
     float2 rec = make_float2(-INFINITY, 0.0f);
     if (depth_ok(dq)) {
-      const float nu = window_nu(tile, li, lj, i, j, dq, a);
+      const float nu = interior ? window_nu_fast(tile, li, lj, dq, a)
+                                : window_nu(tile, li, lj, i, j, dq, a);
       const float om = (nu == 0.0f) ? 1.0f : fminf(a.scale / sqrtf(nu / a.n2), 1.0f);
       rec = make_float2(dq, om);
     }
