@@ -269,80 +269,155 @@ __device__ __forceinline__ float from_fixed(unsigned long long v, int E) {
   return (float)ldexp((double)(long long)v, -E);
 }
 
+// The window parameters of the backward as the confidence kernel's record,
+// so both share the tile staging and the window statistic.
+__device__ __forceinline__ ConfArgs conf_of(const TsdfBackArgs &a) {
+  ConfArgs c{};
+  c.depth = a.depth;
+  c.Ws = a.Ws;
+  c.Hs = a.Hs;
+  c.K = a.K;
+  c.radius = a.radius;
+  c.tw2 = a.tw2;
+  c.n2 = a.n2;
+  c.scale = a.scale;
+  return c;
+}
+
 // dL/dnu at each source pixel: dL/domega * domega/dnu where the min(., 1)
-// of the weight is inactive and nu > 0.
+// of the weight is inactive and nu > 0.  nu is the confidence kernel's
+// window statistic (same tile staging, same terms in the same order); one
+// 32 x 8 tile of view blockIdx.z per workgroup.
 __global__ __launch_bounds__(256) void tsdf_bwd_nu_kernel(TsdfBackArgs a) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (i >= a.ns) return;
-  const size_t o = (size_t)k * a.ns + i;
+  __shared__ float tile[kConfLH * kConfLW];
+  const ConfArgs c = conf_of(a);
+  const int k = blockIdx.z, i0 = blockIdx.x * kConfTX, j0 = blockIdx.y * kConfTY;
+  stage_tile(tile, a.depth + (size_t)k * a.ns, i0, j0, c);
+  __syncthreads();
+  const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool interior = i0 >= a.radius && j0 >= a.radius && i0 + kConfTX + a.radius <= a.Ws &&
+                        j0 + kConfTY + a.radius <= a.Hs;
+  if (ly >= kConfTY || i >= a.Ws || j >= a.Hs) return;
+  const size_t o = (size_t)k * a.ns + (size_t)j * a.Ws + i;
   const int E = fixed_exponent(a);
   float out = 0.0f;
   const float gw = (E == INT_MIN) ? 0.0f : from_fixed(a.acc_w[o], E);
-  const float *dk = a.depth + (size_t)k * a.ns;
-  const float dq = dk[i];
+  const int li = lx + kMaxR, lj = ly + kMaxR;
+  const float dq = tile[lj * kConfLW + li];  // NaN for a hole
   if (gw != 0.0f && depth_ok(dq)) {
-    const int qy = (int)(i / (uint32_t)a.Ws), qx = (int)(i - (uint32_t)qy * a.Ws);
-    float nu = 0.0f;
-    for (int dy = -a.radius; dy <= a.radius; ++dy) {
-      const int jj = qy + dy;
-      if (jj < 0 || jj >= a.Hs) continue;
-      for (int dx = -a.radius; dx <= a.radius; ++dx) {
-        const int ii = qx + dx;
-        if (ii < 0 || ii >= a.Ws) continue;
-        const float dn = dk[(size_t)jj * a.Ws + ii];
-        float term;
-        if (depth_ok(dn)) {
-          const float dd = dq - dn;
-          term = fminf(dd * dd, a.tw2);
-        } else {
-          term = a.tw2;
-        }
-        nu = nu + term;
-      }
-    }
+    const float nu = interior ? window_nu_fast(tile, li, lj, dq, c)
+                              : window_nu(tile, li, lj, i, j, dq, c);
     if (nu > 0.0f) {
       const float raw = a.scale / sqrtf(nu / a.n2);
       if (raw < 1.0f) out = gw * ((-0.5f * raw) / nu);
     }
   }
-  a.gnu[o] = out;
+  gmem(a.gnu)[o] = out;
 }
 
-// g_depth_in[r] = direct (fixed point) + window terms of r as a centre and
-// as a neighbour of each q in its window.
-__global__ __launch_bounds__(256) void tsdf_bwd_finish_kernel(TsdfBackArgs a) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (i >= a.ns) return;
-  const size_t o = (size_t)k * a.ns + i;
-  const int E = fixed_exponent(a);
-  float g = (E == INT_MIN) ? 0.0f : from_fixed(a.acc_D[o], E);
-  const float *dk = a.depth + (size_t)k * a.ns;
-  const float *gn = a.gnu + (size_t)k * a.ns;
-  const float dr = dk[i];
-  if (depth_ok(dr)) {
-    const int ry = (int)(i / (uint32_t)a.Ws), rx = (int)(i - (uint32_t)ry * a.Ws);
-    const float gr = gn[i];
-    for (int dy = -a.radius; dy <= a.radius; ++dy) {
-      const int jj = ry + dy;
-      if (jj < 0 || jj >= a.Hs) continue;
-      for (int dx = -a.radius; dx <= a.radius; ++dx) {
-        const int ii = rx + dx;
-        if (ii < 0 || ii >= a.Ws || (dx == 0 && dy == 0)) continue;
-        const size_t n = (size_t)jj * a.Ws + ii;
-        const float dn = dk[n];
-        if (!depth_ok(dn)) continue;
-        const float dd = dr - dn;  // r as the centre
-        if (dd * dd < a.tw2) {
-          if (gr != 0.0f) g += gr * 2.0f * dd;
-          const float gq = gn[n];  // r as a neighbour of n: d(nu_n)/dD_r = -2 (D_n - D_r)
-          if (gq != 0.0f) g -= gq * 2.0f * (dn - dr);
-        }
+// The window terms of g_depth_in for a pixel r with a usable depth dr, in
+// row-major order over the window without its centre: r as the centre
+// (gr = gnu_r) and r as a neighbour of each n (gq = gnu_n).  Bounds-checked
+// form; holes in `tile` are NaN and fail depth_ok.
+__device__ __forceinline__ float finish_window(const float *tile, const float *gtile, int li,
+                                               int lj, int i, int j, float dr, float gr, float g,
+                                               const TsdfBackArgs &a) {
+  for (int dy = -a.radius; dy <= a.radius; ++dy) {
+    const int jj = j + dy;
+    if (jj < 0 || jj >= a.Hs) continue;
+    for (int dx = -a.radius; dx <= a.radius; ++dx) {
+      const int ii = i + dx;
+      if (ii < 0 || ii >= a.Ws || (dx == 0 && dy == 0)) continue;
+      const int l = (lj + dy) * kConfLW + (li + dx);
+      const float dn = tile[l];
+      if (!depth_ok(dn)) continue;
+      const float dd = dr - dn;
+      if (dd * dd < a.tw2) {
+        if (gr != 0.0f) g += gr * 2.0f * dd;
+        const float gq = gtile[l];
+        if (gq != 0.0f) g -= gq * 2.0f * (dn - dr);
       }
     }
   }
-  a.g_depth_in[o] = g;
+  return g;
+}
+
+// The same for a pixel whose window lies inside the image: a hole's NaN
+// makes dd NaN and fails dd^2 < tau^2, exactly as the hole test skips it.
+template <int R>
+__device__ __forceinline__ float finish_window_interior(const float *tile, const float *gtile,
+                                                        int li, int lj, float dr, float gr,
+                                                        float g, float tw2) {
+#pragma unroll
+  for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+    for (int dx = -R; dx <= R; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      const int l = (lj + dy) * kConfLW + (li + dx);
+      const float dn = tile[l];
+      const float dd = dr - dn;
+      if (dd * dd < tw2) {
+        if (gr != 0.0f) g += gr * 2.0f * dd;
+        const float gq = gtile[l];
+        if (gq != 0.0f) g -= gq * 2.0f * (dn - dr);
+      }
+    }
+  return g;
+}
+
+__device__ __forceinline__ float finish_window_fast(const float *tile, const float *gtile, int li,
+                                                    int lj, float dr, float gr, float g,
+                                                    const TsdfBackArgs &a) {
+  switch (a.radius) {
+    case 0: return finish_window_interior<0>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 1: return finish_window_interior<1>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 2: return finish_window_interior<2>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 3: return finish_window_interior<3>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 4: return finish_window_interior<4>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 5: return finish_window_interior<5>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    case 6: return finish_window_interior<6>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+    default: return finish_window_interior<kMaxR>(tile, gtile, li, lj, dr, gr, g, a.tw2);
+  }
+}
+
+// g_depth_in[r] = direct (fixed point) + window terms of r as a centre and
+// as a neighbour of each q in its window; one 32 x 8 tile of view
+// blockIdx.z per workgroup, depths and gnu staged in LDS with the halo.
+__global__ __launch_bounds__(256) void tsdf_bwd_finish_kernel(TsdfBackArgs a) {
+  __shared__ float tile[kConfLH * kConfLW];
+  __shared__ float gtile[kConfLH * kConfLW];
+  const ConfArgs c = conf_of(a);
+  const int k = blockIdx.z, i0 = blockIdx.x * kConfTX, j0 = blockIdx.y * kConfTY;
+  stage_tile(tile, a.depth + (size_t)k * a.ns, i0, j0, c);
+  {
+    const int r = a.radius, tw = kConfTX + 2 * r, th = kConfTY + 2 * r;
+    const float *gn = a.gnu + (size_t)k * a.ns;
+    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
+      const int ly = e / tw, lx = e - ly * tw;
+      const int gi = i0 - r + lx, gj = j0 - r + ly;
+      float v = 0.0f;
+      if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = gmem(gn)[(size_t)gj * a.Ws + gi];
+      gtile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
+    }
+  }
+  __syncthreads();
+  const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool interior = i0 >= a.radius && j0 >= a.radius && i0 + kConfTX + a.radius <= a.Ws &&
+                        j0 + kConfTY + a.radius <= a.Hs;
+  if (ly >= kConfTY || i >= a.Ws || j >= a.Hs) return;
+  const size_t o = (size_t)k * a.ns + (size_t)j * a.Ws + i;
+  const int E = fixed_exponent(a);
+  float g = (E == INT_MIN) ? 0.0f : from_fixed(a.acc_D[o], E);
+  const int li = lx + kMaxR, lj = ly + kMaxR;
+  const float dr = tile[lj * kConfLW + li];
+  if (depth_ok(dr)) {
+    const float gr = gtile[lj * kConfLW + li];
+    g = interior ? finish_window_fast(tile, gtile, li, lj, dr, gr, g, a)
+                 : finish_window(tile, gtile, li, lj, i, j, dr, gr, g, a);
+  }
+  gmem(a.g_depth_in)[o] = g;
 }
 
 int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s) {
@@ -352,7 +427,7 @@ int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s) {
                        (size_t)a.K * a.ns * 2 + 1);
     if (int rc = check_hip(hipGetLastError(), "zero_u64_kernel")) return rc;
   }
-  const dim3 gp((a.npix + 255) / 256), gs((a.ns + 255) / 256, a.K);
+  const dim3 gp((a.npix + 255) / 256);
   {
     KernelTimer t("tsdf_bwd_max", s);
     hipLaunchKernelGGL(tsdf_bwd_max_kernel, gp, dim3(256), 0, s, a);
@@ -363,13 +438,14 @@ int launch_tsdf_backward(const TsdfBackArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(tsdf_bwd_scatter_kernel, gp, dim3(256), 0, s, a);
     if (int rc = check_hip(hipGetLastError(), "tsdf_bwd_scatter_kernel")) return rc;
   }
+  const dim3 gt((a.Ws + kConfTX - 1) / kConfTX, (a.Hs + kConfTY - 1) / kConfTY, a.K);
   {
     KernelTimer t("tsdf_bwd_nu", s);
-    hipLaunchKernelGGL(tsdf_bwd_nu_kernel, gs, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(tsdf_bwd_nu_kernel, gt, dim3(kConfTX * kConfTY), 0, s, a);
     if (int rc = check_hip(hipGetLastError(), "tsdf_bwd_nu_kernel")) return rc;
   }
   KernelTimer t("tsdf_bwd_finish", s);
-  hipLaunchKernelGGL(tsdf_bwd_finish_kernel, gs, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(tsdf_bwd_finish_kernel, gt, dim3(kConfTX * kConfTY), 0, s, a);
   return check_hip(hipGetLastError(), "tsdf_bwd_finish_kernel");
 }
 
