@@ -529,7 +529,7 @@ def main():
                     help="also run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the geometry stage on a single "
+        print("bench.py measures one GPU: the library runs the geometry stage on a single "
               "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

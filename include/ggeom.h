@@ -51,7 +51,7 @@ extern "C" {
 #define GG_ERR_INVALID (-1)     /* an argument is out of range or NULL          */
 #define GG_ERR_WORKSPACE (-2)   /* ws is NULL or ws_bytes too small             */
 #define GG_ERR_HIP (-3)         /* a HIP runtime call or launch failed          */
-#define GG_ERR_UNSUPPORTED (-4) /* valid but beyond this build's limits         */
+#define GG_ERR_UNSUPPORTED (-4) /* valid but beyond the library's limits        */
 
 #define GG_MAX_VIEWS 16     /* K per call                                    */
 #define GG_MAX_BINS 4096    /* D per volume                                  */

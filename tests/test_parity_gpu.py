@@ -2,8 +2,8 @@
 
 Integer outputs (winner indices, zero-crossing bins) and the fused volume
 F / W are compared bitwise; colour, opacity and depth within 1e-5 relative
-with a floor of 1e-3 of the largest reference magnitude (north-star
-tolerance).  Sizes span several tiles with ragged tails; full-size workloads
+with a floor of 1e-3 of the largest reference magnitude (the FP32
+tolerance of the problem statement, floored for values near zero).  Sizes span several tiles with ragged tails; full-size workloads
 are compared on sampled target pixels the oracle computes one by one.
 """
 import numpy as np
