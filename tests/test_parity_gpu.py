@@ -154,6 +154,44 @@ def test_tiny_and_ragged_images(wh):
     check_tsdf(c, depth)
 
 
+@pytest.mark.parametrize("window", [1, 3, 5, 7, 9, 11, 13, 15])
+def test_every_confidence_window(window):
+    """Each odd window side 1 .. 15 has its own unrolled interior form in the
+    confidence kernel and in both window kernels of the fusion backward; at
+    80 x 40 every one of them meets interior and border tiles.  Volume
+    bitwise, depth gradient to the gradient tolerance."""
+    c = small(w=80, h=40, k=3, bins=24)
+    c["tsdf"] = dict(c["tsdf"], conf_window=window)
+    depth, _ = to_dev(c)
+    (F, W, dep, b), _ = check_tsdf(c, depth)
+    rng = np.random.default_rng(window)
+    g = rng.standard_normal(dep.shape).astype(np.float32)
+    g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, torch.from_numpy(g).to(DEV))
+    gd = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
+    torch.cuda.synchronize()
+    ref = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g.ravel())
+    assert np.abs(ref).max() > 0
+    grad_close(gd.cpu().numpy(), ref, f"tsdf depth gradient, window {window}")
+
+
+def test_library_maxima():
+    """The declared limits: 16 views per call, 4096 bins, and a row of 16384
+    pixels (the widest image the host accepts)."""
+    c = scenes.small_ring(seed=4, width=9, height=7, k=16, n_ring=17, bins=32, noise=0.01,
+                          holes=0.05)
+    assert c["depth"].shape[0] == 16
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+    c = small(w=6, h=5, k=2, bins=4096)
+    depth, _ = to_dev(c)
+    check_tsdf(c, depth)
+    c = small(w=16384, h=2, k=2, bins=8)
+    depth, rgb = to_dev(c)
+    check_splat(c, depth, rgb)
+    check_tsdf(c, depth)
+
+
 def test_single_view_and_many_views():
     for k in (1, 8):
         c = small(k=k)
