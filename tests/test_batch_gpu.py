@@ -74,13 +74,15 @@ def test_batch_shuffled_order_and_replays():
 
 
 def test_batch_mixed_items_carry_and_mask():
-    """Items without splat, odd and tiny bin counts, a single view, a mask and
-    an in-place carried volume."""
+    """Items without splat, odd and tiny bin counts, a single view, a mask,
+    an in-place carried volume and confidence windows other than 7."""
     base = _items(n=4)
     small = scenes.small_ring(seed=3, width=41, height=23, k=1, bins=7)
     base.append(dict(src=small["src"], tgt=small["tgt"], depth=torch.from_numpy(small["depth"]).to(DEV),
                      tsdf=small["tsdf"]))  # no rgb, K=1, D=7 (one bin per thread)
-    base[1]["tsdf"] = dict(base[1]["tsdf"], num_bins=66)  # two bins per thread
+    base[1]["tsdf"] = dict(base[1]["tsdf"], num_bins=66, conf_window=11)  # two bins per thread
+    base[0]["tsdf"] = dict(base[0]["tsdf"], conf_window=15)
+    base[4]["tsdf"] = dict(base[4]["tsdf"], conf_window=1)
     rng = np.random.default_rng(1)
     it = base[2]
     it["mask"] = torch.from_numpy(rng.uniform(0, 1, (it["tgt"].height, it["tgt"].width))
