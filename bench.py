@@ -698,6 +698,10 @@ def main():
         "roofline_valu": roof_valu,
         "kernel_ms_per_step": {k: round(v[0] / max(nb, 1), 4) for k, v in kt.items()},
     }
+    if args.streams > 1:
+        out["kernel_ms_note"] = ("HIP events around each launch, in an untimed pass of the same "
+                                 "two-stream pipeline: a second-stream kernel's time includes "
+                                 "waiting for compute units that the fusion holds")
     if serial_ms is not None:
         out["one_stream_ms_per_step"] = round(serial_ms, 4)
     if not args.no_bwd:
