@@ -49,6 +49,25 @@ def make_frames(n, procs):
     return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
 
 
+def measure_copy_gbs(torch, dev, mib=1024, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second, GB/s) of a
+    `mib` MiB tensor, timed with HIP events on the current stream."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def kernel_sha():
     h = hashlib.sha256()
     for name in ("tsdf.hip", "tsdf_device.h", "ggeom_internal.h"):
@@ -678,6 +697,16 @@ def main():
                      "unit": "T lane-instructions/s", "frac": round(ach / VALU_PEAK_TLANE, 4),
                      "lane_instructions_per_launch": lane_ops,
                      "source": "SQ_INSTS_VALU of the committed counter summary"}
+
+    # the same GPU's copy bandwidth (1 GiB device-to-device, read + write), for comparison
+    cb = measure_copy_gbs(torch, dev)
+    roof["copy_gb_s"] = round(cb, 1)
+    roof["frac_of_copy"] = round(achieved / cb, 4)
+    tr = roof["traffic"]
+    if tr is not None:
+        # counted HBM-side bytes (read + write of the committed counter summary) over the same time
+        roof["traffic_gb_s"] = round(tr / (int_ms * 1e-3) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_gb_s"] / HBM_PEAK_GBS, 4)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
