@@ -16,7 +16,6 @@ samples, so the 1 mm check bounds the skip rate loosely and a second check at
 h = 1e-5 m, where kinks are rare, bounds it tightly.
 """
 import numpy as np
-import pytest
 
 import oracle
 import scenes

@@ -8,7 +8,6 @@ import numpy as np
 import pytest
 import torch
 
-import paper_2505_18932_amd as gg
 from paper_2505_18932_amd import _lib as L
 
 pytestmark = pytest.mark.gpu
