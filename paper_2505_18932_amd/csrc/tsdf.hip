@@ -164,11 +164,12 @@ int launch_extract_backward(const ExtractArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// adjoint of the fusion.  (1) per pixel with a crossing, recompute the two
-// voxels' per-view terms and find max |contribution|; (2) scatter them into
-// per-source-pixel 64-bit fixed-point accumulators (integer addition is
-// associative: the result does not depend on arrival order); (3) chain the
-// weight gradient through nu of its window; (4) gather the window terms.
+// adjoint of the fusion.  (1) per pixel with a crossing, bound |contribution|
+// of its two voxels' per-view terms from the voxels alone; (2) recompute the
+// terms and scatter them into per-source-pixel 64-bit fixed-point
+// accumulators scaled by that bound (integer addition is associative: the
+// result does not depend on arrival order); (3) chain the weight gradient
+// through nu of its window; (4) gather the window terms.
 
 __global__ void zero_u64_kernel(unsigned long long *p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -209,19 +210,27 @@ __device__ __forceinline__ void voxel_adjoint(const TsdfBackArgs &a, uint32_t pi
   }
 }
 
+// An upper bound on |dD| and |dw| over every view sample of the pixel's two
+// voxels, from the voxel alone: the table weight is at most 1 and the clamp
+// keeps |c| <= tau, so |dD| <= |gF| / W and |dw| <= |gF| (tau + |F|) / W.
+// Rounding is monotone, so the bound evaluated in FP32 also bounds the
+// FP32 terms voxel_adjoint computes.
+__device__ __forceinline__ float voxel_bound(const TsdfBackArgs &a, uint32_t pix, int d,
+                                             float gF) {
+  const size_t o = (size_t)pix * a.D + d;
+  const float Wn = gmem(a.W)[o], Fv = gmem(a.F)[o];
+  const float tau = gload2(a.bins + d).y, ag = fabsf(gF);
+  return fmaxf(ag / Wn, (ag * (tau + fabsf(Fv))) / Wn);
+}
+
 __global__ __launch_bounds__(256) void tsdf_bwd_max_kernel(TsdfBackArgs a) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   float m = 0.0f;
   if (p < a.npix) {
-    const int d = a.bin[p];
+    const int d = gmem(a.bin)[p];
     if (d >= 0) {
       const float2 g = reinterpret_cast<const float2 *>(a.g_F2)[p];
-      voxel_adjoint(a, p, d, g.x, [&](int, uint32_t, float dD, float dw) {
-        m = fmaxf(m, fmaxf(fabsf(dD), fabsf(dw)));
-      });
-      voxel_adjoint(a, p, d + 1, g.y, [&](int, uint32_t, float dD, float dw) {
-        m = fmaxf(m, fmaxf(fabsf(dD), fabsf(dw)));
-      });
+      m = fmaxf(voxel_bound(a, p, d, g.x), voxel_bound(a, p, d + 1, g.y));
     }
   }
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
