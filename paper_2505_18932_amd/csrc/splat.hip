@@ -113,6 +113,8 @@ __global__ __launch_bounds__(256) void splat_backward_kernel(SplatArgs a) {
     const float dydD = (h1 * Z - X1 * h2) / Z2;
     const float sig = V.sscale * (D / Z);
     const float dsdD = V.sscale * V.P.c[2] / Z2;
+    // per source pixel: the Gaussian's footprint terms of dG/dD as products
+    const float inv_s2 = 1.0f / g.s2, ks = dsdD / (sig * g.s2);
     const uint8_t *cq = a.rgb + ((size_t)k * a.ns + q) * 3;
     const float c[3] = {(float)cq[0] / 255.0f, (float)cq[1] / 255.0f, (float)cq[2] / 255.0f};
     const size_t kt = (size_t)k * a.nt;
@@ -127,18 +129,20 @@ __global__ __launch_bounds__(256) void splat_backward_kernel(SplatArgs a) {
         const int32_t win = a.fw_win[kt + p];
         if (win < 0) continue;
         if (!(g.z <= a.fw_depth[kt + p] * a.band)) continue;
+        // G exactly as the forward evaluates it: its equality with 1 selects the
+        // opacity term below, as it selected the tape's count in the forward
         const float G = expf((-0.5f * d2) / g.s2);
-        const float n = tape[p];
+        const float inv_n = 1.0f / tape[p];
         float dLdG = 0.0f;
         if (grgb) {
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
             const float gr = grgb[ch * a.nt + p];
-            const float contrib = (gr * G) / n;
+            const float contrib = (gr * G) * inv_n;
             if (ch == 0) gc0 += contrib;
             if (ch == 1) gc1 += contrib;
             if (ch == 2) gc2 += contrib;
-            dLdG += (gr * (c[ch] - frgb[ch * a.nt + p])) / n;
+            dLdG += (gr * (c[ch] - frgb[ch * a.nt + p])) * inv_n;
           }
         }
         if (a.g_alpha) {
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(256) void splat_backward_kernel(SplatArgs a) {
           dLdG += a.g_alpha[kt + p] * others;
         }
         const float dx = ((float)aa + 0.5f) - g.x, dy = ((float)b + 0.5f) - g.y;
-        const float dGdD = G * ((dx * dxdD + dy * dydD) / g.s2 + d2 * dsdD / (sig * g.s2));
+        const float dGdD = G * ((dx * dxdD + dy * dydD) * inv_s2 + d2 * ks);
         gD += dLdG * dGdD;
         if (a.g_depth && (uint32_t)win == q) gD += a.g_depth[kt + p] * h2;
       }
