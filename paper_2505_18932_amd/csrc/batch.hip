@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__re
   __shared__ RasterLds lds;
   for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
-    raster_tile(items[wi.item].splat, wi.k, work_tile(wi), lds);
+    raster_tile<false>(items[wi.item].splat, wi.k, work_tile(wi), lds);
   });
 }
 

@@ -38,7 +38,7 @@ __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
 
 __global__ __launch_bounds__(256) void splat_raster_kernel(SplatArgs a) {
   __shared__ RasterLds L;
-  raster_tile(a, blockIdx.y, blockIdx.x, L);
+  raster_tile<true>(a, blockIdx.y, blockIdx.x, L);
 }
 
 uint32_t splat_tiles_per_splat(float r_max) {

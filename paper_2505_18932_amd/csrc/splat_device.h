@@ -248,6 +248,9 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
 
 // Z-test and band blend of target tile `tile` of view k (kTile * kTile
 // threads).
+// kKeepFirst: carry the thread's first entry from the z-test to the blend in
+// registers (more VGPRs, fewer loads); the results are the same either way.
+template <bool kKeepFirst>
 __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t tile,
                                             RasterLds &lds) {
   unsigned long long *zkey = lds.zkey, *sG = lds.sG, *sR = lds.sR, *sGr = lds.sGr, *sB = lds.sB,
@@ -265,12 +268,20 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
   const SplatView &V = a.views[k];
   const float *dk = a.depth + (size_t)k * a.ns;
   const uint8_t *ck = a.rgb + (size_t)k * a.ns * 3;
-  // z-test
+  // z-test.  With kKeepFirst the thread's first entry (most threads have one
+  // or two) keeps its index and footprint in registers for the blend pass.
+  uint32_t q_first = 0xffffffffu;
+  SplatGeom g_first;
+  g_first.ok = false;
   for (uint32_t e = beg + t; e < end; e += blockDim.x) {
     const uint32_t q = gmem(a.list)[e];
     if (q >= a.ns) continue;
     const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
     const SplatGeom g = splat_geom(V, gmem(dk)[q], i, j, a);
+    if (kKeepFirst && e == beg + t) {
+      q_first = q;
+      g_first = g;
+    }
     if (!g.ok) continue;
     const unsigned long long key = ((unsigned long long)__float_as_uint(g.z) << 32) | q;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
@@ -282,10 +293,16 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
   __syncthreads();
   // band blend
   for (uint32_t e = beg + t; e < end; e += blockDim.x) {
-    const uint32_t q = gmem(a.list)[e];
+    const bool first = kKeepFirst && e == beg + t;
+    const uint32_t q = first ? q_first : gmem(a.list)[e];
     if (q >= a.ns) continue;
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
-    const SplatGeom g = splat_geom(V, gmem(dk)[q], i, j, a);
+    SplatGeom g;
+    if (first) {
+      g = g_first;
+    } else {
+      const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
+      g = splat_geom(V, gmem(dk)[q], i, j, a);
+    }
     if (!g.ok) continue;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
     const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);
