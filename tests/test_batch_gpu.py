@@ -122,3 +122,35 @@ def test_batch_bins_per_thread(vec):
         plan.close()
     finally:
         lib.gg_set_volume_vector(0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_batch_random_mix(seed):
+    """Seeded random mixes of 3 to 12 small ring items: view counts 1 to 8,
+    ragged sizes, 2 to 199 bins, any confidence window, some items without
+    colour (no splat) or with a temporal mask; the one graph launch equals
+    the plain calls bitwise, on two replays."""
+    rng = np.random.default_rng(2000 + seed)
+    items = []
+    for n in range(int(rng.integers(3, 13))):
+        k = int(rng.integers(1, 9))
+        c = scenes.small_ring(seed=100 * seed + n, width=int(rng.integers(1, 120)),
+                              height=int(rng.integers(1, 80)), k=k, n_ring=max(8, k + 2),
+                              bins=int(rng.integers(2, 200)), noise=0.01,
+                              holes=float(rng.uniform(0.0, 0.2)))
+        it = dict(src=c["src"], tgt=c["tgt"], depth=torch.from_numpy(c["depth"]).to(DEV),
+                  splat=c["splat"],
+                  tsdf=dict(c["tsdf"], conf_window=int(rng.choice([1, 3, 5, 7, 9, 11, 13, 15]))))
+        if rng.uniform() < 0.8:
+            it["rgb"] = torch.from_numpy(c["rgb"]).to(DEV)
+        if rng.uniform() < 0.3:
+            it["mask"] = torch.from_numpy(
+                rng.uniform(0, 1.2, (c["tgt"].height, c["tgt"].width)).astype(np.float32)).to(DEV)
+        items.append(it)
+    refs = [_plain(it) for it in items]
+    plan = gg.BatchPlan(items)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        _check(items, refs)
+    plan.close()
