@@ -80,3 +80,22 @@ def test_full_video_two_frames(video_frames):
     assert (r0 > 0).mean() > 0.9
     _, acc = oracle.raymarch(c["src"], frames[0][0], c["tgt"], c["tsdf"])[:2]
     check(dict(c, depth=frames[1][0]), dprev=r0, acc=acc)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_cases(seed):
+    """Seeded random small ring scenes: 1 to 8 views, ragged sizes, 2 to 199
+    bins (the march's bounds), any confidence window, noise and holes, then a
+    second frame with the first one's output as the temporal input under a
+    random mask."""
+    rng = np.random.default_rng(3000 + seed)
+    k = int(rng.integers(1, 9))
+    c = scenes.small_ring(seed=seed, width=int(rng.integers(1, 90)), height=int(rng.integers(1, 60)),
+                          k=k, n_ring=max(8, k + 2), bins=int(rng.integers(2, 200)),
+                          noise=float(rng.uniform(0.0, 0.03)), holes=float(rng.uniform(0.0, 0.3)))
+    c["tsdf"] = dict(c["tsdf"], conf_window=int(rng.choice([1, 3, 5, 7, 9, 11, 13, 15])))
+    rd = check(c)
+    prev = oracle.raymarch(c["src"], c["depth"], c["tgt"], c["tsdf"])
+    mask = rng.uniform(0.0, 1.2, rd.shape).astype(np.float32)
+    c2 = dict(c, depth=(c["depth"] * np.float32(1.01)).astype(np.float32))
+    check(c2, dprev=prev[0], acc=prev[1], mask=mask)

@@ -166,3 +166,25 @@ def test_full_video_masks_and_filter(video_frames):
     assert np.array_equal(bits(m.cpu().numpy()), bits(mr))
     fr = oracle.temporal_filter(d1, mr, d0)
     assert np.array_equal(bits(f.cpu().numpy()), bits(fr))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_masks_and_filter(seed):
+    """Seeded random shapes and reduction factors: the difference masks and
+    the filtered depth (with random holes in both depths) bitwise."""
+    rng = np.random.default_rng(4000 + seed)
+    K, H, W = int(rng.integers(1, 9)), int(rng.integers(1, 120)), int(rng.integers(1, 200))
+    factor = int(rng.integers(1, 9))
+    b, a = _pair(seed, K, H, W)
+    d = rng.uniform(0.5, 5, (K, H, W)).astype(np.float32)
+    d[rng.random(d.shape) < 0.1] = 0
+    p = rng.uniform(0.5, 5, (K, H, W)).astype(np.float32)
+    p[rng.random(p.shape) < 0.1] = 0
+    m, f = gg.difference_masks(torch.from_numpy(b).to(DEV), torch.from_numpy(a).to(DEV),
+                               dict(factor=factor), depth=torch.from_numpy(d).to(DEV),
+                               depth_prev=torch.from_numpy(p).to(DEV))
+    torch.cuda.synchronize()
+    mref = oracle.difference_mask(b, a, factor=factor)
+    fref = oracle.temporal_filter(d, mref, p)
+    assert np.array_equal(bits(m.cpu().numpy()), bits(mref)), f"seed {seed}: masks"
+    assert np.array_equal(bits(f.cpu().numpy()), bits(fref)), f"seed {seed}: filtered depth"
