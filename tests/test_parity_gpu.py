@@ -450,3 +450,39 @@ def test_full_video_in_the_benchmark_launch(video_frames):
     assert np.array_equal(bits(so["depth"].cpu().numpy()), bits(sref["depth"]))
     close(so["rgb"].cpu().numpy(), sref["rgb"], what="rgb")
     close(so["alpha"].cpu().numpy(), sref["alpha"], what="alpha")
+
+
+def test_backward_at_the_streaming_size(streaming_frame):
+    """The adjoints at 1920x1080, K=8, D=256 (the backward the benchmark
+    times there), through properties that hold at any size: a second call
+    agrees bitwise, and doubling every upstream gradient doubles every input
+    gradient exactly (the fusion's fixed-point scale moves by one power of
+    two; every other step is a product with, or a sum of, doubled terms)."""
+    c, (d, r) = streaming_frame
+    depth, rgb = torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)
+    tp, sp = c["tsdf"], c["splat"]
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], tp)
+    so = gg.splat_views(c["src"], depth, rgb, c["tgt"], sp)
+    rng = np.random.default_rng(6)
+    g = torch.from_numpy(rng.standard_normal(dep.shape).astype(np.float32)).to(DEV)
+    gs = [torch.from_numpy(rng.standard_normal(so[k].shape).astype(np.float32)).to(DEV)
+          for k in ("rgb", "depth", "alpha")]
+
+    def fusion_grad(scale):
+        g2 = gg.tsdf_extract_depth_backward(c["tgt"], tp, F, W, b, g * scale)
+        return gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], tp, F, W, b, g2)
+
+    def splat_grad(scale):
+        return gg.splat_views_backward(c["src"], depth, rgb, c["tgt"], sp, so,
+                                       *(x * scale for x in gs))
+
+    a1, a2, a3 = fusion_grad(1.0), fusion_grad(1.0), fusion_grad(2.0)
+    s1, s2, s3 = splat_grad(1.0), splat_grad(1.0), splat_grad(2.0)
+    torch.cuda.synchronize()
+    assert torch.isfinite(a1).all() and (a1 != 0).sum() > 0.05 * a1.numel()
+    assert torch.equal(a1.view(torch.int32), a2.view(torch.int32)), "fusion gradient repeat"
+    assert torch.equal((2 * a1).view(torch.int32), a3.view(torch.int32)), "fusion gradient x2"
+    for x, y, z, what in zip(s1, s2, s3, ("depth", "colour")):
+        assert torch.isfinite(x).all() and (x != 0).any(), what
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32)), f"splat {what} repeat"
+        assert torch.equal((2 * x).view(torch.int32), z.view(torch.int32)), f"splat {what} x2"
