@@ -154,3 +154,37 @@ def test_batch_random_mix(seed):
         torch.cuda.synchronize()
         _check(items, refs)
     plan.close()
+
+
+def _full_size_items():
+    """The 24 batching items at their full resolutions.  Each item's views
+    are rendered at 1/8 scale (rendering all of them at full size takes
+    minutes on the host) and upsampled by repetition: full-size depth and
+    colour maps with the scene's structure, for the full-size cameras."""
+    out = []
+    for desc in scenes.config4_items():
+        w, h = desc["width"], desc["height"]
+        lo = scenes.config4_item(desc, scale=8)
+        seq = scenes.RingSequence(4, desc["seed"], 16, 1.0, w, h, desc["k"],
+                                  scenes.MovingSpheres(desc["seed"], 4),
+                                  target_angle=desc["angle"])
+        ys = np.minimum(np.arange(h) // 8, lo["depth"].shape[1] - 1)
+        xs = np.minimum(np.arange(w) // 8, lo["depth"].shape[2] - 1)
+        depth = np.ascontiguousarray(lo["depth"][:, ys][:, :, xs])
+        rgb = np.ascontiguousarray(lo["rgb"][:, ys][:, :, xs])
+        out.append(dict(src=seq.src, tgt=seq.tgt, depth=torch.from_numpy(depth).to(DEV),
+                        rgb=torch.from_numpy(rgb).to(DEV), splat=lo["splat"], tsdf=lo["tsdf"]))
+    return out
+
+
+def test_batch_full_size_benchmark_tuning():
+    """All 24 items at full size (2.6 G voxels) with the launch tuning the
+    benchmark measures (512 threads per fusion workgroup, 4 persistent
+    workgroups per CU): one graph launch equals the 24 plain call pairs."""
+    items = _full_size_items()
+    refs = [_plain(it) for it in items]
+    plan = gg.BatchPlan(items, 512, 4)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check(items, refs)
+    plan.close()
