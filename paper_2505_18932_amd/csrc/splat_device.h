@@ -304,6 +304,11 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
       g = splat_geom(V, gmem(dk)[q], i, j, a);
     }
     if (!g.ok) continue;
+    // the entry's colour (c = u8 / 255) and mask, once for all its pixels
+    const float c0 = (float)gmem(ck)[3 * (size_t)q + 0] / 255.0f;
+    const float c1 = (float)gmem(ck)[3 * (size_t)q + 1] / 255.0f;
+    const float c2 = (float)gmem(ck)[3 * (size_t)q + 2] / 255.0f;
+    const float m = a.mask_in ? gmem(a.mask_in)[(size_t)k * a.ns + q] : 0.0f;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
     const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);
     for (int b = b0; b <= b1; ++b)
@@ -314,17 +319,12 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
         const float zw = __uint_as_float((uint32_t)(zkey[lp] >> 32));
         if (!(g.z <= zw * a.band)) continue;
         const float G = expf((-0.5f * d2) / g.s2);
-        const float c0 = (float)gmem(ck)[3 * (size_t)q + 0] / 255.0f;
-        const float c1 = (float)gmem(ck)[3 * (size_t)q + 1] / 255.0f;
-        const float c2 = (float)gmem(ck)[3 * (size_t)q + 2] / 255.0f;
         atomicAdd(&sG[lp], (unsigned long long)llrint((double)G * kFixG));
         atomicAdd(&sR[lp], (unsigned long long)llrint((double)(G * c0) * kFixG));
         atomicAdd(&sGr[lp], (unsigned long long)llrint((double)(G * c1) * kFixG));
         atomicAdd(&sB[lp], (unsigned long long)llrint((double)(G * c2) * kFixG));
-        if (a.mask_in) {
-          const float m = gmem(a.mask_in)[(size_t)k * a.ns + q];
+        if (a.mask_in)
           atomicAdd(&sM[lp], (unsigned long long)llrint((double)(G * m) * kFixG));
-        }
         if (G < 1.0f)
           atomicAdd(&sL[lp], (unsigned long long)llrint((double)logf(1.0f - G) * kFixL));
         else
