@@ -134,10 +134,16 @@ __global__ __launch_bounds__(256) void ewa_bin_kernel(EwaArgs a) {
     }
   }
   uint32_t *cnt = (kFill ? a.tile_cursor : a.tile_count) + (size_t)k * a.ntiles;
+  // the covered tiles in row-major order: column sx, row sy of the range
+  int sx = 0, sy = 0;
   for (int s = 0;; ++s) {
     const bool has = s < n;
     if (__ballot(has) == 0ull) break;
-    const uint32_t tile = has ? (uint32_t)((ty0 + s / nx) * a.ntx + (tx0 + s % nx)) : 0u;
+    const uint32_t tile = has ? (uint32_t)((ty0 + sy) * a.ntx + (tx0 + sx)) : 0u;
+    if (++sx == nx) {
+      sx = 0;
+      ++sy;
+    }
     const uint32_t slot = aggregated_slot<kFill>(cnt, tile, has);
     if (kFill && has) {
       const uint32_t pos = gmem(a.tile_offset)[(size_t)k * a.ntiles + tile] + slot;
