@@ -68,7 +68,7 @@ __device__ __forceinline__ EwaGauss ewa_gauss(const EwaArgs &a, int k, float D, 
   const float X1 = fmaf(D, h1, P.c[1]);
   const float Z = fmaf(D, h2, P.c[2]);
   if (!(Z > a.zmin)) return g;
-  const float inv = 1.0f / Z;
+  const float inv = recip_pos(Z);  // the correctly rounded 1 / Z
   const float u = X0 * inv, v = X1 * inv;
   const float ca = (u - a.cx) / a.fx, cb = (v - a.cy) / a.fy;
   const float sig = a.views[k].sscale * (D * inv), s2 = sig * sig;

@@ -24,7 +24,7 @@ __device__ __forceinline__ SplatGeom splat_geom(const SplatView &V, float D, uin
   const float X1 = fmaf(D, h1, V.P.c[1]);
   const float Z = fmaf(D, h2, V.P.c[2]);
   if (!(Z > a.zmin)) return g;
-  const float inv = 1.0f / Z;
+  const float inv = recip_pos(Z);  // the correctly rounded 1 / Z
   g.x = X0 * inv;
   g.y = X1 * inv;
   g.z = Z;
