@@ -486,3 +486,29 @@ def test_backward_at_the_streaming_size(streaming_frame):
         assert torch.isfinite(x).all() and (x != 0).any(), what
         assert torch.equal(x.view(torch.int32), y.view(torch.int32)), f"splat {what} repeat"
         assert torch.equal((2 * x).view(torch.int32), z.view(torch.int32)), f"splat {what} x2"
+
+
+def test_backward_at_the_differentiation_size():
+    """The three adjoints the benchmark times at 640x360, K=4, D=96 (random
+    upstream gradients on every output) against the oracle's adjoints, to the
+    gradient tolerance."""
+    c = scenes.config3()
+    depth, rgb = to_dev(c)
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    so = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    rng = np.random.default_rng(7)
+    g_t = rng.standard_normal(dep.shape).astype(np.float32)
+    g_rgb, g_z, g_a = (rng.standard_normal(so[k].shape).astype(np.float32)
+                       for k in ("rgb", "depth", "alpha"))
+    gd, gc = gg.splat_views_backward(c["src"], depth, rgb, c["tgt"], c["splat"], so,
+                                     *(torch.from_numpy(x).to(DEV) for x in (g_rgb, g_z, g_a)))
+    g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b,
+                                        torch.from_numpy(g_t).to(DEV))
+    gt = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
+    torch.cuda.synchronize()
+    rd, rc = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"], g_rgb,
+                                   g_z, g_a)
+    rt = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g_t.ravel())
+    grad_close(gc.cpu().numpy(), rc, "splat colour gradient")
+    grad_close(gd.cpu().numpy(), rd, "splat depth gradient")
+    grad_close(gt.cpu().numpy(), rt, "fusion depth gradient")
