@@ -294,14 +294,16 @@ def test_volume_tile_shape_does_not_change_results():
 
 def grad_close(got, ref, what):
     """Gradients: 1e-5 relative, norm-wise and per entry.  Each entry is a sum
-    of FP32 terms as large as the largest gradient, so below 1% of the
-    largest magnitude the per-entry bound becomes absolute, 1e-7 of the
-    largest (about two FP32 ulps of the largest term): the FP32 oracle itself
-    differs from the FP64 build by far more than this (cancellation)."""
+    of FP32 terms as large as the largest gradient, which FP32 summation in
+    any order carries to about n 2^-24 of that magnitude; so below 10% of the
+    largest magnitude the per-entry bound becomes absolute, 1e-6 of the
+    largest (about the rounding of sixteen such terms).  The FP32 oracle
+    itself differs from its FP64 build by up to about 1e-6 of the largest
+    gradient on the random scenes."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), what
-    floor = 1e-2 * np.abs(ref).max()
+    floor = 1e-1 * np.abs(ref).max()
     bad = np.abs(got - ref) > 1e-5 * np.maximum(np.abs(ref), floor)
     assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance; " \
                           f"worst {np.abs(got - ref)[bad].max():.3g}"
