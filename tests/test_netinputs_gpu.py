@@ -67,3 +67,34 @@ def test_network_inputs_full_video_frame(video_frames):
     ref = oracle.network_inputs(c["src"], c["tgt"], dep.cpu().numpy(), sp["rgb"].cpu().numpy(),
                                 sp["depth"].cpu().numpy(), sp["alpha"].cpu().numpy())
     assert np.array_equal(bits(out.cpu().numpy()), bits(ref))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_cases(seed):
+    """Seeded random small ring scenes (1 to 8 views, ragged sizes, holes):
+    the network inputs of the GPU splat and fusion outputs, and the blend of
+    random weights, bitwise."""
+    rng = np.random.default_rng(5000 + seed)
+    k = int(rng.integers(1, 9))
+    c = scenes.small_ring(seed=seed, width=int(rng.integers(1, 90)), height=int(rng.integers(1, 60)),
+                          k=k, n_ring=max(8, k + 2), bins=int(rng.integers(2, 160)),
+                          noise=0.01, holes=float(rng.uniform(0.0, 0.3)))
+    depth = torch.from_numpy(c["depth"]).to(DEV)
+    rgb = torch.from_numpy(c["rgb"]).to(DEV)
+    sp = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
+    _, _, dep, _ = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+    out = gg.network_inputs(c["src"], c["tgt"], dep, sp)
+    H, W = c["tgt"].height, c["tgt"].width
+    w = torch.from_numpy(rng.uniform(0, 1, (k, H, W)).astype(np.float32)).to(DEV)
+    wb = torch.from_numpy(rng.uniform(0, 1, (H, W)).astype(np.float32)).to(DEV)
+    bg = torch.from_numpy(rng.uniform(0, 1, (3, H, W)).astype(np.float32)).to(DEV)
+    o, d = gg.blend_views(sp["rgb"], sp["depth"], sp["alpha"], w, wb, bg)
+    torch.cuda.synchronize()
+    ref = oracle.network_inputs(c["src"], c["tgt"], dep.cpu().numpy(), sp["rgb"].cpu().numpy(),
+                                sp["depth"].cpu().numpy(), sp["alpha"].cpu().numpy())
+    assert np.array_equal(bits(out.cpu().numpy()), bits(ref)), f"seed {seed}: network inputs"
+    ro, rd = oracle.blend(sp["rgb"].cpu().numpy(), sp["depth"].cpu().numpy(),
+                          sp["alpha"].cpu().numpy(), w.cpu().numpy(), wb.cpu().numpy(),
+                          bg.cpu().numpy())
+    assert np.array_equal(bits(o.cpu().numpy()), bits(ro)), f"seed {seed}: blend colour"
+    assert np.array_equal(bits(d.cpu().numpy()), bits(rd)), f"seed {seed}: blend depth"
