@@ -275,3 +275,15 @@ def test_product_path_refuses_cpu_tensors():
     c = scenes.config1()
     with pytest.raises(ValueError, match="GPU"):
         ops.tsdf_integrate(c["src"], torch.from_numpy(c["depth"]), c["tgt"], c["tsdf"])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says
+    so, before it touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
