@@ -287,3 +287,12 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library every entry point raises at once: there
+    is no fallback path."""
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libggeom.so")
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="is not built"):
+        ops.workspace_size(3, 2, 8, 8, 8, 8, 16)
