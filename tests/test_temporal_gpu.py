@@ -188,3 +188,43 @@ def test_random_masks_and_filter(seed):
     fref = oracle.temporal_filter(d, mref, p)
     assert np.array_equal(bits(m.cpu().numpy()), bits(mref)), f"seed {seed}: masks"
     assert np.array_equal(bits(f.cpu().numpy()), bits(fref)), f"seed {seed}: filtered depth"
+
+
+def test_full_video_temporal_path(video_frames):
+    """The temporal path at the metric's size (1280x720, K=4, D=128) as the
+    benchmark's temporal leg runs it: masks and filtered depth between frames
+    0 and 1, the masked splat of the filtered depth, then the fusion of the
+    filtered depth carried in place under the splatted mask.  The oracle
+    follows 2000 sampled pixel columns through both frames, bitwise; the mask
+    splat is compared in full to the forward tolerance."""
+    c, frames = video_frames
+    (d0, rgb0), (d1, rgb1) = frames
+    src, tgt, sp, tp = c["src"], c["tgt"], c["splat"], c["tsdf"]
+    D = int(tp["num_bins"])
+    rng = np.random.default_rng(9)
+    pix = np.sort(rng.choice(tgt.width * tgt.height, 2000, replace=False)).astype(np.int32)
+    F, W, _, _ = gg.tsdf_integrate(src, torch.from_numpy(d0).to(DEV), tgt, tp)
+    F0 = F.reshape(-1, D)[pix].cpu().numpy()
+    W0 = W.reshape(-1, D)[pix].cpu().numpy()
+    m, filt = gg.difference_masks(torch.from_numpy(rgb1).to(DEV), torch.from_numpy(rgb0).to(DEV),
+                                  depth=torch.from_numpy(d1).to(DEV),
+                                  depth_prev=torch.from_numpy(d0).to(DEV))
+    so = gg.splat_views(src, filt, torch.from_numpy(rgb1).to(DEV), tgt, sp, mask=m)
+    F, W, dep, b = gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=W, F=F, W=W,
+                                     mask=so["mask_max"])
+    torch.cuda.synchronize()
+    mref = oracle.difference_mask(rgb1, rgb0)
+    fref = oracle.temporal_filter(d1, mref, d0)
+    assert np.array_equal(bits(filt.cpu().numpy()), bits(fref))
+    Fr0, Wr0 = oracle.integrate(src, d0, tgt, tp, pixels=pix)
+    assert np.array_equal(bits(F0), bits(Fr0)) and np.array_equal(bits(W0), bits(Wr0))
+    mmax = so["mask_max"].cpu().numpy()
+    Fr1, Wr1 = oracle.integrate(src, fref, tgt, tp, mask=mmax, F_prev=Fr0, W_prev=Wr0, pixels=pix)
+    assert np.array_equal(bits(F.reshape(-1, D)[pix].cpu().numpy()), bits(Fr1))
+    assert np.array_equal(bits(W.reshape(-1, D)[pix].cpu().numpy()), bits(Wr1))
+    dr, br = oracle.extract(Fr1, Wr1, tp)
+    assert np.array_equal(b.reshape(-1)[pix].cpu().numpy(), br)
+    ref = oracle.splat(src, fref, rgb1, tgt, sp, mask=mref)
+    close(so["mask"].cpu().numpy(), ref["mask"], what="mask")
+    close(mmax, ref["mask_max"], what="mask_max")
+    assert (mmax > 0.6).any() and (mmax < 1.0).any()
