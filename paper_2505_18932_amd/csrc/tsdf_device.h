@@ -422,11 +422,126 @@ __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, fl
   }
 }
 
-template <int V, int KC, bool kExact>
+// ---------------------------------------------------------------------------
+// The volume stream through LDS.  In the compute layout a wavefront holds 16
+// neighbouring pixels x 4 consecutive chunks (lane = chunk * 16 + pixel), so
+// a lane quad of a direct F / W access touches four pixels, i.e. four cache
+// lines, and the vector-memory unit takes one pass per line.  Per pixel the
+// wavefront's 4 chunks are one contiguous run of 4V floats, so instead the
+// loads and stores move each run with lane quads inside one 64-byte piece
+// (one line per quad), and the wavefront's own LDS slice exchanges the data
+// with the compute layout.  Needs V = 4 or 8, 16 pixels per wavefront row and
+// a chunk count per pixel that is a multiple of 4 (the launcher checks).
+
+template <int V>
+struct VolStage {
+  static constexpr int kRowF4 = V + 1;              // float4 per pixel row (+1 pad: no bank conflicts)
+  static constexpr int kArray = 16 * kRowF4 * 4;    // floats per array per wavefront
+  static constexpr int kWave = 2 * kArray;          // F and W
+  static constexpr int kIssues = V / 4;             // float4 per lane per array
+};
+
+// Orders one wavefront's LDS writes before its following LDS reads of other
+// lanes' data (LDS executes a wavefront's instructions in order; this keeps
+// the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void lds_put4(float *p, gg_v4f v) { *(gg_v4f *)p = v; }
+__device__ __forceinline__ gg_v4f lds_get4(const float *p) { return *(const gg_v4f *)p; }
+
+// Stream position of issue h of this lane: pixel row p (0..15) of the
+// wavefront and float4 j (0..V-1) of that pixel's run.
+template <int V>
+__device__ __forceinline__ void stage_pos(int h, uint32_t lane, uint32_t &p, uint32_t &j) {
+  const uint32_t f = (uint32_t)h * 64u + lane;
+  p = f / V;
+  j = f % V;
+}
+
+template <int V>
+__device__ __forceinline__ void stage_load(const float *src, uint32_t pix0, uint32_t npix,
+                                           size_t run0, int D, gg_v4f (&r)[VolStage<V>::kIssues]) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int h = 0; h < VolStage<V>::kIssues; ++h) {
+    uint32_t p, j;
+    stage_pos<V>(h, lane, p, j);
+    r[h] = (gg_v4f){0.0f, 0.0f, 0.0f, 0.0f};
+    if (pix0 + p < npix)
+      r[h] = *(const GG_GLOBAL gg_v4f *)(src + (size_t)(pix0 + p) * D + run0 + 4u * j);
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void stage_put_stream(float *st, const gg_v4f (&r)[VolStage<V>::kIssues]) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int h = 0; h < VolStage<V>::kIssues; ++h) {
+    uint32_t p, j;
+    stage_pos<V>(h, lane, p, j);
+    lds_put4(st + (p * VolStage<V>::kRowF4 + j) * 4, r[h]);
+  }
+}
+
+// compute layout: lane = c * 16 + p holds floats [c V, c V + V) of row p
+template <int V>
+__device__ __forceinline__ void stage_get_compute(const float *st, float (&o)[V]) {
+  const uint32_t lane = threadIdx.x & 63u, p = lane & 15u, c = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < V / 4; ++e) {
+    const gg_v4f v = lds_get4(st + (p * VolStage<V>::kRowF4 + c * (V / 4) + e) * 4);
+    o[4 * e] = v.x; o[4 * e + 1] = v.y; o[4 * e + 2] = v.z; o[4 * e + 3] = v.w;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void stage_put_compute(float *st, const float (&o)[V]) {
+  const uint32_t lane = threadIdx.x & 63u, p = lane & 15u, c = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < V / 4; ++e)
+    lds_put4(st + (p * VolStage<V>::kRowF4 + c * (V / 4) + e) * 4,
+             (gg_v4f){o[4 * e], o[4 * e + 1], o[4 * e + 2], o[4 * e + 3]});
+}
+
+template <int V>
+__device__ __forceinline__ void stage_store(const float *st, float *dst, uint32_t pix0,
+                                            uint32_t npix, size_t run0, int D) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int h = 0; h < VolStage<V>::kIssues; ++h) {
+    uint32_t p, j;
+    stage_pos<V>(h, lane, p, j);
+    const gg_v4f v = lds_get4(st + (p * VolStage<V>::kRowF4 + j) * 4);
+    if (pix0 + p < npix) *(GG_GLOBAL gg_v4f *)(dst + (size_t)(pix0 + p) * D + run0 + 4u * j) = v;
+  }
+}
+
+// Dynamic LDS of integrate_tile: sF, sW (one float per thread), sBest (one
+// int per pixel); with kStage also the bin table (D float2) and the
+// wavefronts' volume slices.
+__host__ __device__ constexpr size_t integrate_lds_head(uint32_t threads, uint32_t ppb) {
+  return ((sizeof(float) * 2 * threads + sizeof(int) * ppb) + 15u) & ~(size_t)15u;
+}
+
+template <int V>
+__host__ __device__ constexpr size_t integrate_lds_bytes(uint32_t threads, uint32_t ppb, int D,
+                                                         bool stage) {
+  return integrate_lds_head(threads, ppb) +
+         (stage ? (size_t)8 * D + sizeof(float) * VolStage<V>::kWave * (threads / 64u) : 0);
+}
+
+template <int V, int KC, bool kExact, bool kStage = false>
 __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t tile, float *smem) {
+  static_assert(!kStage || V == 4 || V == 8, "staged volume stream needs V = 4 or 8");
   float *sF = smem;
   float *sW = smem + blockDim.x;
   int *sBest = reinterpret_cast<int *>(smem + 2 * blockDim.x);
+  float2 *sBins = nullptr;
+  float *sVol = nullptr;
 
   // thread -> (pixel lp, chunk of V bins): 2^pw_shift neighbouring pixels
   // of a row interleave in each wavefront, so one gather instruction reads
@@ -444,13 +559,31 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   const size_t base = (size_t)pix * a.D + d0;
 
   float z[V], tau[V], S[V], Wo[V];
+  if constexpr (kStage) {
+    // the bin table once per workgroup in LDS
+    char *head = reinterpret_cast<char *>(smem) + integrate_lds_head(blockDim.x, a.ppb);
+    sBins = reinterpret_cast<float2 *>(head);
+    sVol = reinterpret_cast<float *>(head + 8 * (size_t)a.D) +
+           (size_t)(t >> 6) * VolStage<V>::kWave;
+    for (int d = (int)t; d < a.D; d += (int)blockDim.x) sBins[d] = gload2(a.bins + d);
+    __syncthreads();
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const float2 b = gload2(a.bins + d0 + v);
-    z[v] = b.x;
-    tau[v] = b.y;
-    S[v] = 0.0f;
-    Wo[v] = 0.0f;
+    for (int v = 0; v < V; ++v) {
+      const float2 b = sBins[d0 + v];
+      z[v] = b.x;
+      tau[v] = b.y;
+      S[v] = 0.0f;
+      Wo[v] = 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float2 b = gload2(a.bins + d0 + v);
+      z[v] = b.x;
+      tau[v] = b.y;
+      S[v] = 0.0f;
+      Wo[v] = 0.0f;
+    }
   }
   // the carried volume streams from HBM; its loads are issued after the
   // first views' gathers (see fuse_voxels)
@@ -459,15 +592,58 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   for (int v = 0; v < V; ++v) Fp[v] = Wp[v] = 0.0f;
   const bool carry = active && a.carry;
   float mraw = 0.0f;
+  // staged stream: the wavefront's first pixel and the offset of its runs
+  // (every lane of a wavefront shares the pixel group and the 4 chunks)
+  const uint32_t rest0 = (t & ~63u) >> 4;
+  const uint32_t grp0 = fdiv(rest0, a.cpp_div);
+  const uint32_t pix0 = tile * a.ppb + (grp0 << 4);
+  const size_t run0 = (size_t)(rest0 - grp0 * a.cpp) * V;
+  gg_v4f rF[kStage ? VolStage<V>::kIssues : 1], rW[kStage ? VolStage<V>::kIssues : 1];
   auto load_volume = [&] {
-    if (carry) {
-      loadv<V>(a.F_prev + base, Fp);
-      loadv<V>(a.W_prev + base, Wp);
+    if constexpr (kStage) {
+      if (a.carry) {
+        stage_load<V>(a.F_prev, pix0, a.npix, run0, a.D, rF);
+        stage_load<V>(a.W_prev, pix0, a.npix, run0, a.D, rW);
+      }
+    } else {
+      if (carry) {
+        loadv<V>(a.F_prev + base, Fp);
+        loadv<V>(a.W_prev + base, Wp);
+      }
     }
     if (active && a.mask) mraw = gmem(a.mask)[pix];
   };
   float Fn[V], Wn[V];
-  if (active) {
+  if constexpr (kStage) {
+    // every lane takes part in the wavefront's exchanges
+    const uint32_t y = fdiv(pix, a.wt_div);
+    const uint32_t x = pix - y * a.wt_div.d;
+    if (active)
+      fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
+    else
+      load_volume();
+    if (a.carry) {
+      stage_put_stream<V>(sVol, rF);
+      stage_put_stream<V>(sVol + VolStage<V>::kArray, rW);
+      wave_lds_sync();
+      stage_get_compute<V>(sVol, Fp);
+      stage_get_compute<V>(sVol + VolStage<V>::kArray, Wp);
+    }
+    const float m = a.mask ? fmaxf(1.0f - mraw, 0.0f) : 1.0f;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float wp = a.carry ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
+      const float wn = wp + Wo[v];
+      Fn[v] = (active && wn > 0.0f) ? fmaf(wp, Fp[v], S[v]) / wn : 0.0f;
+      Wn[v] = active ? wn : 0.0f;
+    }
+    wave_lds_sync();
+    stage_put_compute<V>(sVol, Fn);
+    stage_put_compute<V>(sVol + VolStage<V>::kArray, Wn);
+    wave_lds_sync();
+    stage_store<V>(sVol, a.F, pix0, a.npix, run0, a.D);
+    stage_store<V>(sVol + VolStage<V>::kArray, a.W, pix0, a.npix, run0, a.D);
+  } else if (active) {
     const uint32_t y = fdiv(pix, a.wt_div);
     const uint32_t x = pix - y * a.wt_div.d;
     fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
@@ -486,10 +662,17 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
     for (int v = 0; v < V; ++v) Fn[v] = Wn[v] = 0.0f;
   }
   if (a.out_depth) {
-    const float2 *bins = a.bins;
-    extract_block<V>(Fn, Wn, lane, active, pix, lp, chunk, a.cpp, 1u << a.pw_shift, d0, a.D, sF,
-                     sW, sBest, a.out_depth, a.out_bin,
-                     [bins](int d) { return gload2(bins + d).x; });
+    if constexpr (kStage) {
+      const float2 *bins = sBins;
+      extract_block<V>(Fn, Wn, lane, active, pix, lp, chunk, a.cpp, 1u << a.pw_shift, d0, a.D,
+                       sF, sW, sBest, a.out_depth, a.out_bin,
+                       [bins](int d) { return bins[d].x; });
+    } else {
+      const float2 *bins = a.bins;
+      extract_block<V>(Fn, Wn, lane, active, pix, lp, chunk, a.cpp, 1u << a.pw_shift, d0, a.D,
+                       sF, sW, sBest, a.out_depth, a.out_bin,
+                       [bins](int d) { return gload2(bins + d).x; });
+    }
   }
 }
 
