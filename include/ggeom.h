@@ -388,7 +388,10 @@ int tsdf_extract_depth_backward(const gg_camera *tgt, const gg_tsdf_params *prm,
  * Arguments as tsdf_integrate, with F, W the forward's outputs (call before
  * the next frame overwrites them), bin its out_bin; g_depth_in float
  * K x src_h x src_w is overwritten.  Scatter uses 64-bit fixed-point atomics
- * with a data-derived scale, so the result is deterministic. */
+ * with a data-derived scale, so the result is deterministic: with m the
+ * largest bound |g_F| max(1, tau + |F|) / W over the pixels' two voxels (FP32)
+ * and 2^(e-1) <= 2 m tgt_w tgt_h < 2^e, every term is rounded to the quantum
+ * 2^-(61-e), which keeps every sum below 2^61 in magnitude. */
 int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
                             const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
                             const float *W, const int32_t *bin, const float *g_F2,

@@ -306,39 +306,67 @@ def temporal_filter(depth, mask, prev=None, prec=32):
     return out
 
 
-def splat_backward(src, depth, rgb, tgt, sp, g_rgb, g_depth, g_alpha, prec=32):
+def splat_backward(src, depth, rgb, tgt, sp, g_rgb, g_depth, g_alpha, prec=32, bound=False):
+    """Adjoint of the splat: (d depth, d colour); with ``bound`` also the
+    terms' magnitude sums of each (same shapes) and the term count of each
+    depth entry (the tests' per-entry error bound)."""
     rt = _rt(prec)
     K = len(src)
     d = _f32(depth)
     c = np.ascontiguousarray(rgb, np.uint8)
     gd = np.zeros(d.shape, rt)
     gc = np.zeros(d.shape + (3,), rt)
+    md = np.zeros(d.shape, rt) if bound else None
+    mc = np.zeros(d.shape + (3,), rt) if bound else None
+    nd = np.zeros(d.shape, np.int32) if bound else None
     tc = cam(tgt)
-    rc = lib(prec).orc_splat_backward(
+    rc = lib(prec).orc_splat_backward_mag(
         cams(src), K, _p(d), _p(c), C.byref(tc), C.byref(splat_params(sp)),
         _p(np.ascontiguousarray(g_rgb, rt)), _p(np.ascontiguousarray(g_depth, rt)),
-        _p(np.ascontiguousarray(g_alpha, rt)), _p(gd), _p(gc))
+        _p(np.ascontiguousarray(g_alpha, rt)), _p(gd), _p(gc), _p(md), _p(mc), _p(nd))
     if rc != 0:
         raise RuntimeError(f"orc_splat_backward failed: {rc}")
+    if bound:
+        return gd, gc, (md, mc, nd)
     return gd, gc
 
 
-def tsdf_backward(src, depth, tgt, tsdf, g_out, mask=None, F_prev=None, W_prev=None, prec=32):
+def tsdf_backward(src, depth, tgt, tsdf, g_out, mask=None, F_prev=None, W_prev=None, prec=32,
+                  pixels=None, bound=False):
+    """Adjoint of fusion + extraction with respect to the input depths, for
+    the upstream gradient ``g_out`` on the extracted depth (all target pixels
+    row-major, or one per entry of ``pixels``: every other pixel's gradient
+    is zero; F_prev / W_prev then follow the list too).  With ``bound`` also
+    the terms' magnitude sum and term count of each entry, the largest term
+    count of the fusion-weight adjoint, each entry's error in quanta of a
+    fixed-point sum, and the largest |term| (the tests' error bound)."""
     rt = _rt(prec)
     K = len(src)
     d = _f32(depth)
     gd = np.zeros(d.shape, rt)
     D = int(tsdf["num_bins"])
-    npix = tgt.width * tgt.height
+    npix = tgt.width * tgt.height if pixels is None else len(pixels)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
     Fp = None if F_prev is None else np.ascontiguousarray(F_prev, rt).reshape(npix, D)
     Wp = None if W_prev is None else np.ascontiguousarray(W_prev, rt).reshape(npix, D)
     m = None if mask is None else _f32(mask)
+    md = np.zeros(d.shape, rt) if bound else None
+    nd = np.zeros(d.shape, np.int32) if bound else None
+    qs = np.zeros(d.shape, rt) if bound else None
+    ncmax = C.c_int32(0)
+    tbound = C.c_double(0.0)
     tc = cam(tgt)
-    rc = lib(prec).orc_tsdf_backward(cams(src), K, _p(d), C.byref(tc), C.byref(tsdf_params(tsdf)),
-                                     _p(m), _p(Fp), _p(Wp), _p(np.ascontiguousarray(g_out, rt)),
-                                     _p(gd))
+    g = np.ascontiguousarray(g_out, rt).ravel()
+    if g.size != npix:
+        raise ValueError("g_out needs one value per (listed) target pixel")
+    rc = lib(prec).orc_tsdf_backward_px(
+        cams(src), K, _p(d), C.byref(tc), C.byref(tsdf_params(tsdf)), _p(m), _p(Fp), _p(Wp),
+        _p(g), _p(pix), 0 if pix is None else len(pix), _p(gd), _p(md), _p(nd),
+        C.byref(ncmax) if bound else None, _p(qs), C.byref(tbound) if bound else None)
     if rc != 0:
         raise RuntimeError(f"orc_tsdf_backward failed: {rc}")
+    if bound:
+        return gd, (md, nd, int(ncmax.value), qs, float(tbound.value))
     return gd
 
 

@@ -124,50 +124,108 @@ static int depth_ok(float d) { return d > 0.0f && d < INFINITY; }
  * Its image in camera b, K_b (R_b p + t_b), is exactly
  *   z * H (px, py, 1)^T + c,   H = K_b R_b R_a^T K_a^{-1},
  *                              c = K_b (t_b - R_b R_a^T t_a),
- * i.e. affine in z along the ray.  H and c are formed in FP64 in the order
- * written here (reading: this order is normative) and rounded once.
+ * i.e. affine in z along the ray.  H and c are these plain matrix products,
+ * each 3 x 3 factor written out from the camera (K_a^{-1} = [[1/fx, 0,
+ * -cx/fx], [0, 1/fy, -cy/fy], [0, 0, 1]]), evaluated right to left in
+ * binary128 (113-bit significand) and rounded once to the working
+ * precision.  Reading: the constants are the rounding of the exact products;
+ * binary128 carries them to far below an FP32 (or FP64) rounding step, also
+ * where an entry is the small difference of large terms, so the rounded
+ * value does not depend on the order of evaluation.  An entry whose value
+ * is below 2^-50 of the sum of the magnitudes of the monomials forming it
+ * (the same products over the entries' magnitudes) is pure cancellation
+ * residue (an identity pair's off-diagonal terms, say) and is taken as 0:
+ * binary128 leaves such residues order-dependent, the threshold does not.
  * ---------------------------------------------------------------------- */
-void orc_relproj_d(const orc_camera *a, const orc_camera *b, double H[9], double c[3]) {
-  double M[3][3], e[3], A[3][3];
+typedef __float128 quad;
+
+static void q3_mul(const quad A[9], const quad B[9], quad C[9]) {
   for (int r = 0; r < 3; ++r)
-    for (int k = 0; k < 3; ++k)
-      M[r][k] = ((double)b->R[3 * r + 0] * (double)a->R[3 * k + 0] +
-                 (double)b->R[3 * r + 1] * (double)a->R[3 * k + 1]) +
-                (double)b->R[3 * r + 2] * (double)a->R[3 * k + 2];
-  for (int r = 0; r < 3; ++r)
-    e[r] = (double)b->t[r] - ((M[r][0] * (double)a->t[0] + M[r][1] * (double)a->t[1]) +
-                              M[r][2] * (double)a->t[2]);
-  for (int k = 0; k < 3; ++k) {
-    A[0][k] = (double)b->fx * M[0][k] + (double)b->cx * M[2][k];
-    A[1][k] = (double)b->fy * M[1][k] + (double)b->cy * M[2][k];
-    A[2][k] = M[2][k];
-  }
-  c[0] = (double)b->fx * e[0] + (double)b->cx * e[2];
-  c[1] = (double)b->fy * e[1] + (double)b->cy * e[2];
-  c[2] = e[2];
+    for (int k = 0; k < 3; ++k) {
+      quad acc = 0;
+      for (int m = 0; m < 3; ++m) acc += A[3 * r + m] * B[3 * m + k];
+      C[3 * r + k] = acc;
+    }
+}
+
+static void q3_vec(const quad A[9], const quad x[3], quad y[3]) {
   for (int r = 0; r < 3; ++r) {
-    double h0 = A[r][0] / (double)a->fx;
-    double h1 = A[r][1] / (double)a->fy;
-    H[3 * r + 0] = h0;
-    H[3 * r + 1] = h1;
-    H[3 * r + 2] = (A[r][2] - h0 * (double)a->cx) - h1 * (double)a->cy;
+    quad acc = 0;
+    for (int m = 0; m < 3; ++m) acc += A[3 * r + m] * x[m];
+    y[r] = acc;
   }
+}
+
+static quad qabs(quad x) { return x < 0 ? -x : x; }
+
+/* H = K_b R_b R_a^T K_a^{-1} and c = K_b (t_b - R_b R_a^T t_a) from the
+ * factors M1 .. M4 (row-major), and with every factor replaced by its
+ * entrywise magnitude, the sums of the monomials' magnitudes. */
+static void relproj_q(const orc_camera *a, const orc_camera *b, quad H[9], quad c[3]) {
+  const quad fxa = a->fx, fya = a->fy;
+  const quad Kb[9] = {b->fx, 0, b->cx, 0, b->fy, b->cy, 0, 0, 1};
+  const quad Kai[9] = {1 / fxa, 0, -(quad)a->cx / fxa, 0, 1 / fya, -(quad)a->cy / fya, 0, 0, 1};
+  quad Rb[9], RaT[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      Rb[3 * r + k] = b->R[3 * r + k];
+      RaT[3 * r + k] = a->R[3 * k + r];
+    }
+  const quad ta[3] = {a->t[0], a->t[1], a->t[2]};
+  const quad tb[3] = {b->t[0], b->t[1], b->t[2]};
+  quad Hm[9], cm[3];
+  for (int pass = 0; pass < 2; ++pass) {
+    /* pass 0: the values; pass 1: the same products over magnitudes */
+    quad kb[9], kai[9], rb[9], rat[9], xa[3], xb[3];
+    for (int i = 0; i < 9; ++i) {
+      kb[i] = pass ? qabs(Kb[i]) : Kb[i];
+      kai[i] = pass ? qabs(Kai[i]) : Kai[i];
+      rb[i] = pass ? qabs(Rb[i]) : Rb[i];
+      rat[i] = pass ? qabs(RaT[i]) : RaT[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+      xa[i] = pass ? qabs(ta[i]) : ta[i];
+      xb[i] = pass ? qabs(tb[i]) : tb[i];
+    }
+    quad T1[9], T2[9], u[3], v[3], e[3];
+    quad *Ho = pass ? Hm : H, *co = pass ? cm : c;
+    q3_mul(rat, kai, T1); /* R_a^T K_a^{-1}            */
+    q3_mul(rb, T1, T2);   /* R_b R_a^T K_a^{-1}        */
+    q3_mul(kb, T2, Ho);   /* K_b R_b R_a^T K_a^{-1}    */
+    q3_vec(rat, xa, u);   /* R_a^T t_a                 */
+    q3_vec(rb, u, v);     /* R_b R_a^T t_a             */
+    for (int r = 0; r < 3; ++r) e[r] = pass ? xb[r] + v[r] : xb[r] - v[r];
+    q3_vec(kb, e, co);    /* K_b (t_b - R_b R_a^T t_a) */
+  }
+  const quad tiny = 0x1p-50Q;
+  for (int i = 0; i < 9; ++i)
+    if (qabs(H[i]) < tiny * Hm[i]) H[i] = 0;
+  for (int i = 0; i < 3; ++i)
+    if (qabs(c[i]) < tiny * cm[i]) c[i] = 0;
+}
+
+/* FP64 rounding (the FP64 oracle and the tests' world-space check). */
+void orc_relproj_d(const orc_camera *a, const orc_camera *b, double H[9], double c[3]) {
+  quad Hq[9], cq[3];
+  relproj_q(a, b, Hq, cq);
+  for (int i = 0; i < 9; ++i) H[i] = (double)Hq[i];
+  for (int i = 0; i < 3; ++i) c[i] = (double)cq[i];
 }
 
 /* The relative projection in the oracle's working precision. */
 static void relproj(const orc_camera *a, const orc_camera *b, real H[9], real c[3]) {
-  double Hd[9], cd[3];
-  orc_relproj_d(a, b, Hd, cd);
-  for (int i = 0; i < 9; ++i) H[i] = (real)Hd[i];
-  for (int i = 0; i < 3; ++i) c[i] = (real)cd[i];
+  quad Hq[9], cq[3];
+  relproj_q(a, b, Hq, cq);
+  for (int i = 0; i < 9; ++i) H[i] = (real)Hq[i];
+  for (int i = 0; i < 3; ++i) c[i] = (real)cq[i];
 }
 
 /* Exported FP32 rounding of the relative projection (for tests). */
 void orc_relproj(const orc_camera *a, const orc_camera *b, float H[9], float c[3]) {
-  double Hd[9], cd[3];
-  orc_relproj_d(a, b, Hd, cd);
-  for (int i = 0; i < 9; ++i) H[i] = (float)Hd[i];
-  for (int i = 0; i < 3; ++i) c[i] = (float)cd[i];
+  quad Hq[9], cq[3];
+  relproj_q(a, b, Hq, cq);
+  for (int i = 0; i < 9; ++i) H[i] = (float)Hq[i];
+  for (int i = 0; i < 3; ++i) c[i] = (float)cq[i];
 }
 
 /* The ray of pixel centre (px, py): h = H (px, py, 1)^T, fused per row. */
@@ -1192,11 +1250,16 @@ void orc_temporal_filter(const float *depth, const real *mask, const real *prev,
  *   dG/dD = G * ( (dx * dx/dD + dy * dy/dD) / s2 + d2 (dsigma/dD) / (sigma s2) )
  * with dx = centre - x.  Gradients are overwritten, not accumulated.
  * The forward outputs (winners, depth, rgb) are recomputed here.
+ * Error-bound outputs (optional, for the tests' tolerance): m_depth_in and
+ * m_rgb_in are the same sums over the terms' magnitudes (factors replaced
+ * by their magnitudes, differences of computed values by the sums of their
+ * magnitudes), cnt_in the number of terms of each depth gradient.
  * ---------------------------------------------------------------------- */
-int orc_splat_backward(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
-                       const orc_camera *tgt, const orc_splat_params *sp, const real *g_rgb,
-                       const real *g_depth, const real *g_alpha, real *g_depth_in,
-                       real *g_rgb_in) {
+int orc_splat_backward_mag(const orc_camera *src, int K, const float *depth,
+                           const uint8_t *rgb, const orc_camera *tgt, const orc_splat_params *sp,
+                           const real *g_rgb, const real *g_depth, const real *g_alpha,
+                           real *g_depth_in, real *g_rgb_in, real *m_depth_in, real *m_rgb_in,
+                           int32_t *cnt_in) {
   const int Ws = src[0].width, Hs = src[0].height, Wt = tgt->width, Ht = tgt->height;
   const size_t ns = (size_t)Ws * Hs, nt = (size_t)Wt * Ht;
   int32_t *win = (int32_t *)malloc(sizeof(int32_t) * nt * K);
@@ -1211,6 +1274,12 @@ int orc_splat_backward(const orc_camera *src, int K, const float *depth, const u
   const real band = (real)1 + (real)sp->band_rel;
   for (size_t n = 0; n < ns * K; ++n) g_depth_in[n] = 0;
   for (size_t n = 0; n < ns * K * 3; ++n) g_rgb_in[n] = 0;
+  if (m_depth_in)
+    for (size_t n = 0; n < ns * K; ++n) m_depth_in[n] = 0;
+  if (m_rgb_in)
+    for (size_t n = 0; n < ns * K * 3; ++n) m_rgb_in[n] = 0;
+  if (cnt_in)
+    for (size_t n = 0; n < ns * K; ++n) cnt_in[n] = 0;
   for (int k = 0; k < K; ++k) {
     real H[9], c[3];
     relproj(&src[k], tgt, H, c);
@@ -1264,7 +1333,11 @@ int orc_splat_backward(const orc_camera *src, int K, const float *depth, const u
         const real dydD = (h[1] * Z - X[1] * h[2]) / Z2;
         const real sig = sscale * ((real)dk[q] / Z);
         const real dsdD = sscale * c[2] / Z2;
-        real gD = 0, gc[3] = {0, 0, 0};
+        /* magnitudes of the same factors (differences as sums of magnitudes) */
+        const real mxdD = (RABS(h[0]) * Z + RABS(X[0]) * RABS(h[2])) / Z2;
+        const real mydD = (RABS(h[1]) * Z + RABS(X[1]) * RABS(h[2])) / Z2;
+        real gD = 0, gc[3] = {0, 0, 0}, mD = 0, mc[3] = {0, 0, 0};
+        int32_t nD = 0;
         for (int b = g.b0; b <= g.b1; ++b)
           for (int a = g.a0; a <= g.a1; ++a) {
             const real d2 = cover_d2(&g, a, b);
@@ -1273,25 +1346,41 @@ int orc_splat_backward(const orc_camera *src, int K, const float *depth, const u
             if (win[o] < 0 || !(g.z <= od[o] * band)) continue;
             const real G = REXP(((real)-0.5 * d2) / g.s2);
             const real n = nrm[p];
-            real dLdG = 0;
+            real dLdG = 0, mLdG = 0;
             for (int ch = 0; ch < 3; ++ch) {
               const real gr = g_rgb[(nt * 3 * k) + ch * nt + p];
               const real cq = (real)ck[q * 3 + ch] / (real)255;
+              const real orc = orgb[nt * 3 * k + ch * nt + p];
               gc[ch] += gr * G / n;
-              dLdG += gr * (cq - orgb[nt * 3 * k + ch * nt + p]) / n;
+              mc[ch] += RABS(gr) * G / n;
+              dLdG += gr * (cq - orc) / n;
+              mLdG += RABS(gr) * (cq + RABS(orc)) / n;
             }
             /* product of (1 - G_j) over the other band members, directly */
             real others = 1;
             for (size_t e = start[p]; e < start[p + 1]; ++e)
               if (band_q[e] != q) others = others * ((real)1 - band_G[e]);
             dLdG += g_alpha[o] * others;
+            mLdG += RABS(g_alpha[o]) * others;
             const real dx = ((real)a + (real)0.5) - g.x, dy = ((real)b + (real)0.5) - g.y;
             const real dGdD = G * ((dx * dxdD + dy * dydD) / g.s2 + d2 * dsdD / (sig * g.s2));
+            const real mGdD = G * ((RABS(dx) * mxdD + RABS(dy) * mydD) / g.s2 +
+                                   d2 * RABS(dsdD) / (sig * g.s2));
             gD += dLdG * dGdD;
-            if (win[o] == (int32_t)q) gD += g_depth[o] * h[2];
+            mD += mLdG * mGdD;
+            nD += 1;
+            if (win[o] == (int32_t)q) {
+              gD += g_depth[o] * h[2];
+              mD += RABS(g_depth[o]) * RABS(h[2]);
+              nD += 1;
+            }
           }
         g_depth_in[ns * k + q] = gD;
         for (int ch = 0; ch < 3; ++ch) g_rgb_in[(ns * k + q) * 3 + ch] = gc[ch];
+        if (m_depth_in) m_depth_in[ns * k + q] = mD;
+        if (m_rgb_in)
+          for (int ch = 0; ch < 3; ++ch) m_rgb_in[(ns * k + q) * 3 + ch] = mc[ch];
+        if (cnt_in) cnt_in[ns * k + q] = nD;
       }
   }
   free(win);
@@ -1304,6 +1393,14 @@ int orc_splat_backward(const orc_camera *src, int K, const float *depth, const u
   free(band_G);
   free(band_q);
   return 0;
+}
+
+int orc_splat_backward(const orc_camera *src, int K, const float *depth, const uint8_t *rgb,
+                       const orc_camera *tgt, const orc_splat_params *sp, const real *g_rgb,
+                       const real *g_depth, const real *g_alpha, real *g_depth_in,
+                       real *g_rgb_in) {
+  return orc_splat_backward_mag(src, K, depth, rgb, tgt, sp, g_rgb, g_depth, g_alpha, g_depth_in,
+                                g_rgb_in, NULL, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------
@@ -1321,39 +1418,82 @@ int orc_splat_backward(const orc_camera *src, int K, const float *depth, const u
  *   dnu/dD_n = -2 (D_q - D_n) [ same ]   (valid in-bounds neighbours n).
  * No gradient reaches the carried state, the mask or the cameras.  The two
  * voxels per pixel are recomputed from the inputs (the volume is not kept).
+ *
+ * With a pixel list, only the listed target pixels carry an upstream
+ * gradient (g_out per list entry); every other pixel's is zero and adds
+ * nothing, so only the listed pixels' voxels are formed.
+ * Error-bound outputs (optional, for the tests' tolerance): g_mag[q] is the
+ * same sum over the magnitudes of its terms, each term's factors replaced
+ * by their magnitudes, and a difference of computed values by the sum of
+ * their magnitudes (running error analysis: a sum of n terms rounded in
+ * any order lies within about (n + c) 2^-24 g_mag of the exact sum);
+ * g_cnt[q] counts the terms of g_depth_in[q], *conf_cnt_max the most terms
+ * of any dL/domega entry (which feeds the window terms).  For a sum formed
+ * in fixed point (every term rounded to one quantum Q): g_qsens[q] bounds
+ * the error of g_depth_in[q] in units of Q (half a quantum per term, and a
+ * window term's sensitivity to its dL/domega sum), and *term_bound is the
+ * largest |term| any listed voxel can produce, |gF| max(1, tau + |F|) / W.
  * ---------------------------------------------------------------------- */
-int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const orc_camera *tgt,
-                      const orc_tsdf_params *p, const float *mask, const real *F_prev,
-                      const real *W_prev, const real *g_out, real *g_depth_in) {
+int orc_tsdf_backward_px(const orc_camera *src, int K, const float *depth,
+                         const orc_camera *tgt, const orc_tsdf_params *p, const float *mask,
+                         const real *F_prev, const real *W_prev, const real *g_out,
+                         const int32_t *pixels, int npx, real *g_depth_in, real *g_mag,
+                         int32_t *g_cnt, int32_t *conf_cnt_max, real *g_qsens,
+                         double *term_bound) {
   const int D = p->num_bins;
   const int Ws = src[0].width, Hs = src[0].height, Wt = tgt->width, Ht = tgt->height;
-  const size_t ns = (size_t)Ws * Hs, nt = (size_t)Wt * Ht;
+  const size_t ns = (size_t)Ws * Hs;
+  /* the voxels of the listed pixels (all pixels, row-major, without a list);
+   * g_out, F_prev and W_prev follow the list */
+  const size_t nt = pixels ? (size_t)npx : (size_t)Wt * Ht;
   real *conf = (real *)calloc(ns * K, sizeof(real));
   real *gconf = (real *)calloc(ns * K, sizeof(real));
+  real *mconf = (real *)calloc(ns * K, sizeof(real));
+  int32_t *nconf = (int32_t *)calloc(ns * K, sizeof(int32_t));
   real *F = (real *)malloc(sizeof(real) * nt * D), *W = (real *)malloc(sizeof(real) * nt * D);
   real *dep = (real *)malloc(sizeof(real) * nt);
   int32_t *bin = (int32_t *)malloc(sizeof(int32_t) * nt);
   real *zb = (real *)malloc(sizeof(real) * D), *tb = (real *)malloc(sizeof(real) * D);
-  if (!conf || !gconf || !F || !W || !dep || !bin || !zb || !tb) return -2;
+  if (!conf || !gconf || !mconf || !nconf || !F || !W || !dep || !bin || !zb || !tb) return -2;
   for (int k = 0; k < K; ++k) orc_confidence(depth + ns * k, Ws, Hs, p, conf + ns * k);
-  orc_integrate(src, K, depth, conf, tgt, p, mask, F_prev, W_prev, F, W, NULL, 0);
+  orc_integrate(src, K, depth, conf, tgt, p, mask, F_prev, W_prev, F, W, pixels,
+                pixels ? npx : 0);
   orc_extract(p, F, W, (int)nt, dep, bin);
   orc_bins(p, zb, tb);
   real Hk[16][9], ck[16][3];
   for (int k = 0; k < K; ++k) relproj(tgt, &src[k], Hk[k], ck[k]);
   for (size_t n = 0; n < ns * K; ++n) g_depth_in[n] = 0;
-  for (size_t pix = 0; pix < nt; ++pix) {
-    const int d = bin[pix];
+  if (g_mag)
+    for (size_t n = 0; n < ns * K; ++n) g_mag[n] = 0;
+  if (g_cnt)
+    for (size_t n = 0; n < ns * K; ++n) g_cnt[n] = 0;
+  if (g_qsens)
+    for (size_t n = 0; n < ns * K; ++n) g_qsens[n] = 0;
+  double tb_max = 0;
+  for (size_t i = 0; i < nt; ++i) {
+    const size_t pix = pixels ? (size_t)pixels[i] : i;
+    const int d = bin[i];
     if (d < 0) continue;
-    const real *f = F + pix * D;
+    const real *f = F + i * D;
     const real delta = f[d] - f[d + 1], dz = zb[d + 1] - zb[d];
-    const real gF[2] = {g_out[pix] * (-dz * f[d + 1] / (delta * delta)),
-                        g_out[pix] * (dz * f[d] / (delta * delta))};
+    const real gF[2] = {g_out[i] * (-dz * f[d + 1] / (delta * delta)),
+                        g_out[i] * (dz * f[d] / (delta * delta))};
+    /* magnitudes (running error bound): dz and delta are exact differences
+     * of shared values (Sterbenz; opposite signs), so they enter as is */
+    const real aF[2] = {RABS(g_out[i]) * (dz * RABS(f[d + 1]) / (delta * delta)),
+                        RABS(g_out[i]) * (dz * RABS(f[d]) / (delta * delta))};
     const int x = (int)(pix % Wt), y = (int)(pix / Wt);
     for (int e = 0; e < 2; ++e) {
       const int dd = d + e;
       const real z = zb[dd], tau = tb[dd];
-      const real Wn = W[pix * D + dd], Fv = F[pix * D + dd];
+      const real Wn = W[i * D + dd], Fv = F[i * D + dd];
+      {
+        /* largest term this voxel can produce: |gF| / W times max(1, tau + |F|)
+         * (fusion weights are at most 1, clamped distances at most tau) */
+        const double gb = fabs((double)gF[e]) / (double)Wn;
+        const double m = gb * fmax(1.0, (double)tau + fabs((double)Fv));
+        if (m > tb_max) tb_max = m;
+      }
       for (int k = 0; k < K; ++k) {
         real h[3], X[3];
         ray_of(Hk[k], (real)x + (real)0.5, (real)y + (real)0.5, h);
@@ -1369,10 +1509,23 @@ int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const or
         if (s < -tau) continue;
         const real cval = RMIN(s, tau);
         const real w = conf[ns * k + q];
-        if (s < tau) g_depth_in[ns * k + q] += gF[e] * w / Wn;
+        if (s < tau) {
+          g_depth_in[ns * k + q] += gF[e] * w / Wn;
+          if (g_mag) g_mag[ns * k + q] += aF[e] * w / Wn;
+          if (g_cnt) g_cnt[ns * k + q] += 1;
+          if (g_qsens) g_qsens[ns * k + q] += (real)0.5;
+        }
         gconf[ns * k + q] += gF[e] * (cval - Fv) / Wn;
+        mconf[ns * k + q] += aF[e] * (RABS(cval) + RABS(Fv)) / Wn;
+        nconf[ns * k + q] += 1;
       }
     }
+  }
+  if (term_bound) *term_bound = tb_max;
+  if (conf_cnt_max) {
+    int32_t m = 0;
+    for (size_t n = 0; n < ns * K; ++n) m = nconf[n] > m ? nconf[n] : m;
+    *conf_cnt_max = m;
   }
   /* chain through the window statistic */
   const int r = (p->conf_window - 1) / 2;
@@ -1403,6 +1556,7 @@ int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const or
         if (!(raw < 1)) continue; /* min(., 1) active */
         const real dwdnu = (real)-0.5 * raw / nu;
         const real gnu = gq * dwdnu;
+        const real agnu = mconf[ns * k + q] * ((real)0.5 * raw / nu);
         for (int dy = -r; dy <= r; ++dy)
           for (int dx = -r; dx <= r; ++dx) {
             const int ii = i + dx, jj = j + dy;
@@ -1413,11 +1567,30 @@ int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const or
             if (!(dd * dd < tw2)) continue;
             g_depth_in[ns * k + q] += gnu * (real)2 * dd;
             g_depth_in[ns * k + n] -= gnu * (real)2 * dd;
+            if (g_mag) {
+              g_mag[ns * k + q] += agnu * (real)2 * RABS(dd);
+              g_mag[ns * k + n] += agnu * (real)2 * RABS(dd);
+            }
+            if (g_cnt) {
+              g_cnt[ns * k + q] += 1;
+              g_cnt[ns * k + n] += 1;
+            }
+            if (g_qsens) {
+              /* an absolute error e in dL/domega_q moves this term by
+               * e |domega/dnu| 2 |dd|; a sum of nconf terms each rounded to a
+               * quantum carries at most nconf / 2 quanta */
+              const real qs = (real)0.5 * (real)nconf[ns * k + q] * ((real)0.5 * raw / nu) *
+                              (real)2 * RABS(dd);
+              g_qsens[ns * k + q] += qs;
+              g_qsens[ns * k + n] += qs;
+            }
           }
       }
   }
   free(conf);
   free(gconf);
+  free(mconf);
+  free(nconf);
   free(F);
   free(W);
   free(dep);
@@ -1425,4 +1598,11 @@ int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const or
   free(zb);
   free(tb);
   return 0;
+}
+
+int orc_tsdf_backward(const orc_camera *src, int K, const float *depth, const orc_camera *tgt,
+                      const orc_tsdf_params *p, const float *mask, const real *F_prev,
+                      const real *W_prev, const real *g_out, real *g_depth_in) {
+  return orc_tsdf_backward_px(src, K, depth, tgt, p, mask, F_prev, W_prev, g_out, NULL, 0,
+                              g_depth_in, NULL, NULL, NULL, NULL, NULL);
 }

@@ -92,35 +92,60 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-// H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a), in FP64 in this
-// order, rounded once to FP32.
+// H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a): M = R_b R_a^T
+// and e = t_b - M t_a first, then the intrinsics of b on the left and those
+// of a on the right, in binary128 (113-bit significand), rounded once to
+// FP32.  binary128 keeps every entry far below an FP32 rounding step of its
+// exact value, also entries that are small differences of large terms, so
+// the rounding is that of the exact product whatever the evaluation order.
+// An entry below 2^-50 of the summed magnitudes of its monomials (the same
+// formulas over magnitudes, carried beside the values) is cancellation
+// residue and becomes 0, so that it is not left to the evaluation order.
 void relproj(const gg_camera &a, const gg_camera &b, Proj &out) {
-  double M[3][3], e[3], A[3][3], H[9], c[3];
+  typedef __float128 q;
+  auto qa = [](q x) { return x < 0 ? -x : x; };
+  q M[3][3], Mm[3][3], e[3], em[3], A[3][3], Am[3][3], H[9], Hm[9], c[3], cm[3];
   for (int r = 0; r < 3; ++r)
-    for (int k = 0; k < 3; ++k)
-      M[r][k] = ((double)b.R[3 * r + 0] * (double)a.R[3 * k + 0] +
-                 (double)b.R[3 * r + 1] * (double)a.R[3 * k + 1]) +
-                (double)b.R[3 * r + 2] * (double)a.R[3 * k + 2];
-  for (int r = 0; r < 3; ++r)
-    e[r] = (double)b.t[r] -
-           ((M[r][0] * (double)a.t[0] + M[r][1] * (double)a.t[1]) + M[r][2] * (double)a.t[2]);
-  for (int k = 0; k < 3; ++k) {
-    A[0][k] = (double)b.fx * M[0][k] + (double)b.cx * M[2][k];
-    A[1][k] = (double)b.fy * M[1][k] + (double)b.cy * M[2][k];
-    A[2][k] = M[2][k];
-  }
-  c[0] = (double)b.fx * e[0] + (double)b.cx * e[2];
-  c[1] = (double)b.fy * e[1] + (double)b.cy * e[2];
-  c[2] = e[2];
+    for (int k = 0; k < 3; ++k) {
+      const q b0 = b.R[3 * r + 0], b1 = b.R[3 * r + 1], b2 = b.R[3 * r + 2];
+      const q a0 = a.R[3 * k + 0], a1 = a.R[3 * k + 1], a2 = a.R[3 * k + 2];
+      M[r][k] = (b0 * a0 + b1 * a1) + b2 * a2;
+      Mm[r][k] = (qa(b0) * qa(a0) + qa(b1) * qa(a1)) + qa(b2) * qa(a2);
+    }
   for (int r = 0; r < 3; ++r) {
-    const double h0 = A[r][0] / (double)a.fx;
-    const double h1 = A[r][1] / (double)a.fy;
+    e[r] = (q)b.t[r] - ((M[r][0] * (q)a.t[0] + M[r][1] * (q)a.t[1]) + M[r][2] * (q)a.t[2]);
+    em[r] = qa(b.t[r]) +
+            ((Mm[r][0] * qa(a.t[0]) + Mm[r][1] * qa(a.t[1])) + Mm[r][2] * qa(a.t[2]));
+  }
+  const q bfx = b.fx, bfy = b.fy, bcx = b.cx, bcy = b.cy;
+  for (int k = 0; k < 3; ++k) {
+    A[0][k] = bfx * M[0][k] + bcx * M[2][k];
+    A[1][k] = bfy * M[1][k] + bcy * M[2][k];
+    A[2][k] = M[2][k];
+    Am[0][k] = bfx * Mm[0][k] + qa(bcx) * Mm[2][k];
+    Am[1][k] = bfy * Mm[1][k] + qa(bcy) * Mm[2][k];
+    Am[2][k] = Mm[2][k];
+  }
+  c[0] = bfx * e[0] + bcx * e[2];
+  c[1] = bfy * e[1] + bcy * e[2];
+  c[2] = e[2];
+  cm[0] = bfx * em[0] + qa(bcx) * em[2];
+  cm[1] = bfy * em[1] + qa(bcy) * em[2];
+  cm[2] = em[2];
+  const q afx = a.fx, afy = a.fy, acx = a.cx, acy = a.cy;
+  for (int r = 0; r < 3; ++r) {
+    const q h0 = A[r][0] / afx, h1 = A[r][1] / afy;
+    const q m0 = Am[r][0] / afx, m1 = Am[r][1] / afy;
     H[3 * r + 0] = h0;
     H[3 * r + 1] = h1;
-    H[3 * r + 2] = (A[r][2] - h0 * (double)a.cx) - h1 * (double)a.cy;
+    H[3 * r + 2] = (A[r][2] - h0 * acx) - h1 * acy;
+    Hm[3 * r + 0] = m0;
+    Hm[3 * r + 1] = m1;
+    Hm[3 * r + 2] = (Am[r][2] + m0 * qa(acx)) + m1 * qa(acy);
   }
-  for (int i = 0; i < 9; ++i) out.H[i] = (float)H[i];
-  for (int i = 0; i < 3; ++i) out.c[i] = (float)c[i];
+  const q tiny = 0x1p-50Q;
+  for (int i = 0; i < 9; ++i) out.H[i] = qa(H[i]) < tiny * Hm[i] ? 0.0f : (float)H[i];
+  for (int i = 0; i < 3; ++i) out.c[i] = qa(c[i]) < tiny * cm[i] ? 0.0f : (float)c[i];
 }
 
 static bool finite_f(float v) { return std::isfinite(v); }

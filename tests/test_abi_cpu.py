@@ -296,3 +296,24 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(RuntimeError, match="is not built"):
         ops.workspace_size(3, 2, 8, 8, 8, 8, 16)
+
+
+def test_relative_projection_random_pairs_bitwise_equal_oracle():
+    """Library and oracle form H and c independently (a factored evaluation
+    and the plain product of the four 3 x 3 factors), both in binary128,
+    rounded once, with cancellation residues below 2^-50 of their monomials'
+    magnitudes taken as 0: their FP32 constants agree bitwise for random
+    rigs, including identical cameras (H near the identity, c near 0)."""
+    rng = np.random.default_rng(11)
+    for _ in range(600):
+        w, h = int(rng.integers(8, 2000)), int(rng.integers(8, 2000))
+        ring = scenes.ring_rig(int(rng.integers(3, 24)), float(rng.uniform(0.3, 3.0)), w, h,
+                               f=float(rng.uniform(50.0, 3000.0)))
+        i, j = rng.integers(0, len(ring), 2)
+        if rng.uniform() < 0.25:
+            j = i
+        a, b = ring[i].quantized(), ring[j].quantized()
+        H, c = ops.relative_projection(a, b)
+        Ho, co = oracle.relproj(a, b)
+        assert np.array(H, np.float32).tobytes() == Ho.astype(np.float32).tobytes(), (i, j)
+        assert np.array(c, np.float32).tobytes() == co.astype(np.float32).tobytes(), (i, j)

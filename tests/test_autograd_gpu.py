@@ -7,7 +7,7 @@ import torch
 import oracle
 import paper_2505_18932_amd as gg
 import scenes
-from tests.test_parity_gpu import grad_close
+from tests.test_parity_gpu import grad_close, splat_ref, tsdf_ref
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -42,11 +42,12 @@ def test_autograd_matches_oracle_adjoints():
         (dep_t * torch.from_numpy(g_t).to(DEV)).sum()
     loss.backward()
     torch.cuda.synchronize()
-    rd, rc = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"], g_rgb,
-                                   g_z, g_a)
-    rt = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g_t.ravel())
-    grad_close(colour.grad.cpu().numpy(), rc, "colour gradient")
-    grad_close(depth.grad.cpu().numpy(), rd + rt, "depth gradient (splat + fusion)")
+    (rd, (md, nd)), (rc, bc) = splat_ref(c, g_rgb, g_z, g_a)
+    rt, (mt, nt, qt) = tsdf_ref(c, g_t.ravel())
+    grad_close(colour.grad.cpu().numpy(), rc, bc, "colour gradient")
+    # the two adjoints add: so do their magnitudes, term counts and allowances
+    grad_close(depth.grad.cpu().numpy(), rd + rt, (md + mt, nd + nt, qt),
+               "depth gradient (splat + fusion)")
 
 
 def test_fusion_gradient_matches_finite_differences():

@@ -1,6 +1,7 @@
 """The batched path (persistent kernels in one hipGraph launch) against the
 plain calls, item by item, bitwise, for several launch tunings, item orders
-and graph replays."""
+and graph replays; and against the oracle directly, in full at half size and
+on sampled pixel columns at full size."""
 import numpy as np
 import pytest
 import torch
@@ -181,10 +182,65 @@ def test_batch_full_size_benchmark_tuning():
     """All 24 items at full size (2.6 G voxels) with the launch tuning the
     benchmark measures (512 threads per fusion workgroup, 4 persistent
     workgroups per CU): one graph launch equals the 24 plain call pairs."""
+    import oracle
+    from tests.test_parity_gpu import bits
+
     items = _full_size_items()
     refs = [_plain(it) for it in items]
     plan = gg.BatchPlan(items, 512, 4)
     plan.launch()
     torch.cuda.synchronize()
     _check(items, refs)
+    # and the batched volume against the oracle on 1500 sampled pixel columns
+    # of three items: 1280x720 K=8 D=128, 1920x1080 K=6 D=128, 1920x1080 K=8 D=64
+    rng = np.random.default_rng(9)
+    for i in (0, 3, 14):
+        it = items[i]
+        D = it["tsdf"]["num_bins"]
+        npix = it["tgt"].width * it["tgt"].height
+        pix = np.sort(rng.choice(npix, 1500, replace=False)).astype(np.int32)
+        Fr, Wr = oracle.integrate(it["src"], it["depth"].cpu().numpy(), it["tgt"], it["tsdf"],
+                                  pixels=pix)
+        _, br = oracle.extract(Fr, Wr, it["tsdf"])
+        assert np.array_equal(bits(it["F"].reshape(-1, D)[pix].cpu().numpy()), bits(Fr)), i
+        assert np.array_equal(bits(it["W"].reshape(-1, D)[pix].cpu().numpy()), bits(Wr)), i
+        assert np.array_equal(it["bin_out"].reshape(-1)[pix].cpu().numpy(), br), i
+    plan.close()
+
+
+def test_batch_against_the_oracle():
+    """Four batching items rendered at half their resolution -- 640x360 K=8
+    D=128, 960x540 K=6 D=128, 320x180 K=4 D=128 and 960x540 K=8 D=64 -- in
+    one graph launch, compared with the oracle directly: the volume and the
+    bins bitwise, the extracted depth within 1e-5, splat winners and winner
+    depth bitwise, colour and opacity within 1e-5."""
+    import oracle
+    from tests.test_parity_gpu import bits, close
+
+    descs = scenes.config4_items()
+    cs = [scenes.config4_item(descs[i], scale=2) for i in (0, 3, 12, 14)]
+    items = [dict(src=c["src"], tgt=c["tgt"], depth=torch.from_numpy(c["depth"]).to(DEV),
+                  rgb=torch.from_numpy(c["rgb"]).to(DEV), splat=c["splat"], tsdf=c["tsdf"])
+             for c in cs]
+    assert (len(cs[0]["src"]), cs[0]["tsdf"]["num_bins"]) == (8, 128)
+    plan = gg.BatchPlan(items)
+    plan.launch()
+    torch.cuda.synchronize()
+    for n, (c, it) in enumerate(zip(cs, items)):
+        D = c["tsdf"]["num_bins"]
+        Fr, Wr = oracle.integrate(c["src"], c["depth"], c["tgt"], c["tsdf"])
+        dr, br = oracle.extract(Fr, Wr, c["tsdf"])
+        Fg = it["F"].reshape(-1, D).cpu().numpy()
+        Wg = it["W"].reshape(-1, D).cpu().numpy()
+        assert np.array_equal(bits(Fg), bits(Fr)), f"item {n}: F"
+        assert np.array_equal(bits(Wg), bits(Wr)), f"item {n}: W"
+        assert np.array_equal(it["bin_out"].reshape(-1).cpu().numpy(), br), f"item {n}: bins"
+        close(it["depth_out"].reshape(-1).cpu().numpy(), dr, what=f"item {n}: depth")
+        sr = oracle.splat(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"])
+        so = it["splat_out"]
+        assert np.array_equal(so["win_idx"].cpu().numpy(), sr["win_idx"]), f"item {n}: winners"
+        assert np.array_equal(bits(so["depth"].cpu().numpy()), bits(sr["depth"])), \
+            f"item {n}: winner depth"
+        close(so["rgb"].cpu().numpy(), sr["rgb"], what=f"item {n}: rgb")
+        close(so["alpha"].cpu().numpy(), sr["alpha"], what=f"item {n}: alpha")
     plan.close()

@@ -25,8 +25,9 @@ MUTANTS = [
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
     ("no_occlusion_cut", "if (s < -tau) continue; /* occluded in view k */", "", PINS),
-    ("transposed_rotation", "(double)b->R[3 * r + 0] * (double)a->R[3 * k + 0]",
-     "(double)b->R[3 * r + 0] * (double)a->R[0 + k]", PINS),
+    ("transposed_rotation", "RaT[3 * r + k] = a->R[3 * k + r];",
+     "RaT[3 * r + k] = a->R[3 * r + k];", PINS),
+    ("residue_snap_too_coarse", "const quad tiny = 0x1p-50Q;", "const quad tiny = 0x1p-3Q;", PINS),
     ("pixel_corner_not_centre",
      "ray_of(Hk[k], (real)x + (real)0.5, (real)y + (real)0.5, h[k]);",
      "ray_of(Hk[k], (real)x, (real)y + (real)0.5, h[k]);", PINS),

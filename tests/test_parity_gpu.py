@@ -169,9 +169,9 @@ def test_every_confidence_window(window):
     g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, torch.from_numpy(g).to(DEV))
     gd = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
     torch.cuda.synchronize()
-    ref = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g.ravel())
+    ref, bd = tsdf_ref(c, g.ravel())
     assert np.abs(ref).max() > 0
-    grad_close(gd.cpu().numpy(), ref, f"tsdf depth gradient, window {window}")
+    grad_close(gd.cpu().numpy(), ref, bd, f"tsdf depth gradient, window {window}")
 
 
 def test_library_maxima():
@@ -292,21 +292,63 @@ def test_volume_tile_shape_does_not_change_results():
 # adjoints against the oracle's
 
 
-def grad_close(got, ref, what):
-    """Gradients: 1e-5 relative, norm-wise and per entry.  Each entry is a sum
-    of FP32 terms as large as the largest gradient, which FP32 summation in
-    any order carries to about n 2^-24 of that magnitude; so below 10% of the
-    largest magnitude the per-entry bound becomes absolute, 1e-6 of the
-    largest (about the rounding of sixteen such terms).  The FP32 oracle
-    itself differs from its FP64 build by up to about 1e-6 of the largest
-    gradient on the random scenes."""
+U32 = 2.0 ** -24
+# Roundings along one term beyond the count of summed terms: the term's own
+# products and quotients (about a dozen), the extraction factor upstream, the
+# 49-term window statistic of a fusion-weight term, and a band's colour sum
+# inside the splat's colour difference.
+CHAIN = 96
+
+
+def grad_close(got, ref, bound, what):
+    """Gradients against the FP32 oracle: norm-wise within 1e-5, and per
+    entry within 1e-5 of the entry or within the running error bound
+    (terms + CHAIN) 2^-24 M (+ Q, see below), whichever is larger.  M is the
+    oracle's sum of the entry's terms over magnitudes (differences of computed
+    values as sums of magnitudes) and terms its number of summed terms: the
+    GPU sums the same FP32 terms, the oracle in FP32 one by one, so both lie
+    within that bound of the exact sum of the terms.  ``bound`` is (M, terms)
+    or (M, terms, Q): Q an absolute allowance per entry, the fixed-point
+    quantisation of the fusion adjoint's sums (fusion_quantum)."""
+    mag, terms = bound[0], bound[1]
+    quant = bound[2] if len(bound) > 2 else 0.0
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
+    mag = np.asarray(mag, np.float64)
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), what
-    floor = 1e-1 * np.abs(ref).max()
-    bad = np.abs(got - ref) > 1e-5 * np.maximum(np.abs(ref), floor)
-    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance; " \
-                          f"worst {np.abs(got - ref)[bad].max():.3g}"
+    allowed = np.maximum(1e-5 * np.abs(ref),
+                         (np.asarray(terms, np.float64) + CHAIN) * U32 * mag + quant)
+    bad = np.abs(got - ref) > allowed
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond the bound; worst " \
+                          f"{(np.abs(got - ref)[bad] / np.maximum(allowed[bad], 1e-300)).max():.3g}x"
+
+
+def fusion_quantum(term_bound, npix):
+    """The fusion adjoint accumulates in 64-bit fixed point with the scale
+    include/ggeom.h states: the quantum is 2^-E, E = 61 - e, 2^(e-1) <=
+    2 npix m < 2^e, m the largest |term| bound (here the oracle's, which the
+    library's FP32 evaluation matches to rounding: one power of two of slack)."""
+    if term_bound <= 0:
+        return 0.0
+    e = np.frexp(2.0 * npix * term_bound)[1]
+    return 2.0 ** -(61 - e - 1)
+
+
+def tsdf_ref(c, g, **kw):
+    """Oracle fusion adjoint and its bound (terms: the entry's own plus the
+    most terms of any fusion-weight adjoint feeding its window terms; Q: the
+    entry's error in fixed-point quanta times the quantum)."""
+    r, (m, n, ncm, qs, tb) = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g,
+                                                  bound=True, **kw)
+    q = fusion_quantum(tb, c["tgt"].width * c["tgt"].height)
+    return r, (m, n + ncm, np.asarray(qs, np.float64) * q)
+
+
+def splat_ref(c, g_rgb, g_z, g_a):
+    """Oracle splat adjoints (depth, colour) with their bounds."""
+    rd, rc, (md, mc, nd) = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"],
+                                                 c["splat"], g_rgb, g_z, g_a, bound=True)
+    return (rd, (md, nd)), (rc, (mc, nd[..., None]))
 
 
 def test_tsdf_backward_parity():
@@ -318,8 +360,8 @@ def test_tsdf_backward_parity():
     g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, torch.from_numpy(g).to(DEV))
     gd = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
     torch.cuda.synchronize()
-    ref = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g.ravel())
-    grad_close(gd.cpu().numpy(), ref, "tsdf depth gradient")
+    ref, bd = tsdf_ref(c, g.ravel())
+    grad_close(gd.cpu().numpy(), ref, bd, "tsdf depth gradient")
 
 
 def test_splat_backward_parity():
@@ -334,10 +376,9 @@ def test_splat_backward_parity():
                                      torch.from_numpy(g_rgb).to(DEV), torch.from_numpy(g_z).to(DEV),
                                      torch.from_numpy(g_a).to(DEV))
     torch.cuda.synchronize()
-    rd, rc = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"], g_rgb,
-                                   g_z, g_a)
-    grad_close(gc.cpu().numpy(), rc, "splat colour gradient")
-    grad_close(gd.cpu().numpy(), rd, "splat depth gradient")
+    (rd, bd), (rc, bc) = splat_ref(c, g_rgb, g_z, g_a)
+    grad_close(gc.cpu().numpy(), rc, bc, "splat colour gradient")
+    grad_close(gd.cpu().numpy(), rd, bd, "splat depth gradient")
 
 
 def test_two_call_fusion_on_two_streams():
@@ -508,9 +549,49 @@ def test_backward_at_the_differentiation_size():
                                         torch.from_numpy(g_t).to(DEV))
     gt = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
     torch.cuda.synchronize()
-    rd, rc = oracle.splat_backward(c["src"], c["depth"], c["rgb"], c["tgt"], c["splat"], g_rgb,
-                                   g_z, g_a)
-    rt = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g_t.ravel())
-    grad_close(gc.cpu().numpy(), rc, "splat colour gradient")
-    grad_close(gd.cpu().numpy(), rd, "splat depth gradient")
-    grad_close(gt.cpu().numpy(), rt, "fusion depth gradient")
+    (rd, bd), (rc, bc) = splat_ref(c, g_rgb, g_z, g_a)
+    rt, bt = tsdf_ref(c, g_t.ravel())
+    grad_close(gc.cpu().numpy(), rc, bc, "splat colour gradient")
+    grad_close(gd.cpu().numpy(), rd, bd, "splat depth gradient")
+    grad_close(gt.cpu().numpy(), rt, bt, "fusion depth gradient")
+
+
+def test_backward_at_the_streaming_size_against_the_oracle(streaming_frame):
+    """Both adjoints at 1920x1080, K=8, D=256 (the streaming workload) against
+    the oracle's, with the upstream gradients nonzero on 2000 sampled target
+    pixels only: every other pixel contributes nothing, so the oracle forms
+    only those pixels' voxels, while the GPU runs its full launch (every
+    pixel, zero gradients elsewhere).  Tolerance: the gradient bound."""
+    c, (d, r) = streaming_frame
+    ct = dict(c, depth=d, rgb=r)
+    depth, rgb = torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)
+    tp, sp = c["tsdf"], c["splat"]
+    Ht, Wt = c["tgt"].height, c["tgt"].width
+    rng = np.random.default_rng(8)
+    pix = np.sort(rng.choice(Ht * Wt, 2000, replace=False)).astype(np.int32)
+    sel = np.zeros(Ht * Wt, bool)
+    sel[pix] = True
+    sel = sel.reshape(Ht, Wt)
+    g = np.zeros((Ht, Wt), np.float32)
+    g[sel] = rng.standard_normal(sel.sum()).astype(np.float32)
+    F, W, dep, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], tp)
+    so = gg.splat_views(c["src"], depth, rgb, c["tgt"], sp)
+    K = d.shape[0]
+    g_rgb = np.zeros((K, 3, Ht, Wt), np.float32)
+    g_z = np.zeros((K, Ht, Wt), np.float32)
+    g_a = np.zeros((K, Ht, Wt), np.float32)
+    g_rgb[:, :, sel] = rng.standard_normal((K, 3, sel.sum())).astype(np.float32)
+    g_z[:, sel] = rng.standard_normal((K, sel.sum())).astype(np.float32)
+    g_a[:, sel] = rng.standard_normal((K, sel.sum())).astype(np.float32)
+    g2 = gg.tsdf_extract_depth_backward(c["tgt"], tp, F, W, b, torch.from_numpy(g).to(DEV))
+    gt = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], tp, F, W, b, g2)
+    gd, gc = gg.splat_views_backward(c["src"], depth, rgb, c["tgt"], sp, so,
+                                     *(torch.from_numpy(x).to(DEV) for x in (g_rgb, g_z, g_a)))
+    torch.cuda.synchronize()
+    rt, bt = tsdf_ref(ct, g.ravel()[pix], pixels=pix)
+    assert (rt != 0).sum() > 10000
+    grad_close(gt.cpu().numpy(), rt, bt, "fusion depth gradient (streaming size)")
+    (rd, bd), (rc, bc) = splat_ref(ct, g_rgb, g_z, g_a)
+    assert (rd != 0).sum() > 1000
+    grad_close(gd.cpu().numpy(), rd, bd, "splat depth gradient (streaming size)")
+    grad_close(gc.cpu().numpy(), rc, bc, "splat colour gradient (streaming size)")

@@ -14,7 +14,8 @@ import torch
 import oracle
 import paper_2505_18932_amd as gg
 import scenes
-from tests.test_parity_gpu import DEV, bits, check_splat, check_tsdf, grad_close, to_dev
+from tests.test_parity_gpu import (DEV, bits, check_splat, check_tsdf, grad_close, to_dev,
+                                    tsdf_ref)
 
 pytestmark = pytest.mark.gpu
 
@@ -49,8 +50,8 @@ def test_random_case(seed):
     g2 = gg.tsdf_extract_depth_backward(c["tgt"], c["tsdf"], F, W, b, torch.from_numpy(g).to(DEV))
     gd = gg.tsdf_integrate_backward(c["src"], depth, c["tgt"], c["tsdf"], F, W, b, g2)
     torch.cuda.synchronize()
-    gref = oracle.tsdf_backward(c["src"], c["depth"], c["tgt"], c["tsdf"], g.ravel())
-    grad_close(gd.cpu().numpy(), gref, f"seed {seed}: tsdf depth gradient")
+    gref, bd = tsdf_ref(c, g.ravel())
+    grad_close(gd.cpu().numpy(), gref, bd, f"seed {seed}: tsdf depth gradient")
 
     # a second frame carried in place under a random mask
     mask = rng.uniform(0.0, 1.2, (c["tgt"].height, c["tgt"].width)).astype(np.float32)
