@@ -363,6 +363,25 @@ int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
                           float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
                           void *stream);
 
+/* tsdf_integrate without a workspace argument and without allocating: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Arguments, results
+ * and errors are those of tsdf_integrate (bitwise the same outputs); the
+ * scratch (the view table and the bin table) is a static device array of the
+ * library, GG_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held from the first
+ * call on a device until the process ends.  A call whose workspace would
+ * exceed it (gg_workspace_size(GG_OP_TSDF_INTEGRATE, ...) > 64 MiB, e.g.
+ * more than about 8.3 M source pixels over all views) returns
+ * GG_ERR_UNSUPPORTED before anything is enqueued.  Every call on one device
+ * shares that device's scratch, which keeps the last call's contents and is
+ * fully rewritten before it is read: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller. */
+#define GG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
+                           const gg_camera *tgt, const gg_tsdf_params *prm,
+                           const float *temporal_mask, const float *F_prev, const float *W_prev,
+                           float *F, float *W, float *out_depth, int32_t *out_bin, void *stream);
+
 /* tsdf_extract_depth -- the surface is where the fused signed distance
  * changes sign along the ray (Suppl. A.1).  On the bins: d* = the smallest
  * d in [0, D-2] with W_d > 0, W_{d+1} > 0, F_d > 0 and F_{d+1} <= 0;

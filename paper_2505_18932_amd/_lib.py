@@ -81,6 +81,7 @@ SIGNATURES = {
                                    SZ, P]),
     "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_view_table": (C.c_int, [CAM, I32, P, TSP, P, SZ, P]),
+    "tsdf_integrate_noalloc": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P]),
     "tsdf_integrate_tabled": (C.c_int, [CAM, I32, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
     "tsdf_raymarch": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
     "network_inputs": (C.c_int, [CAM, I32, CAM, P, P, P, P, P, P]),

@@ -353,6 +353,33 @@ static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what,
   return GG_OK;
 }
 
+// Scratch of tsdf_integrate_noalloc: a file-scope device array, one copy per
+// device the library runs on, held until the process ends.  Host code never
+// uses the array's name as an address: its device address is looked up once
+// per device (hipGetSymbolAddress, with that device current) and kept here.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int scratch_of_current_device(void **out, const char *what) {
+  int dev = 0;
+  if (int rc = check_hip(hipGetDevice(&dev), what)) return rc;
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(GG_ERR_UNSUPPORTED, "%s: device %d beyond %d", what, dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), what)) return rc;
+    if (!p) return fail(GG_ERR_HIP, "%s: no device address for the scratch", what);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GG_OK;
+}
+
 }  // namespace gg
 
 using namespace gg;
@@ -798,6 +825,23 @@ int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
                           void *stream) {
   return integrate_impl("tsdf_integrate_tabled", true, src, K, nullptr, tgt, prm, temporal_mask, F_prev,
                         W_prev, F, W, out_depth, out_bin, ws, ws_bytes, stream);
+}
+
+int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
+                           const gg_camera *tgt, const gg_tsdf_params *prm,
+                           const float *temporal_mask, const float *F_prev, const float *W_prev,
+                           float *F, float *W, float *out_depth, int32_t *out_bin, void *stream) {
+  const char *N = "tsdf_integrate_noalloc";
+  if (int rc = check_sources(src, K, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  const size_t need = tsdf_layout(K, src[0].width, src[0].height, prm->num_bins, false).total;
+  if (need > kScratchBytes)
+    return fail(GG_ERR_UNSUPPORTED, "%s: needs %zu bytes of scratch, the static scratch holds %zu",
+                N, need, kScratchBytes);
+  void *ws = nullptr;
+  if (int rc = scratch_of_current_device(&ws, N)) return rc;
+  return integrate_impl(N, false, src, K, depth, tgt, prm, temporal_mask, F_prev, W_prev, F, W,
+                        out_depth, out_bin, ws, kScratchBytes, stream);
 }
 
 int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,

@@ -314,6 +314,40 @@ def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None,
     return F, W, od, ob
 
 
+def tsdf_integrate_noalloc(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
+                           mask=None, extract=True, stream=None):
+    """tsdf_integrate through the entry point that takes no workspace and
+    allocates nothing (its scratch is the library's static device array).
+    Outputs not passed in are created here; the C call itself allocates
+    nothing.  Returns (F, W, depth, bin)."""
+    dev = _device(depth)
+    sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
+    K = len(sa)
+    sw, sh = _wh(sa)
+    tw, th, D = tg.width, tg.height, tp.num_bins
+    _need(depth, torch.float32, (K, sh, sw), "depth", dev)
+    vol = (th, tw, D)
+    if (F_prev is None) != (W_prev is None):
+        raise ValueError("F_prev and W_prev go together")
+    if F_prev is not None:
+        _need(F_prev, torch.float32, vol, "F_prev", dev)
+        _need(W_prev, torch.float32, vol, "W_prev", dev)
+    if mask is not None:
+        _need(mask, torch.float32, (th, tw), "mask", dev)
+    F = torch.empty(vol, dtype=torch.float32, device=dev) if F is None else \
+        _need(F, torch.float32, vol, "F", dev)
+    W = torch.empty(vol, dtype=torch.float32, device=dev) if W is None else \
+        _need(W, torch.float32, vol, "W", dev)
+    od = ob = None
+    if extract:
+        od = torch.empty((th, tw), dtype=torch.float32, device=dev)
+        ob = torch.empty((th, tw), dtype=torch.int32, device=dev)
+    L.check(L.lib().tsdf_integrate_noalloc(sa, K, _ptr(depth), C.byref(tg), C.byref(tp),
+                                           _ptr(mask), _ptr(F_prev), _ptr(W_prev), _ptr(F),
+                                           _ptr(W), _ptr(od), _ptr(ob), _stream(dev, stream)))
+    return F, W, od, ob
+
+
 def tsdf_raymarch(src, depth, tgt, params, *, depth_prev=None, acc_prev=None, mask=None,
                   steps=False, out_depth=None, out_acc=None, ws=None, stream=None):
     """Volume-free march of every target ray (see include/ggeom.h).

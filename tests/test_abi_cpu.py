@@ -317,3 +317,19 @@ def test_relative_projection_random_pairs_bitwise_equal_oracle():
         Ho, co = oracle.relproj(a, b)
         assert np.array(H, np.float32).tobytes() == Ho.astype(np.float32).tobytes(), (i, j)
         assert np.array(c, np.float32).tobytes() == co.astype(np.float32).tobytes(), (i, j)
+
+
+def test_noalloc_rejects_a_workspace_beyond_its_static_scratch():
+    """tsdf_integrate_noalloc checks the size its scratch would need against
+    the 64 MiB static array before touching the device."""
+    lib = L.lib()
+    src = ops.cameras(scenes._quantize_all(scenes.parallel_rig([0.01 * k for k in range(8)],
+                                                               1920, 1080, 1000.0)))
+    tgt = ops.camera(scenes.parallel_rig([0.0], 1920, 1080, 1000.0)[0])
+    tp = ops.tsdf_params(scenes.tsdf_params(num_bins=64, trunc=4.0))
+    need = ops.workspace_size(3, 8, 1920, 1080, 1920, 1080, 64)
+    assert need > 64 << 20
+    rc = lib.tsdf_integrate_noalloc(src, 8, FAKE, C.byref(tgt), C.byref(tp), None, None, None,
+                                    FAKE, FAKE, FAKE, FAKE, None)
+    assert rc == L.GG_ERR_UNSUPPORTED
+    assert "static scratch" in lib.gg_last_error().decode()
