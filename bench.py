@@ -104,6 +104,27 @@ def recorded_valu_instructions():
     return float(v.group(1))
 
 
+def fusion_stream_probe_ms(gg, torch, dev, tgt, tp, F, W, reps=10):
+    """Mean duration of the fusion kernel launched with no views on the
+    volume (F, W) in place (gg_fusion_stream_probe), HIP events on the
+    current stream."""
+    H, Wd = F.shape[0], F.shape[1]
+    od = torch.empty((H, Wd), device=dev)
+    ob = torch.empty((H, Wd), dtype=torch.int32, device=dev)
+    ws = torch.empty(gg.workspace_size(3, 1, 1, 1, Wd, H, tp.num_bins), dtype=torch.uint8,
+                     device=dev)
+    for _ in range(2):
+        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws)
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
 def cpu_baseline(c, depth, rgb, budget_s=12.0, max_frames=30):
     """The CPU oracle (plain C, OpenMP) on the same workload: whole frames
     (splat + fusion with carry + extraction) in sequence until the time
@@ -702,6 +723,14 @@ def main():
     cb = measure_copy_gbs(torch, dev)
     roof["copy_gb_s"] = round(cb, 1)
     roof["frac_of_copy"] = round(achieved / cb, 4)
+    # the fusion kernel's own volume stream alone (same kernel and launch shape, no views): the
+    # ceiling of its access pattern on this GPU, on the carried volume in place
+    pr_ms = fusion_stream_probe_ms(gg, torch, dev, tgt, tp, F, Wv)
+    pr_bytes = vox * 16 + ns * 8
+    roof["stream_probe"] = {"kernel_ms": round(pr_ms, 4),
+                            "gb_s": round(pr_bytes / (pr_ms * 1e-3) / 1e9, 1),
+                            "bytes_per_launch": pr_bytes}
+    roof["frac_of_stream_probe"] = round(achieved / roof["stream_probe"]["gb_s"], 4)
     tr = roof["traffic"]
     if tr is not None:
         # counted HBM-side bytes (read + write of the committed counter summary) over the same time

@@ -499,6 +499,20 @@ int gg_set_volume_vector(int bins_per_thread);
  * depend on it; it exists to exercise both paths.  Process-wide. */
 int gg_set_ewa_sort_limit(int keys);
 
+/* Measurement utility: the fusion kernel of tsdf_integrate launched in its
+ * own launch shape (gg_set_volume_tile / _vector) with no views, so that it
+ * moves exactly its volume stream -- F_prev and W_prev read, F and W
+ * written (16 bytes per voxel, may alias), the fused extraction -- and none
+ * of the view-table gathers: the ceiling of the fusion's memory access
+ * pattern on this device.  Each voxel only decays its carried weight:
+ * W = min(decay W_prev, weight_cap), F = (W F_prev) / W (0 where W is 0).
+ * Arguments as tsdf_integrate; out_depth and out_bin are required; ws:
+ * gg_workspace_size(GG_OP_TSDF_INTEGRATE, 1, 1, 1, tgt_w, tgt_h, D, NULL). */
+int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
+                           const float *F_prev, const float *W_prev, float *F, float *W,
+                           float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* Self-check of the correctly rounded reciprocal the fusion kernels use for
  * 1/z: for every FP32 value with biased exponent in [e_lo, e_hi] (all 2^23
  * significands of each), compares it bitwise with IEEE division on the

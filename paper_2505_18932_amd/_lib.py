@@ -105,6 +105,7 @@ SIGNATURES = {
     "gg_batch_device_bytes": (SZ, [P]),
     "gg_batch_destroy": (C.c_int, [P]),
     "gg_fast_reciprocal": (C.c_int, [P, P, C.c_int64, P]),
+    "gg_fusion_stream_probe": (C.c_int, [CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
 }
 
 _lib = None

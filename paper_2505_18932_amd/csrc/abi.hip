@@ -827,6 +827,59 @@ int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
                         W_prev, F, W, out_depth, out_bin, ws, ws_bytes, stream);
 }
 
+int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
+                           const float *F_prev, const float *W_prev, float *F, float *W,
+                           float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
+                           void *stream) {
+  const char *N = "gg_fusion_stream_probe";
+  if (int rc = check_camera(tgt, N)) return rc;
+  if (int rc = check_tsdf(prm, N)) return rc;
+  if (!F_prev || !W_prev || !F || !W || !out_depth || !out_bin)
+    return fail(GG_ERR_INVALID, "%s: NULL array argument", N);
+  const int D = prm->num_bins;
+  const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
+  VolumeShape vs;
+  const bool a32 = aligned(F, 32) && aligned(W, 32) && aligned(F_prev, 32) && aligned(W_prev, 32);
+  if (int rc = volume_shape(D, npix, vs, N, a32)) return rc;
+  const size_t va = 4 * (size_t)vs.V;
+  if (!aligned(F, va) || !aligned(W, va) || !aligned(F_prev, va) || !aligned(W_prev, va))
+    return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
+  if ((size_t)npix * D > (size_t)1 << 40) return fail(GG_ERR_UNSUPPORTED, "%s: volume too large", N);
+  const TsdfLayout L = tsdf_layout(1, 1, 1, D, false);
+  if (int rc = check_ws(ws, ws_bytes, L.total, N)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  float2 *bins = (float2 *)((char *)ws + L.bins);
+  if (int rc = launch_bins(*prm, bins, s)) return rc;
+  // the fusion kernel's own launch with no views: every voxel only decays
+  // its carried weight (W = min(decay W_prev, cap), F = that weight times
+  // F_prev over itself), so the kernel moves exactly its volume stream
+  IntegrateArgs a{};
+  a.table = (const float2 *)ws;
+  a.bins = bins;
+  a.F_prev = F_prev;
+  a.W_prev = W_prev;
+  a.F = F;
+  a.W = W;
+  a.out_depth = out_depth;
+  a.out_bin = out_bin;
+  a.K = 0;
+  a.Ws = a.Hs = 1;
+  a.D = D;
+  a.npix = npix;
+  a.ns = 1;
+  a.wt_div = make_fastdiv((uint32_t)tgt->width);
+  a.cpp_div = make_fastdiv(vs.cpp);
+  a.cpp = vs.cpp;
+  a.ppb = vs.ppb;
+  a.pw_shift = vs.pw_shift;
+  a.nblocks = vs.nblocks;
+  a.decay = prm->decay;
+  a.cap = prm->weight_cap;
+  a.carry = 1;
+  a.exact_only = 0;
+  return launch_integrate(a, vs.V, vs.threads, s);
+}
+
 int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
                            const gg_camera *tgt, const gg_tsdf_params *prm,
                            const float *temporal_mask, const float *F_prev, const float *W_prev,

@@ -314,6 +314,24 @@ def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None,
     return F, W, od, ob
 
 
+def fusion_stream_probe(tgt, params, F_prev, W_prev, F, W, out_depth, out_bin, *, ws=None,
+                        stream=None):
+    """The fusion kernel's volume stream alone (no views, no gathers): the
+    ceiling of its memory access pattern (see include/ggeom.h)."""
+    dev = _device(F_prev)
+    tg, tp = camera(tgt), tsdf_params(params)
+    vol = (tg.height, tg.width, tp.num_bins)
+    for t, n in ((F_prev, "F_prev"), (W_prev, "W_prev"), (F, "F"), (W, "W")):
+        _need(t, torch.float32, vol, n, dev)
+    _need(out_depth, torch.float32, vol[:2], "out_depth", dev)
+    _need(out_bin, torch.int32, vol[:2], "out_bin", dev)
+    need = workspace_size(L.GG_OP_TSDF_INTEGRATE, 1, 1, 1, tg.width, tg.height, tp.num_bins)
+    wsb, wsn = _ws(need, dev, ws)
+    L.check(L.lib().gg_fusion_stream_probe(C.byref(tg), C.byref(tp), _ptr(F_prev), _ptr(W_prev),
+                                           _ptr(F), _ptr(W), _ptr(out_depth), _ptr(out_bin),
+                                           _ptr(wsb), wsn, _stream(dev, stream)))
+
+
 def tsdf_integrate_noalloc(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
                            mask=None, extract=True, stream=None):
     """tsdf_integrate through the entry point that takes no workspace and

@@ -595,3 +595,35 @@ def test_backward_at_the_streaming_size_against_the_oracle(streaming_frame):
     assert (rd != 0).sum() > 1000
     grad_close(gd.cpu().numpy(), rd, bd, "splat depth gradient (streaming size)")
     grad_close(gc.cpu().numpy(), rc, bc, "splat colour gradient (streaming size)")
+
+
+@pytest.mark.parametrize("vec", [8, 4, 2])
+def test_fusion_stream_probe(vec):
+    """The fusion kernel launched with no views (the benchmark's ceiling
+    probe of the volume stream) only decays the carried weight, in place:
+    W = min(decay W_prev, cap), F = (W F_prev) / W (0 where W is 0), in that
+    FP32 order; its fused extraction equals tsdf_extract_depth on the
+    result."""
+    from paper_2505_18932_amd import autotune
+    c = small(w=61, h=35, k=3, bins=32)
+    depth, _ = to_dev(c)
+    tp = c["tsdf"]
+    F, W, _, _ = gg.tsdf_integrate(c["src"], depth, c["tgt"], tp)
+    Fp, Wp = F.cpu().numpy(), W.cpu().numpy()
+    od = torch.empty(F.shape[:2], device=DEV)
+    ob = torch.empty(F.shape[:2], dtype=torch.int32, device=DEV)
+    autotune.set_plain((16, 16, vec))
+    try:
+        gg.ops.fusion_stream_probe(c["tgt"], tp, F, W, F, W, od, ob)
+        torch.cuda.synchronize()
+    finally:
+        autotune.set_plain((0, 0, 0))
+    wn = np.minimum(np.float32(tp["decay"]) * Wp, np.float32(tp["weight_cap"]))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        fn = np.where(wn > 0, (wn * Fp) / wn, np.float32(0)).astype(np.float32)
+    assert np.array_equal(bits(W.cpu().numpy()), bits(wn))
+    assert np.array_equal(bits(F.cpu().numpy()), bits(fn))
+    d2, b2 = gg.tsdf_extract_depth(c["tgt"], tp, F, W)
+    torch.cuda.synchronize()
+    assert torch.equal(od.view(torch.int32), d2.view(torch.int32))
+    assert torch.equal(ob, b2)
