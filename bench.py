@@ -104,6 +104,11 @@ def recorded_valu_instructions():
     return float(v.group(1))
 
 
+# The fusion launch shape the main leg tuned (or --tile), passed with every later fusion call of
+# this script (the library keeps no launch shape of its own).
+TILE = [None]
+
+
 def fusion_stream_probe_ms(gg, torch, dev, tgt, tp, F, W, reps=10):
     """Mean duration of the fusion kernel launched with no views on the
     volume (F, W) in place (gg_fusion_stream_probe), HIP events on the
@@ -114,12 +119,12 @@ def fusion_stream_probe_ms(gg, torch, dev, tgt, tp, F, W, reps=10):
     ws = torch.empty(gg.workspace_size(3, 1, 1, 1, Wd, H, tp.num_bins), dtype=torch.uint8,
                      device=dev)
     for _ in range(2):
-        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws)
+        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws, tuning=TILE[0])
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     s.record()
     for _ in range(reps):
-        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws)
+        gg.ops.fusion_stream_probe(tgt, tp, F, W, F, W, od, ob, ws=ws, tuning=TILE[0])
     e.record()
     e.synchronize()
     return s.elapsed_time(e) / reps
@@ -201,7 +206,7 @@ def paper_shape_leg(gg, torch, dev, c, frames, steps=20):
         gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s, stream=side)
         main.wait_event(ev_t[b])
         gg.tsdf_integrate(src, depth[f], tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv, ws=wss[b],
-                          table_ready=True)
+                          table_ready=True, tuning=TILE[0])
         ev_f[b].record(main)
 
     def per_frame(fn):
@@ -245,7 +250,7 @@ def bwd_fwd_ratio(gg, torch, dev, c=None, reps=10):
 
     def fwd():
         o = gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"])
-        F, W, d, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
+        F, W, d, b = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"], tuning=TILE[0])
         return o, F, W, d, b
 
     o, F, W, d, b = fwd()
@@ -311,7 +316,8 @@ def batched_speedup(gg, torch, dev, procs, tune=True, tuning=None):
     def plain():
         for it, o in zip(items, outs):
             gg.splat_views(it["src"], it["depth"], it["rgb"], it["tgt"], it["splat"])
-            gg.tsdf_integrate(it["src"], it["depth"], it["tgt"], it["tsdf"], F=o["F"], W=o["W"])
+            gg.tsdf_integrate(it["src"], it["depth"], it["tgt"], it["tsdf"], F=o["F"], W=o["W"],
+                              tuning=TILE[0])
 
     def timed(fn, reps=5):
         fn()
@@ -376,7 +382,7 @@ def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
                                 filtered=filt, ws=wsm)
             gg.splat_views(src, filt, rgb[f], tgt, sp, mask=mask, out=so[0], ws=ws_s)
             gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv,
-                              mask=so[0]["mask_max"], ws=wst[0])
+                              mask=so[0]["mask_max"], ws=wst[0], tuning=TILE[0])
             return
         b = i % 2
         main = torch.cuda.current_stream(dev)
@@ -388,7 +394,7 @@ def temporal_path(gg, torch, dev, src, tgt, sp, tp, depth, rgb, steps, warmup):
         ready[b].record(side)
         main.wait_event(ready[b])
         gg.tsdf_integrate(src, filt, tgt, tp, F_prev=F, W_prev=Wv, F=F, W=Wv,
-                          mask=so[b]["mask_max"], ws=wst[b], table_ready=True)
+                          mask=so[b]["mask_max"], ws=wst[b], table_ready=True, tuning=TILE[0])
         done[b].record(main)
 
     def timed(first):
@@ -616,9 +622,11 @@ def main():
     ev_table = [torch.cuda.Event(), torch.cuda.Event()]
     ev_fused = [torch.cuda.Event(), torch.cuda.Event()]
 
-    def step(i, carry=True):
+    def step(i, carry=True, tuning=None):
         f = i % nf
-        prev = dict(F_prev=F if carry else None, W_prev=Wv if carry else None, F=F, W=Wv)
+        tun = tuning if tuning is not None else TILE[0]
+        prev = dict(F_prev=F if carry else None, W_prev=Wv if carry else None, F=F, W=Wv,
+                    tuning=tun)
         if s_splat is None:
             gg.splat_views(src, depth[f], rgb[f], tgt, sp, out=sout, ws=ws_s)
             return gg.tsdf_integrate(src, depth[f], tgt, tp, ws=ws_t, **prev)
@@ -638,12 +646,12 @@ def main():
     step(0, carry=False)
     if args.tile:
         tile = tuple(int(v) for v in args.tile.split(","))
-        autotune.set_plain(tile)
     elif s_splat is not None:
         # timed inside the two-stream step, where the fusion shares the device
         tile, tile_times, _ = autotune.tune_plain_step(step, 1)
     else:
         tile, tile_times = autotune.tune_plain(src, depth[0], tgt, tp, use_cache=False)
+    TILE[0] = tile
     for i in range(1, args.warmup):
         step(i)
     torch.cuda.synchronize()

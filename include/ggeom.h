@@ -94,6 +94,26 @@ typedef struct gg_mask_params {
   int32_t factor; /* the mask is formed at 1/factor resolution (§3.2: 4), 1 .. 16     */
 } gg_mask_params;
 
+/* Launch shape of the volume kernels (tsdf_integrate and its variants,
+ * tsdf_extract_depth, gg_fusion_stream_probe), passed with each call; NULL or
+ * a zero field takes the default.  Results never depend on it (it exists for
+ * the autotuner).
+ *   pixels_per_block  whole target pixels per workgroup, 0..1024 (0: 512
+ *                     threads' worth)
+ *   pixels_per_row    neighbouring pixels interleaved in a wavefront row of
+ *                     the fusion, 0..64 (the largest power of two <= it
+ *                     dividing pixels_per_block is used; 0: 16)
+ *   bins_per_thread   1, 2, 4 or 8 (0: 4 where it divides num_bins); used
+ *                     where it divides num_bins and, for 8, where every
+ *                     volume argument is 32-byte aligned, else the largest of
+ *                     4, 2, 1 dividing num_bins.
+ * Invalid values: GG_ERR_INVALID. */
+typedef struct gg_volume_tuning {
+  int32_t pixels_per_block;
+  int32_t pixels_per_row;
+  int32_t bins_per_thread;
+} gg_volume_tuning;
+
 /* Operations for gg_workspace_size(). */
 enum {
   GG_OP_SPLAT = 1,
@@ -202,6 +222,9 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
  * ulp): the outputs are bitwise reproducible, independent of the launch.
  *
  * src, K, depth, rgb, tgt, prm: as splat_views.  lowpass >= 0 (px^2).
+ * sort_limit: the longest per-tile key list sorted in LDS in one piece
+ * (64..512; 0: 512); longer lists are sorted as runs of the largest power of
+ * two not above it, merged in global memory.  Results do not depend on it.
  * out_rgb float K x 3 x tgt_h x tgt_w; out_alpha, out_depth float
  * K x tgt_h x tgt_w: overwritten.  ws: gg_workspace_size(GG_OP_SPLAT_EWA,
  * ...), 256-byte aligned; it holds the Gaussians' records and per-tile key
@@ -209,8 +232,8 @@ int splat_views_backward(const gg_camera *src, int32_t K, const float *depth,
  * ------------------------------------------------------------------------- */
 int splat_views_ewa(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
                     const gg_camera *tgt, const gg_splat_params *prm, float lowpass,
-                    float *out_rgb, float *out_alpha, float *out_depth, void *ws,
-                    size_t ws_bytes, void *stream);
+                    int32_t sort_limit, float *out_rgb, float *out_alpha, float *out_depth,
+                    void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * tsdf_raymarch -- the volume-free form of the fusion (Suppl. A.1): per
@@ -340,11 +363,12 @@ int difference_masks(int32_t K, int32_t width, int32_t height, const uint8_t *rg
  * F_prev, W_prev float tgt_h x tgt_w x D or both NULL (no carry); they may
  * alias F, W.  F, W float tgt_h x tgt_w x D: overwritten.
  * out_depth float tgt_h x tgt_w, out_bin int32 tgt_h x tgt_w: both or neither.
+ * tuning [host]: the launch shape, or NULL (gg_volume_tuning).
  * ------------------------------------------------------------------------- */
 int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
                    const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
                    const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
-                   void *ws, size_t ws_bytes, void *stream);
+                   const gg_volume_tuning *tuning, void *ws, size_t ws_bytes, void *stream);
 
 /* The fusion in two calls, for a caller that builds a frame's view table on
  * another stream ahead of the fusion (it depends on the depth maps only):
@@ -360,8 +384,8 @@ int tsdf_view_table(const gg_camera *src, int32_t K, const float *depth,
 int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
                           const gg_tsdf_params *prm, const float *temporal_mask,
                           const float *F_prev, const float *W_prev, float *F, float *W,
-                          float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
-                          void *stream);
+                          float *out_depth, int32_t *out_bin, const gg_volume_tuning *tuning,
+                          void *ws, size_t ws_bytes, void *stream);
 
 /* tsdf_integrate without a workspace argument and without allocating: for
  * callers that cannot allocate device memory (code under HIP graph capture,
@@ -380,15 +404,18 @@ int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
 int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
                            const gg_camera *tgt, const gg_tsdf_params *prm,
                            const float *temporal_mask, const float *F_prev, const float *W_prev,
-                           float *F, float *W, float *out_depth, int32_t *out_bin, void *stream);
+                           float *F, float *W, float *out_depth, int32_t *out_bin,
+                           const gg_volume_tuning *tuning, void *stream);
 
 /* tsdf_extract_depth -- the surface is where the fused signed distance
  * changes sign along the ray (Suppl. A.1).  On the bins: d* = the smallest
  * d in [0, D-2] with W_d > 0, W_{d+1} > 0, F_d > 0 and F_{d+1} <= 0;
  * out_depth = z_d + (z_{d+1} - z_d) F_d / (F_d - F_{d+1}), out_bin = d*;
- * no crossing: 0 and -1.  F, W float tgt_h x tgt_w x D. */
+ * no crossing: 0 and -1.  F, W float tgt_h x tgt_w x D.  tuning [host]: the
+ * launch shape or NULL (results do not depend on it). */
 int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
-                       const float *W, float *out_depth, int32_t *out_bin, void *stream);
+                       const float *W, float *out_depth, int32_t *out_bin,
+                       const gg_volume_tuning *tuning, void *stream);
 
 /* Adjoint of tsdf_extract_depth: for L = <g_depth, out_depth>,
  * g_F2[p] = (dL/dF_{d*}, dL/dF_{d*+1}) at the pixel's crossing (0, 0 where
@@ -443,8 +470,9 @@ typedef struct gg_batch_item {
 
 /* Launch shape chosen by the autotuner (0 = default). */
 typedef struct gg_batch_tuning {
-  int32_t volume_threads; /* threads per fusion workgroup, multiple of 64 in 64..1024 (256) */
-  int32_t blocks_per_cu;  /* persistent workgroups per compute unit, 1..64 (4)              */
+  int32_t volume_threads;  /* threads per fusion workgroup, multiple of 64 in 64..1024 (256) */
+  int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..64 (4)              */
+  int32_t bins_per_thread; /* of the fusion, as in gg_volume_tuning (0: default)            */
 } gg_batch_tuning;
 
 typedef struct gg_batch gg_batch;
@@ -454,13 +482,13 @@ typedef struct gg_batch gg_batch;
  * uploads descriptors and captures the phases into a graph.  The plan binds
  * the items' device pointers: refill those buffers between launches.  This
  * call allocates and synchronises; gg_batch_launch does neither. */
-int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tuning,
-                    gg_batch **plan);
+int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tuning,
+                  gg_batch **plan);
 /* One graph launch running the whole batch on `stream`. */
 int gg_batch_launch(gg_batch *plan, void *stream);
 size_t gg_batch_device_bytes(const gg_batch *plan);
 /* Frees the plan (call after its last launch has completed). */
-int gg_batch_destroy(gg_batch *plan);
+int gg_batch_free(gg_batch *plan);
 
 /* ---------------------------------------------------------------------------
  * Utilities.
@@ -476,31 +504,8 @@ const char *gg_last_error(void);
  * and rounded to FP32 once.  H [host] 9 floats row-major, c [host] 3. */
 int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c);
 
-/* Launch shape of the volume kernels (tsdf_integrate, tsdf_extract_depth):
- * whole target pixels per workgroup (each thread holding consecutive bins of
- * one pixel, see gg_set_volume_vector) and the number of neighbouring pixels
- * interleaved in a wavefront row of tsdf_integrate (a power of two dividing
- * the former; the largest such <= pixels_per_row is used).  0 restores the
- * defaults (512 threads' worth of pixels; up to 16 per row).  Results do not
- * depend on the choice; it exists for the autotuner.  Process-wide. */
-int gg_set_volume_tile(int pixels_per_block, int pixels_per_row);
-
-/* Bins held by each thread of the volume kernels: 1, 2, 4 or 8 (0 restores
- * the default, 4 where it divides num_bins).  Used where it divides
- * num_bins and, for 8, where every volume argument is 32-byte aligned;
- * otherwise the largest of 4, 2, 1 dividing num_bins.  Results do not
- * depend on it; it exists for the autotuner.  Process-wide.  Returns
- * GG_ERR_INVALID for any other value. */
-int gg_set_volume_vector(int bins_per_thread);
-
-/* Longest per-tile key list splat_views_ewa sorts in LDS in one piece
- * (64..512; 0 restores 512); longer lists are sorted as runs of the largest
- * power of two not above it, merged in global memory.  Results do not
- * depend on it; it exists to exercise both paths.  Process-wide. */
-int gg_set_ewa_sort_limit(int keys);
-
-/* Measurement utility: the fusion kernel of tsdf_integrate launched in its
- * own launch shape (gg_set_volume_tile / _vector) with no views, so that it
+/* Measurement utility: the fusion kernel of tsdf_integrate launched in the
+ * launch shape of `tuning` with no views, so that it
  * moves exactly its volume stream -- F_prev and W_prev read, F and W
  * written (16 bytes per voxel, may alias), the fused extraction -- and none
  * of the view-table gathers: the ceiling of the fusion's memory access
@@ -510,8 +515,8 @@ int gg_set_ewa_sort_limit(int keys);
  * gg_workspace_size(GG_OP_TSDF_INTEGRATE, 1, 1, 1, tgt_w, tgt_h, D, NULL). */
 int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
                            const float *F_prev, const float *W_prev, float *F, float *W,
-                           float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
-                           void *stream);
+                           float *out_depth, int32_t *out_bin, const gg_volume_tuning *tuning,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /* Self-check of the correctly rounded reciprocal the fusion kernels use for
  * 1/z: for every FP32 value with biased exponent in [e_lo, e_hi] (all 2^23

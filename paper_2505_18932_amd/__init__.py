@@ -9,19 +9,19 @@ C ABI (include/ggeom.h).
 from . import _lib, autograd
 from .ops import (BatchPlan, blend_views, camera, cameras, difference_masks, mask_params,
                   network_inputs,
-                  relative_projection, set_ewa_sort_limit, splat_params, splat_views,
+                  relative_projection, splat_params, splat_views,
                   splat_views_backward, splat_views_ewa, timing_enable, timing_read, timing_reset,
                   tsdf_extract_depth, tsdf_extract_depth_backward, tsdf_integrate,
                   tsdf_integrate_backward, tsdf_integrate_noalloc, tsdf_params, tsdf_raymarch,
-                  tsdf_view_table,
+                  tsdf_view_table, volume_tuning,
                   workspace_size)
 
 __all__ = ["BatchPlan", "blend_views", "camera", "cameras", "difference_masks", "mask_params",
            "network_inputs",
-           "relative_projection", "set_ewa_sort_limit", "splat_params", "splat_views",
+           "relative_projection", "splat_params", "splat_views",
            "splat_views_backward", "splat_views_ewa", "timing_enable", "timing_read", "timing_reset",
            "tsdf_extract_depth", "tsdf_extract_depth_backward", "tsdf_integrate",
            "tsdf_integrate_backward", "tsdf_integrate_noalloc", "tsdf_params", "tsdf_raymarch",
-           "tsdf_view_table",
+           "tsdf_view_table", "volume_tuning",
            "workspace_size", "_lib",
            "autograd"]

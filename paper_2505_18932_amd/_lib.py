@@ -58,13 +58,20 @@ class GGBatchItem(C.Structure):
 
 
 class GGBatchTuning(C.Structure):
-    _fields_ = [("volume_threads", C.c_int32), ("blocks_per_cu", C.c_int32)]
+    _fields_ = [("volume_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("bins_per_thread", C.c_int32)]
+
+
+class GGVolumeTuning(C.Structure):
+    _fields_ = [("pixels_per_block", C.c_int32), ("pixels_per_row", C.c_int32),
+                ("bins_per_thread", C.c_int32)]
 
 
 P = C.c_void_p
 CAM = C.POINTER(GGCamera)
 SPP = C.POINTER(GGSplatParams)
 TSP = C.POINTER(GGTsdfParams)
+VTP = C.POINTER(GGVolumeTuning)
 I32 = C.c_int32
 SZ = C.c_size_t
 
@@ -74,19 +81,20 @@ SIGNATURES = {
     "splat_views": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, SZ, P]),
     "splat_views_masked": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, SZ,
                                      P]),
-    "splat_views_ewa": (C.c_int, [CAM, I32, P, P, CAM, SPP, C.c_float, P, P, P, P, SZ, P]),
+    "splat_views_ewa": (C.c_int, [CAM, I32, P, P, CAM, SPP, C.c_float, I32, P, P, P, P, SZ, P]),
     "splat_views_backward": (C.c_int, [CAM, I32, P, P, CAM, SPP, P, P, P, P, P, P, P, P, P, P,
                                        SZ, P]),
     "difference_masks": (C.c_int, [I32, I32, I32, P, P, C.POINTER(GGMaskParams), P, P, P, P, P,
                                    SZ, P]),
-    "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
+    "tsdf_integrate": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, VTP, P, SZ, P]),
     "tsdf_view_table": (C.c_int, [CAM, I32, P, TSP, P, SZ, P]),
-    "tsdf_integrate_noalloc": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, P]),
-    "tsdf_integrate_tabled": (C.c_int, [CAM, I32, CAM, TSP, P, P, P, P, P, P, P, P, SZ, P]),
+    "tsdf_integrate_noalloc": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, VTP, P]),
+    "tsdf_integrate_tabled": (C.c_int, [CAM, I32, CAM, TSP, P, P, P, P, P, P, P, VTP, P, SZ,
+                                        P]),
     "tsdf_raymarch": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
     "network_inputs": (C.c_int, [CAM, I32, CAM, P, P, P, P, P, P]),
     "blend_views": (C.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, P]),
-    "tsdf_extract_depth": (C.c_int, [CAM, TSP, P, P, P, P, P]),
+    "tsdf_extract_depth": (C.c_int, [CAM, TSP, P, P, P, P, VTP, P]),
     "tsdf_extract_depth_backward": (C.c_int, [CAM, TSP, P, P, P, P, P, P]),
     "tsdf_integrate_backward": (C.c_int, [CAM, I32, P, CAM, TSP, P, P, P, P, P, P, SZ, P]),
     "gg_last_error": (C.c_char_p, []),
@@ -95,17 +103,14 @@ SIGNATURES = {
     "gg_timing_filter": (C.c_int, [C.c_char_p]),
     "gg_timing_reset": (C.c_int, []),
     "gg_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
-    "gg_set_volume_tile": (C.c_int, [C.c_int, C.c_int]),
-    "gg_set_volume_vector": (C.c_int, [C.c_int]),
-    "gg_set_ewa_sort_limit": (C.c_int, [C.c_int]),
     "gg_selftest_reciprocal": (C.c_int, [I32, I32, P, P]),
-    "gg_batch_create": (C.c_int, [C.POINTER(GGBatchItem), I32, C.POINTER(GGBatchTuning),
-                                  C.POINTER(C.c_void_p)]),
+    "gg_batch_plan": (C.c_int, [C.POINTER(GGBatchItem), I32, C.POINTER(GGBatchTuning),
+                                C.POINTER(C.c_void_p)]),
     "gg_batch_launch": (C.c_int, [P, P]),
     "gg_batch_device_bytes": (SZ, [P]),
-    "gg_batch_destroy": (C.c_int, [P]),
+    "gg_batch_free": (C.c_int, [P]),
     "gg_fast_reciprocal": (C.c_int, [P, P, C.c_int64, P]),
-    "gg_fusion_stream_probe": (C.c_int, [CAM, TSP, P, P, P, P, P, P, P, SZ, P]),
+    "gg_fusion_stream_probe": (C.c_int, [CAM, TSP, P, P, P, P, P, P, VTP, P, SZ, P]),
 }
 
 _lib = None

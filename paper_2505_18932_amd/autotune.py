@@ -6,8 +6,9 @@ caches the winner per GPU architecture and workload class in a JSON file
 next to this module (``tuning_cache.json``):
 
 * plain path: bins per thread, pixels per workgroup and per wavefront row of
-  the fusion for a (K, D, width, height) class, applied through
-  ``gg_set_volume_vector`` and ``gg_set_volume_tile``;
+  the fusion for a (K, D, width, height) class: a launch shape the caller
+  passes with each call (``tuning=`` of the volume calls, the C ABI's
+  ``gg_volume_tuning``); nothing is set process-wide;
 * batched path: (threads per fusion workgroup, persistent workgroups per
   compute unit) for a batch signature.
 """
@@ -19,7 +20,6 @@ import time
 
 import torch
 
-from . import _lib as L
 from . import ops
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -70,32 +70,22 @@ def plain_key(K, D, width, height):
     return f"plain-v/K{K}/D{D}/{width}x{height}"
 
 
-def set_plain(cand):
-    ppb, pw, vec = cand
-    L.check(L.lib().gg_set_volume_tile(ppb, pw))
-    L.check(L.lib().gg_set_volume_vector(vec))
-
-
 def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
     """Best (pixels per workgroup, pixels per row, bins per thread) of
-    tsdf_integrate for this class; sets it process-wide and returns
-    (best, {candidate: ms})."""
+    tsdf_integrate for this class; returns (best, {candidate: ms}), best to
+    be passed as ``tuning=`` to the volume calls."""
     tg, tp = ops.camera(tgt), ops.tsdf_params(params)
     key = plain_key(len(src), tp.num_bins, tg.width, tg.height)
     cache = _load()
     a = arch(depth.device)
     if use_cache and key in cache.get(a, {}):
-        best = tuple(cache[a][key]["best"])
-        set_plain(best)
-        return best, cache[a][key]["times"]
+        return tuple(cache[a][key]["best"]), cache[a][key]["times"]
     F, W, _, _ = ops.tsdf_integrate(src, depth, tgt, params)
     times = {}
     for cand in PLAIN_CANDIDATES:
-        set_plain(cand)
         times["%d,%d,%d" % cand] = _time(lambda: ops.tsdf_integrate(
-            src, depth, tgt, params, F_prev=F, W_prev=W, F=F, W=W), reps)
+            src, depth, tgt, params, F_prev=F, W_prev=W, F=F, W=W, tuning=cand), reps)
     best = tuple(int(v) for v in min(times, key=times.get).split(","))
-    set_plain(best)
     cache.setdefault(a, {})[key] = {"best": list(best), "times": times, "when": time.time()}
     _save(cache)
     return best, times
@@ -103,26 +93,25 @@ def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
 
 def tune_plain_step(step, first, reps=8, warm=2):
     """Best launch shape of the fusion for a whole step of the caller's
-    pipeline (``step(i)`` runs frame i, perhaps on several streams, where
-    the fusion shares the device with other work): each candidate is timed
-    over ``reps`` steps after ``warm`` untimed ones.  Sets the best and
-    returns (best, {candidate: ms per step}, next frame index)."""
+    pipeline (``step(i, tuning)`` runs frame i with that launch shape,
+    perhaps on several streams, where the fusion shares the device with
+    other work): each candidate is timed over ``reps`` steps after ``warm``
+    untimed ones.  Returns (best, {candidate: ms per step}, next frame
+    index)."""
     times = {}
     i = first
     for cand in PLAIN_CANDIDATES:
-        set_plain(cand)
         for _ in range(warm):
-            step(i)
+            step(i, tuning=cand)
             i += 1
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            step(i)
+            step(i, tuning=cand)
             i += 1
         torch.cuda.synchronize()
         times["%d,%d,%d" % cand] = (time.perf_counter() - t0) * 1e3 / reps
     best = tuple(int(v) for v in min(times, key=times.get).split(","))
-    set_plain(best)
     return best, times, i
 
 

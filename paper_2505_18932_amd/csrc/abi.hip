@@ -311,11 +311,20 @@ static int check_ws(void *ws, size_t have, size_t need, const char *what) {
 }
 
 // Launch shape of the volume kernels: V bins per thread, whole pixels per
-// workgroup, neighbouring pixels per wavefront row (tunable through
-// gg_set_volume_tile).
-static int g_ppb_override = 0;
-static int g_pw_override = -1;
-static int g_v_override = 0;  // bins per thread (gg_set_volume_vector)
+// workgroup, neighbouring pixels per wavefront row (the caller's
+// gg_volume_tuning, per call; NULL or zero fields: the defaults).
+static int check_tuning(const gg_volume_tuning *t, const char *what) {
+  if (!t) return GG_OK;
+  if (t->pixels_per_block < 0 || t->pixels_per_block > 1024)
+    return fail(GG_ERR_INVALID, "%s: pixels_per_block %d outside 0..1024", what,
+                t->pixels_per_block);
+  if (t->pixels_per_row < 0 || t->pixels_per_row > 64)
+    return fail(GG_ERR_INVALID, "%s: pixels_per_row %d outside 0..64", what, t->pixels_per_row);
+  const int v = t->bins_per_thread;
+  if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)
+    return fail(GG_ERR_INVALID, "%s: bins_per_thread %d not in {0, 1, 2, 4, 8}", what, v);
+  return GG_OK;
+}
 
 struct VolumeShape {
   int V;
@@ -329,27 +338,28 @@ static uint32_t pick_pw_shift(uint32_t ppb, int cap) {
   return sh;
 }
 
-// Bins per thread: the gg_set_volume_vector choice where it divides D (and,
-// for 8, the volumes are 32-byte aligned), else 4, 2 or 1, the largest
-// dividing D.
-static int volume_v(int D, bool aligned32) {
-  const int o = g_v_override;
+// Bins per thread: the tuning's choice where it divides D (and, for 8, the
+// volumes are 32-byte aligned), else 4, 2 or 1, the largest dividing D.
+static int volume_v(int D, bool aligned32, int o) {
   if (o > 0 && D % o == 0 && (o < 8 || aligned32)) return o;
   return (D % 4 == 0) ? 4 : (D % 2 == 0 ? 2 : 1);
 }
 
 static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what,
-                        bool aligned32) {
-  s.V = volume_v(D, aligned32);
+                        bool aligned32, const gg_volume_tuning *tun) {
+  if (int rc = check_tuning(tun, what)) return rc;
+  const int ppb_t = tun ? tun->pixels_per_block : 0;
+  const int pw_t = tun ? tun->pixels_per_row : 0;
+  s.V = volume_v(D, aligned32, tun ? tun->bins_per_thread : 0);
   s.cpp = (uint32_t)(D / s.V);
   if (s.cpp > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
-  uint32_t ppb = g_ppb_override > 0 ? (uint32_t)g_ppb_override : 512u / s.cpp;
+  uint32_t ppb = ppb_t > 0 ? (uint32_t)ppb_t : 512u / s.cpp;
   if (ppb < 1) ppb = 1;
   while (ppb > 1 && ppb * s.cpp > 1024) --ppb;
   s.ppb = ppb;
   s.threads = ppb * s.cpp;
   s.nblocks = (npix + ppb - 1) / ppb;
-  s.pw_shift = pick_pw_shift(ppb, g_pw_override >= 0 ? g_pw_override : 16);
+  s.pw_shift = pick_pw_shift(ppb, pw_t > 0 ? pw_t : 16);
   return GG_OK;
 }
 
@@ -423,26 +433,6 @@ size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_
     default:
       return 0;
   }
-}
-
-int gg_set_volume_tile(int pixels_per_block, int pixels_per_row) {
-  if (pixels_per_block < 0 || pixels_per_block > 1024)
-    return fail(GG_ERR_INVALID, "gg_set_volume_tile: %d outside 0..1024", pixels_per_block);
-  if (pixels_per_row < 0 || pixels_per_row > 64)
-    return fail(GG_ERR_INVALID, "gg_set_volume_tile: pixels_per_row %d outside 0..64",
-                pixels_per_row);
-  g_ppb_override = pixels_per_block;
-  g_pw_override = pixels_per_row == 0 ? -1 : pixels_per_row;
-  return GG_OK;
-}
-
-int gg_set_volume_vector(int bins_per_thread) {
-  if (bins_per_thread != 0 && bins_per_thread != 1 && bins_per_thread != 2 &&
-      bins_per_thread != 4 && bins_per_thread != 8)
-    return fail(GG_ERR_INVALID, "gg_set_volume_vector: %d not in {0, 1, 2, 4, 8}",
-                bins_per_thread);
-  g_v_override = bins_per_thread;
-  return GG_OK;
 }
 
 // The splat kernels' arguments for K views of `src` into `tgt`, workspace
@@ -536,20 +526,13 @@ int splat_views_masked(const gg_camera *src, int32_t K, const float *depth, cons
   return launch_splat_forward(a, (hipStream_t)stream);
 }
 
-static uint32_t g_ewa_sort_limit = kEwaSortCap;
-
-int gg_set_ewa_sort_limit(int keys) {
-  if (keys != 0 && (keys < 64 || keys > (int)kEwaSortCap))
-    return fail(GG_ERR_INVALID, "gg_set_ewa_sort_limit: %d outside 64..%u", keys, kEwaSortCap);
-  g_ewa_sort_limit = keys == 0 ? kEwaSortCap : (uint32_t)keys;
-  return GG_OK;
-}
-
 int splat_views_ewa(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
                     const gg_camera *tgt, const gg_splat_params *prm, float lowpass,
-                    float *out_rgb, float *out_alpha, float *out_depth, void *ws,
-                    size_t ws_bytes, void *stream) {
+                    int32_t sort_limit, float *out_rgb, float *out_alpha, float *out_depth,
+                    void *ws, size_t ws_bytes, void *stream) {
   const char *W = "splat_views_ewa";
+  if (sort_limit != 0 && (sort_limit < 64 || sort_limit > (int)kEwaSortCap))
+    return fail(GG_ERR_INVALID, "%s: sort_limit %d outside 64..%u", W, sort_limit, kEwaSortCap);
   if (int rc = check_sources(src, K, W)) return rc;
   if (int rc = check_camera(tgt, W)) return rc;
   if (int rc = check_splat(prm, W)) return rc;
@@ -599,7 +582,7 @@ int splat_views_ewa(const gg_camera *src, int32_t K, const float *depth, const u
   a.keys_alt = (unsigned long long *)(w + L.keys_alt);
   a.cap = L.cap;
   a.rec = (float4 *)(w + L.rec);
-  a.sort_limit = g_ewa_sort_limit;
+  a.sort_limit = sort_limit == 0 ? kEwaSortCap : (uint32_t)sort_limit;
   a.out_rgb = out_rgb;
   a.out_alpha = out_alpha;
   a.out_depth = out_depth;
@@ -776,8 +759,9 @@ static int integrate_impl(const char *N, bool tabled, const gg_camera *src, int3
                           const float *depth,
                           const gg_camera *tgt, const gg_tsdf_params *prm,
                           const float *temporal_mask, const float *F_prev, const float *W_prev,
-                          float *F, float *W, float *out_depth, int32_t *out_bin, void *ws,
-                          size_t ws_bytes, void *stream) {
+                          float *F, float *W, float *out_depth, int32_t *out_bin,
+                          const gg_volume_tuning *tuning, void *ws, size_t ws_bytes,
+                          void *stream) {
   if (int rc = check_sources(src, K, N)) return rc;
   if (int rc = check_camera(tgt, N)) return rc;
   if (int rc = check_tsdf(prm, N)) return rc;
@@ -791,7 +775,7 @@ static int integrate_impl(const char *N, bool tabled, const gg_camera *src, int3
   VolumeShape vs;
   const bool a32 = aligned(F, 32) && aligned(W, 32) && (!F_prev || (aligned(F_prev, 32) &&
                                                                      aligned(W_prev, 32)));
-  if (int rc = volume_shape(D, npix, vs, N, a32)) return rc;
+  if (int rc = volume_shape(D, npix, vs, N, a32, tuning)) return rc;
   const size_t va = 4 * (size_t)vs.V;
   if (!aligned(F, va) || !aligned(W, va) || (F_prev && (!aligned(F_prev, va) || !aligned(W_prev, va))))
     return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
@@ -813,24 +797,24 @@ static int integrate_impl(const char *N, bool tabled, const gg_camera *src, int3
 int tsdf_integrate(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
                    const gg_tsdf_params *prm, const float *temporal_mask, const float *F_prev,
                    const float *W_prev, float *F, float *W, float *out_depth, int32_t *out_bin,
-                   void *ws, size_t ws_bytes, void *stream) {
-  return integrate_impl("tsdf_integrate", false, src, K, depth, tgt, prm, temporal_mask, F_prev, W_prev,
-                        F, W, out_depth, out_bin, ws, ws_bytes, stream);
+                   const gg_volume_tuning *tuning, void *ws, size_t ws_bytes, void *stream) {
+  return integrate_impl("tsdf_integrate", false, src, K, depth, tgt, prm, temporal_mask, F_prev,
+                        W_prev, F, W, out_depth, out_bin, tuning, ws, ws_bytes, stream);
 }
 
 int tsdf_integrate_tabled(const gg_camera *src, int32_t K, const gg_camera *tgt,
                           const gg_tsdf_params *prm, const float *temporal_mask,
                           const float *F_prev, const float *W_prev, float *F, float *W,
-                          float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
-                          void *stream) {
-  return integrate_impl("tsdf_integrate_tabled", true, src, K, nullptr, tgt, prm, temporal_mask, F_prev,
-                        W_prev, F, W, out_depth, out_bin, ws, ws_bytes, stream);
+                          float *out_depth, int32_t *out_bin, const gg_volume_tuning *tuning,
+                          void *ws, size_t ws_bytes, void *stream) {
+  return integrate_impl("tsdf_integrate_tabled", true, src, K, nullptr, tgt, prm, temporal_mask,
+                        F_prev, W_prev, F, W, out_depth, out_bin, tuning, ws, ws_bytes, stream);
 }
 
 int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
                            const float *F_prev, const float *W_prev, float *F, float *W,
-                           float *out_depth, int32_t *out_bin, void *ws, size_t ws_bytes,
-                           void *stream) {
+                           float *out_depth, int32_t *out_bin, const gg_volume_tuning *tuning,
+                           void *ws, size_t ws_bytes, void *stream) {
   const char *N = "gg_fusion_stream_probe";
   if (int rc = check_camera(tgt, N)) return rc;
   if (int rc = check_tsdf(prm, N)) return rc;
@@ -840,7 +824,7 @@ int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
   const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
   VolumeShape vs;
   const bool a32 = aligned(F, 32) && aligned(W, 32) && aligned(F_prev, 32) && aligned(W_prev, 32);
-  if (int rc = volume_shape(D, npix, vs, N, a32)) return rc;
+  if (int rc = volume_shape(D, npix, vs, N, a32, tuning)) return rc;
   const size_t va = 4 * (size_t)vs.V;
   if (!aligned(F, va) || !aligned(W, va) || !aligned(F_prev, va) || !aligned(W_prev, va))
     return fail(GG_ERR_INVALID, "%s: volumes must be %zu-byte aligned", N, va);
@@ -883,7 +867,8 @@ int gg_fusion_stream_probe(const gg_camera *tgt, const gg_tsdf_params *prm,
 int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
                            const gg_camera *tgt, const gg_tsdf_params *prm,
                            const float *temporal_mask, const float *F_prev, const float *W_prev,
-                           float *F, float *W, float *out_depth, int32_t *out_bin, void *stream) {
+                           float *F, float *W, float *out_depth, int32_t *out_bin,
+                           const gg_volume_tuning *tuning, void *stream) {
   const char *N = "tsdf_integrate_noalloc";
   if (int rc = check_sources(src, K, N)) return rc;
   if (int rc = check_tsdf(prm, N)) return rc;
@@ -894,7 +879,7 @@ int tsdf_integrate_noalloc(const gg_camera *src, int32_t K, const float *depth,
   void *ws = nullptr;
   if (int rc = scratch_of_current_device(&ws, N)) return rc;
   return integrate_impl(N, false, src, K, depth, tgt, prm, temporal_mask, F_prev, W_prev, F, W,
-                        out_depth, out_bin, ws, kScratchBytes, stream);
+                        out_depth, out_bin, tuning, ws, kScratchBytes, stream);
 }
 
 int tsdf_raymarch(const gg_camera *src, int32_t K, const float *depth, const gg_camera *tgt,
@@ -1022,14 +1007,15 @@ int blend_views(int32_t K, int32_t width, int32_t height, const float *rgb, cons
 }
 
 int tsdf_extract_depth(const gg_camera *tgt, const gg_tsdf_params *prm, const float *F,
-                       const float *W, float *out_depth, int32_t *out_bin, void *stream) {
+                       const float *W, float *out_depth, int32_t *out_bin,
+                       const gg_volume_tuning *tuning, void *stream) {
   const char *N = "tsdf_extract_depth";
   if (int rc = check_camera(tgt, N)) return rc;
   if (int rc = check_tsdf(prm, N)) return rc;
   if (!F || !W || !out_depth || !out_bin) return fail(GG_ERR_INVALID, "%s: NULL argument", N);
   const uint32_t npix = (uint32_t)(tgt->width * tgt->height);
   VolumeShape vs;
-  if (int rc = volume_shape(prm->num_bins, npix, vs, N, aligned(F, 32) && aligned(W, 32)))
+  if (int rc = volume_shape(prm->num_bins, npix, vs, N, aligned(F, 32) && aligned(W, 32), tuning))
     return rc;
   const size_t va = 4 * (size_t)vs.V;
   if (!aligned(F, va) || !aligned(W, va))
@@ -1183,16 +1169,16 @@ struct gg_batch {
   std::vector<char> keep;  // nothing host-side is needed after creation
 };
 
-// Bins per thread of a batch item (as for the plain call).
-static int item_vec(const gg_batch_item &it) {
+// Bins per thread of a batch item (as for the plain call with that tuning).
+static int item_vec(const gg_batch_item &it, int vec) {
   const bool a32 = aligned(it.F, 32) && aligned(it.W, 32) &&
                    (!it.F_prev || (aligned(it.F_prev, 32) && aligned(it.W_prev, 32)));
-  return volume_v(it.tsdf.num_bins, a32);
+  return volume_v(it.tsdf.num_bins, a32, vec);
 }
 
-static int check_item(const gg_batch_item &it, int i) {
+static int check_item(const gg_batch_item &it, int i, int vec) {
   char what[64];
-  snprintf(what, sizeof what, "gg_batch_create: item %d", i);
+  snprintf(what, sizeof what, "gg_batch_plan: item %d", i);
   if (int rc = check_sources(it.src, it.K, what)) return rc;
   if (int rc = check_camera(&it.tgt, what)) return rc;
   if (int rc = check_tsdf(&it.tsdf, what)) return rc;
@@ -1207,7 +1193,7 @@ static int check_item(const gg_batch_item &it, int i) {
       return fail(GG_ERR_INVALID, "%s: splat outputs required with rgb", what);
   }
   const int D = it.tsdf.num_bins;
-  const int V = item_vec(it);
+  const int V = item_vec(it, vec);
   if (D / V > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
   const size_t va = 4 * (size_t)V;
   if (!aligned(it.F, va) || !aligned(it.W, va) ||
@@ -1216,14 +1202,17 @@ static int check_item(const gg_batch_item &it, int i) {
   return GG_OK;
 }
 
-extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tune,
-                               gg_batch **out) {
-  const char *N = "gg_batch_create";
+extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_batch_tuning *tune,
+                             gg_batch **out) {
+  const char *N = "gg_batch_plan";
   if (!items || !out || n < 1) return fail(GG_ERR_INVALID, "%s: need items, n >= 1, out", N);
   if (n > 65535) return fail(GG_ERR_UNSUPPORTED, "%s: at most 65535 items", N);
   *out = nullptr;
+  const int vec = tune ? tune->bins_per_thread : 0;
+  if (vec != 0 && vec != 1 && vec != 2 && vec != 4 && vec != 8)
+    return fail(GG_ERR_INVALID, "%s: bins_per_thread %d not in {0, 1, 2, 4, 8}", N, vec);
   for (int i = 0; i < n; ++i)
-    if (int rc = check_item(items[i], i)) return rc;
+    if (int rc = check_item(items[i], i, vec)) return rc;
   int threads = (tune && tune->volume_threads) ? tune->volume_threads : 256;
   int per_cu = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu : 4;
   if (threads < 64 || threads > 1024 || threads % 64 || per_cu < 1 || per_cu > 64)
@@ -1231,7 +1220,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
                 "blocks_per_cu in 1..64", N);
   for (int i = 0; i < n; ++i) {
     const int D = items[i].tsdf.num_bins;
-    const int V = item_vec(items[i]);
+    const int V = item_vec(items[i], vec);
     while (threads < D / V) threads += 64;
   }
   int dev = 0, cus = 256;
@@ -1254,7 +1243,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
     const int sw = it.src[0].width, sh = it.src[0].height, K = it.K, D = it.tsdf.num_bins;
     const uint32_t npix = (uint32_t)(it.tgt.width * it.tgt.height);
     VolumeShape &vs = shapes[i];
-    vs.V = item_vec(it);
+    vs.V = item_vec(it, vec);
     vs.cpp = (uint32_t)(D / vs.V);
     vs.ppb = std::max(1u, (uint32_t)threads / vs.cpp);
     vs.threads = vs.ppb * vs.cpp;
@@ -1392,7 +1381,7 @@ extern "C" int gg_batch_create(const gg_batch_item *items, int32_t n, const gg_b
   if (side) (void)hipStreamDestroy(side);
   if (cs) (void)hipStreamDestroy(cs);
   if (rc != GG_OK) {
-    gg_batch_destroy(b);
+    gg_batch_free(b);
     return rc;
   }
   *out = b;
@@ -1407,7 +1396,7 @@ extern "C" int gg_batch_launch(gg_batch *plan, void *stream) {
 
 extern "C" size_t gg_batch_device_bytes(const gg_batch *plan) { return plan ? plan->P.dev_bytes : 0; }
 
-extern "C" int gg_batch_destroy(gg_batch *plan) {
+extern "C" int gg_batch_free(gg_batch *plan) {
   if (!plan) return GG_OK;
   BatchPlan &P = plan->P;
   if (P.exec) (void)hipGraphExecDestroy(P.exec);

@@ -52,35 +52,44 @@ int launch_conf(const ConfArgs &a, hipStream_t s) {
   return check_hip(hipGetLastError(), "conf_kernel");
 }
 
-template <int V, int KC, bool kExact, bool kStage>
+template <int V, int KC, bool kExact, bool kStage, int kCarry>
 __global__ __launch_bounds__(1024) void integrate_kernel(IntegrateArgs a) {
   extern __shared__ float smem[];
-  integrate_tile<V, KC, kExact, kStage>(a, xcd_tile(blockIdx.x, a.nblocks), smem);
+  integrate_tile<V, KC, kExact, kStage, kCarry>(a, xcd_tile(blockIdx.x, a.nblocks), smem);
 }
 
-template <int V, int KC, bool kStage>
+template <int V, int KC, bool kStage, int kCarry>
 static void launch_integrate_vk(const IntegrateArgs &a, uint32_t threads, size_t shm,
                                 hipStream_t s) {
   if (a.exact_only)
-    hipLaunchKernelGGL((integrate_kernel<V, KC, true, kStage>), dim3(a.nblocks), dim3(threads),
-                       shm, s, a);
+    hipLaunchKernelGGL((integrate_kernel<V, KC, true, kStage, kCarry>), dim3(a.nblocks),
+                       dim3(threads), shm, s, a);
   else
-    hipLaunchKernelGGL((integrate_kernel<V, KC, false, kStage>), dim3(a.nblocks), dim3(threads),
-                       shm, s, a);
+    hipLaunchKernelGGL((integrate_kernel<V, KC, false, kStage, kCarry>), dim3(a.nblocks),
+                       dim3(threads), shm, s, a);
 }
 
-template <int V, bool kStage>
+template <int V, bool kStage, int kCarry>
 static void launch_integrate_v(const IntegrateArgs &a, uint32_t threads, size_t shm,
                                hipStream_t s) {
   switch (a.K) {
-    case 1: launch_integrate_vk<V, 1, kStage>(a, threads, shm, s); break;
-    case 2: launch_integrate_vk<V, 2, kStage>(a, threads, shm, s); break;
-    case 3: launch_integrate_vk<V, 3, kStage>(a, threads, shm, s); break;
-    case 4: launch_integrate_vk<V, 4, kStage>(a, threads, shm, s); break;
-    case 6: launch_integrate_vk<V, 6, kStage>(a, threads, shm, s); break;
-    case 8: launch_integrate_vk<V, 8, kStage>(a, threads, shm, s); break;
-    default: launch_integrate_vk<V, 0, kStage>(a, threads, shm, s); break;
+    case 1: launch_integrate_vk<V, 1, kStage, kCarry>(a, threads, shm, s); break;
+    case 2: launch_integrate_vk<V, 2, kStage, kCarry>(a, threads, shm, s); break;
+    case 3: launch_integrate_vk<V, 3, kStage, kCarry>(a, threads, shm, s); break;
+    case 4: launch_integrate_vk<V, 4, kStage, kCarry>(a, threads, shm, s); break;
+    case 6: launch_integrate_vk<V, 6, kStage, kCarry>(a, threads, shm, s); break;
+    case 8: launch_integrate_vk<V, 8, kStage, kCarry>(a, threads, shm, s); break;
+    default: launch_integrate_vk<V, 0, kStage, kCarry>(a, threads, shm, s); break;
   }
+}
+
+template <int V>
+static void launch_integrate_staged(const IntegrateArgs &a, uint32_t threads, hipStream_t s) {
+  const size_t shm = integrate_lds_bytes<V>(threads, a.ppb, a.D, true);
+  if (a.carry)
+    launch_integrate_v<V, true, 1>(a, threads, shm, s);
+  else
+    launch_integrate_v<V, true, 0>(a, threads, shm, s);
 }
 
 // The volume stream goes through LDS (integrate_tile's kStage) where the
@@ -95,19 +104,19 @@ static bool stage_fits(const IntegrateArgs &a, uint32_t threads) {
 int launch_integrate(const IntegrateArgs &a, int V, uint32_t threads, hipStream_t s) {
   KernelTimer t("integrate", s);
   if (V == 8 && stage_fits<8>(a, threads))
-    launch_integrate_v<8, true>(a, threads, integrate_lds_bytes<8>(threads, a.ppb, a.D, true), s);
+    launch_integrate_staged<8>(a, threads, s);
   else if (V == 4 && stage_fits<4>(a, threads))
-    launch_integrate_v<4, true>(a, threads, integrate_lds_bytes<4>(threads, a.ppb, a.D, true), s);
+    launch_integrate_staged<4>(a, threads, s);
   else {
     const size_t shm = integrate_lds_head(threads, a.ppb);
     if (V == 8)
-      launch_integrate_v<8, false>(a, threads, shm, s);
+      launch_integrate_v<8, false, -1>(a, threads, shm, s);
     else if (V == 4)
-      launch_integrate_v<4, false>(a, threads, shm, s);
+      launch_integrate_v<4, false, -1>(a, threads, shm, s);
     else if (V == 2)
-      launch_integrate_v<2, false>(a, threads, shm, s);
+      launch_integrate_v<2, false, -1>(a, threads, shm, s);
     else
-      launch_integrate_v<1, false>(a, threads, shm, s);
+      launch_integrate_v<1, false, -1>(a, threads, shm, s);
   }
   return check_hip(hipGetLastError(), "integrate_kernel");
 }

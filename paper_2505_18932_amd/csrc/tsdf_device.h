@@ -462,6 +462,10 @@ __device__ __forceinline__ void stage_pos(int h, uint32_t lane, uint32_t &p, uin
   j = f % V;
 }
 
+// Loads of the stream, unconditional (a pixel past the image reads the last
+// pixel's run, which nothing stores back): no branch separates them from the
+// view gathers, so the compiler's in-order wait counts need not assume that
+// these long-latency loads precede every gather.
 template <int V>
 __device__ __forceinline__ void stage_load(const float *src, uint32_t pix0, uint32_t npix,
                                            size_t run0, int D, gg_v4f (&r)[VolStage<V>::kIssues]) {
@@ -470,9 +474,8 @@ __device__ __forceinline__ void stage_load(const float *src, uint32_t pix0, uint
   for (int h = 0; h < VolStage<V>::kIssues; ++h) {
     uint32_t p, j;
     stage_pos<V>(h, lane, p, j);
-    r[h] = (gg_v4f){0.0f, 0.0f, 0.0f, 0.0f};
-    if (pix0 + p < npix)
-      r[h] = *(const GG_GLOBAL gg_v4f *)(src + (size_t)(pix0 + p) * D + run0 + 4u * j);
+    const uint32_t pp = min(pix0 + p, npix - 1u);
+    r[h] = *(const GG_GLOBAL gg_v4f *)(src + (size_t)pp * D + run0 + 4u * j);
   }
 }
 
@@ -534,9 +537,12 @@ __host__ __device__ constexpr size_t integrate_lds_bytes(uint32_t threads, uint3
          (stage ? (size_t)8 * D + sizeof(float) * VolStage<V>::kWave * (threads / 64u) : 0);
 }
 
-template <int V, int KC, bool kExact, bool kStage = false>
+// kCarry: 1 the previous volume is carried, 0 it is not, -1 a.carry decides
+// at run time (the staged form takes it at compile time).
+template <int V, int KC, bool kExact, bool kStage = false, int kCarry = -1>
 __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t tile, float *smem) {
   static_assert(!kStage || V == 4 || V == 8, "staged volume stream needs V = 4 or 8");
+  static_assert(!kStage || kCarry >= 0, "the staged form takes the carry at compile time");
   float *sF = smem;
   float *sW = smem + blockDim.x;
   int *sBest = reinterpret_cast<int *>(smem + 2 * blockDim.x);
@@ -601,28 +607,33 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   gg_v4f rF[kStage ? VolStage<V>::kIssues : 1], rW[kStage ? VolStage<V>::kIssues : 1];
   auto load_volume = [&] {
     if constexpr (kStage) {
-      if (a.carry) {
+      // kept at this point of the program: after the first views' gathers,
+      // before the others (the scheduler would otherwise sink them to the end)
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (kCarry == 1) {
         stage_load<V>(a.F_prev, pix0, a.npix, run0, a.D, rF);
         stage_load<V>(a.W_prev, pix0, a.npix, run0, a.D, rW);
       }
+      // unconditional as well (without a mask it reads a bin, unused)
+      const float *mb = a.mask ? a.mask : reinterpret_cast<const float *>(a.bins);
+      mraw = gmem(mb)[a.mask ? min(pix, a.npix - 1u) : 0u];
+      __builtin_amdgcn_sched_barrier(0);
     } else {
       if (carry) {
         loadv<V>(a.F_prev + base, Fp);
         loadv<V>(a.W_prev + base, Wp);
       }
+      if (active && a.mask) mraw = gmem(a.mask)[pix];
     }
-    if (active && a.mask) mraw = gmem(a.mask)[pix];
   };
   float Fn[V], Wn[V];
   if constexpr (kStage) {
-    // every lane takes part in the wavefront's exchanges
+    // every lane fuses (a pixel past the image samples nothing in range and
+    // stores nothing) and takes part in the wavefront's exchanges
     const uint32_t y = fdiv(pix, a.wt_div);
     const uint32_t x = pix - y * a.wt_div.d;
-    if (active)
-      fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
-    else
-      load_volume();
-    if (a.carry) {
+    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
+    if constexpr (kCarry == 1) {
       stage_put_stream<V>(sVol, rF);
       stage_put_stream<V>(sVol + VolStage<V>::kArray, rW);
       wave_lds_sync();
@@ -632,7 +643,7 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
     const float m = a.mask ? fmaxf(1.0f - mraw, 0.0f) : 1.0f;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const float wp = a.carry ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
+      const float wp = (kCarry == 1) ? fminf((a.decay * Wp[v]) * m, a.cap) : 0.0f;
       const float wn = wp + Wo[v];
       Fn[v] = (active && wn > 0.0f) ? fmaf(wp, Fp[v], S[v]) / wn : 0.0f;
       Wn[v] = active ? wn : 0.0f;

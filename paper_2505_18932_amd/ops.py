@@ -165,10 +165,11 @@ def splat_views(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *, tap
 
 
 def splat_views_ewa(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *,
-                    lowpass=0.3, out=None, ws=None, stream=None):
+                    lowpass=0.3, sort_limit=0, out=None, ws=None, stream=None):
     """Front-to-back compositing of the EWA-projected per-pixel Gaussians of
-    K views into the target (see include/ggeom.h).  Returns dict(rgb (K, 3,
-    Ht, Wt), alpha, depth (K, Ht, Wt))."""
+    K views into the target (see include/ggeom.h; ``sort_limit`` the longest
+    tile list sorted in LDS at once, 64..512, 0 = 512).  Returns dict(rgb
+    (K, 3, Ht, Wt), alpha, depth (K, Ht, Wt))."""
     dev = _device(depth)
     sa, tg, sp = cameras(src), camera(tgt), splat_params(params)
     K = len(sa)
@@ -189,15 +190,26 @@ def splat_views_ewa(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *,
     need = workspace_size(L.GG_OP_SPLAT_EWA, K, sw, sh, tw, th, 2, sp)
     wsb, wsn = _ws(need, dev, ws)
     L.check(L.lib().splat_views_ewa(sa, K, _ptr(depth), _ptr(rgb), C.byref(tg), C.byref(sp),
-                                    float(lowpass), _ptr(orgb), _ptr(oa), _ptr(od), _ptr(wsb),
-                                    wsn, _stream(dev, stream)))
+                                    float(lowpass), int(sort_limit), _ptr(orgb), _ptr(oa), _ptr(od),
+                                    _ptr(wsb), wsn, _stream(dev, stream)))
     return dict(rgb=orgb, alpha=oa, depth=od)
 
 
-def set_ewa_sort_limit(keys: int) -> None:
-    """Longest tile list splat_views_ewa sorts in LDS at once (64..512,
-    0 = default); results do not depend on it."""
-    L.check(L.lib().gg_set_ewa_sort_limit(int(keys)))
+def volume_tuning(t):
+    """A launch shape of the volume kernels, (pixels per workgroup, pixels per
+    wavefront row, bins per thread) with 0 for a default, as the C record (or
+    None: the defaults)."""
+    if t is None:
+        return None
+    if isinstance(t, L.GGVolumeTuning):
+        return t
+    ppb, pw, vec = (int(v) for v in t)
+    return L.GGVolumeTuning(ppb, pw, vec)
+
+
+def _tref(t):
+    v = volume_tuning(t)
+    return None if v is None else C.byref(v)
 
 
 def difference_masks(rgb: torch.Tensor, rgb_prev: torch.Tensor, params=None, *, depth=None,
@@ -271,11 +283,13 @@ def tsdf_view_table(src, depth, params, *, ws, stream=None):
 
 
 def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
-                   mask=None, extract=True, ws=None, stream=None, table_ready=False):
+                   mask=None, extract=True, ws=None, stream=None, table_ready=False,
+                   tuning=None):
     """Fuse K depth maps into the target volume (in place when F is F_prev).
     Returns (F, W, depth, bin) (depth, bin None when extract=False).  With
     ``table_ready`` the view table is the one tsdf_view_table built into
-    ``ws`` (``depth`` then only fixes the shapes)."""
+    ``ws`` (``depth`` then only fixes the shapes).  ``tuning``: the launch
+    shape (volume_tuning), results unchanged."""
     dev = _device(depth)
     sa, tg, tp = cameras(src), camera(tgt), tsdf_params(params)
     K = len(sa)
@@ -305,17 +319,18 @@ def tsdf_integrate(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None,
     if table_ready:
         L.check(L.lib().tsdf_integrate_tabled(sa, K, C.byref(tg), C.byref(tp), _ptr(mask),
                                               _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W),
-                                              _ptr(od), _ptr(ob), _ptr(wsb), wsn,
+                                              _ptr(od), _ptr(ob), _tref(tuning), _ptr(wsb), wsn,
                                               _stream(dev, stream)))
     else:
         L.check(L.lib().tsdf_integrate(sa, K, _ptr(depth), C.byref(tg), C.byref(tp), _ptr(mask),
                                        _ptr(F_prev), _ptr(W_prev), _ptr(F), _ptr(W), _ptr(od),
-                                       _ptr(ob), _ptr(wsb), wsn, _stream(dev, stream)))
+                                       _ptr(ob), _tref(tuning), _ptr(wsb), wsn,
+                                       _stream(dev, stream)))
     return F, W, od, ob
 
 
 def fusion_stream_probe(tgt, params, F_prev, W_prev, F, W, out_depth, out_bin, *, ws=None,
-                        stream=None):
+                        stream=None, tuning=None):
     """The fusion kernel's volume stream alone (no views, no gathers): the
     ceiling of its memory access pattern (see include/ggeom.h)."""
     dev = _device(F_prev)
@@ -329,11 +344,11 @@ def fusion_stream_probe(tgt, params, F_prev, W_prev, F, W, out_depth, out_bin, *
     wsb, wsn = _ws(need, dev, ws)
     L.check(L.lib().gg_fusion_stream_probe(C.byref(tg), C.byref(tp), _ptr(F_prev), _ptr(W_prev),
                                            _ptr(F), _ptr(W), _ptr(out_depth), _ptr(out_bin),
-                                           _ptr(wsb), wsn, _stream(dev, stream)))
+                                           _tref(tuning), _ptr(wsb), wsn, _stream(dev, stream)))
 
 
 def tsdf_integrate_noalloc(src, depth, tgt, params, *, F_prev=None, W_prev=None, F=None, W=None,
-                           mask=None, extract=True, stream=None):
+                           mask=None, extract=True, stream=None, tuning=None):
     """tsdf_integrate through the entry point that takes no workspace and
     allocates nothing (its scratch is the library's static device array).
     Outputs not passed in are created here; the C call itself allocates
@@ -362,7 +377,8 @@ def tsdf_integrate_noalloc(src, depth, tgt, params, *, F_prev=None, W_prev=None,
         ob = torch.empty((th, tw), dtype=torch.int32, device=dev)
     L.check(L.lib().tsdf_integrate_noalloc(sa, K, _ptr(depth), C.byref(tg), C.byref(tp),
                                            _ptr(mask), _ptr(F_prev), _ptr(W_prev), _ptr(F),
-                                           _ptr(W), _ptr(od), _ptr(ob), _stream(dev, stream)))
+                                           _ptr(W), _ptr(od), _ptr(ob), _tref(tuning),
+                                           _stream(dev, stream)))
     return F, W, od, ob
 
 
@@ -429,7 +445,7 @@ def blend_views(rgb, depth, alpha, weights, w_bg, rgb_bg, *, stream=None):
     return orgb, od
 
 
-def tsdf_extract_depth(tgt, params, F, W, *, stream=None):
+def tsdf_extract_depth(tgt, params, F, W, *, stream=None, tuning=None):
     dev = _device(F)
     tg, tp = camera(tgt), tsdf_params(params)
     vol = (tg.height, tg.width, tp.num_bins)
@@ -438,7 +454,7 @@ def tsdf_extract_depth(tgt, params, F, W, *, stream=None):
     od = torch.empty(vol[:2], dtype=torch.float32, device=dev)
     ob = torch.empty(vol[:2], dtype=torch.int32, device=dev)
     L.check(L.lib().tsdf_extract_depth(C.byref(tg), C.byref(tp), _ptr(F), _ptr(W), _ptr(od),
-                                       _ptr(ob), _stream(dev, stream)))
+                                       _ptr(ob), _tref(tuning), _stream(dev, stream)))
     return od, ob
 
 
@@ -523,7 +539,7 @@ class BatchPlan:
     binds these buffers; write new inputs into the same tensors between
     launches."""
 
-    def __init__(self, items, volume_threads=0, blocks_per_cu=0):
+    def __init__(self, items, volume_threads=0, blocks_per_cu=0, bins_per_thread=0):
         self.items = items
         self._keep = []
         arr = (L.GGBatchItem * len(items))()
@@ -578,9 +594,9 @@ class BatchPlan:
                 b.sp_tape = o["tape"].data_ptr()
             self._keep.append(sa)
         self._arr = arr
-        tune = L.GGBatchTuning(int(volume_threads), int(blocks_per_cu))
+        tune = L.GGBatchTuning(int(volume_threads), int(blocks_per_cu), int(bins_per_thread))
         h = C.c_void_p()
-        L.check(L.lib().gg_batch_create(arr, len(items), C.byref(tune), C.byref(h)))
+        L.check(L.lib().gg_batch_plan(arr, len(items), C.byref(tune), C.byref(h)))
         self._h = h
         self.device_bytes = int(L.lib().gg_batch_device_bytes(h))
 
@@ -591,7 +607,7 @@ class BatchPlan:
     def close(self):
         if self._h:
             torch.cuda.synchronize()
-            L.lib().gg_batch_destroy(self._h)
+            L.lib().gg_batch_free(self._h)
             self._h = None
 
     def __del__(self):

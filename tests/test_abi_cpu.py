@@ -172,10 +172,10 @@ def test_tsdf_rejects_invalid_arguments():
     lib = L.lib()
     src, tgt = _cams()
 
-    def call(prm, Fp=None, Wp=None, od=None, ob=None, ws=FAKE, nws=1 << 40, F=FAKE):
+    def call(prm, Fp=None, Wp=None, od=None, ob=None, ws=FAKE, nws=1 << 40, F=FAKE, tun=None):
         tp = ops.tsdf_params(prm)
         return lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, Fp, Wp, F, FAKE,
-                                  od, ob, ws, nws, None)
+                                  od, ob, None if tun is None else C.byref(tun), ws, nws, None)
 
     good = scenes.tsdf_params(num_bins=64)
     assert call(scenes.tsdf_params(num_bins=1)) == L.GG_ERR_INVALID
@@ -193,8 +193,44 @@ def test_tsdf_rejects_invalid_arguments():
     assert call(good, nws=100) == L.GG_ERR_WORKSPACE
     assert call(good, ws=C.c_void_p((1 << 20) + 8)) == L.GG_ERR_WORKSPACE  # misaligned ws
     tp = ops.tsdf_params(scenes.tsdf_params(num_bins=1))
-    assert lib.tsdf_extract_depth(C.byref(tgt), C.byref(tp), FAKE, FAKE, FAKE, FAKE, None) == \
-        L.GG_ERR_INVALID
+    assert lib.tsdf_extract_depth(C.byref(tgt), C.byref(tp), FAKE, FAKE, FAKE, FAKE, None,
+                                  None) == L.GG_ERR_INVALID
+
+
+def test_volume_tuning_is_per_call_and_validated():
+    """The launch shape travels with each call (gg_volume_tuning); the
+    library has no process-wide setter for it, and rejects invalid shapes
+    before touching the device."""
+    lib = L.lib()
+    for name in ("gg_set_volume_tile", "gg_set_volume_vector", "gg_set_ewa_sort_limit"):
+        assert not hasattr(lib, name), name
+    src, tgt = _cams()
+    tp = ops.tsdf_params(scenes.tsdf_params(num_bins=64))
+    ws_small = 100  # fails the workspace check after a valid tuning
+    for bad in ((-1, 0, 0), (1025, 0, 0), (8, 65, 0), (0, -1, 0), (0, 0, 3), (0, 0, 16),
+                (0, 0, -1)):
+        t = ops.volume_tuning(bad)
+        rc = lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, None, None, FAKE,
+                                FAKE, None, None, C.byref(t), FAKE, 1 << 40, None)
+        assert rc == L.GG_ERR_INVALID, bad
+        assert lib.tsdf_extract_depth(C.byref(tgt), C.byref(tp), FAKE, FAKE, FAKE, FAKE,
+                                      C.byref(t), None) == L.GG_ERR_INVALID, bad
+    for ok in ((0, 0, 0), (16, 16, 8), (32, 8, 4), (1024, 64, 1), (3, 1, 2)):
+        t = ops.volume_tuning(ok)
+        rc = lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, None, None, FAKE,
+                                FAKE, None, None, C.byref(t), FAKE, ws_small, None)
+        assert rc == L.GG_ERR_WORKSPACE, ok
+
+
+def test_batch_entry_points_carry_the_survey_names():
+    lib = L.lib()
+    for name in ("gg_batch_plan", "gg_batch_launch", "gg_batch_free", "gg_batch_device_bytes"):
+        assert hasattr(lib, name), name
+    for name in ("gg_batch_create", "gg_batch_destroy"):
+        assert not hasattr(lib, name), name
+    tune = L.GGBatchTuning(256, 4, 3)  # bins_per_thread 3: invalid
+    h = C.c_void_p()
+    assert lib.gg_batch_plan(None, 0, C.byref(tune), C.byref(h)) == L.GG_ERR_INVALID
 
 
 def test_two_call_fusion_rejects_invalid_arguments():
@@ -209,7 +245,8 @@ def test_two_call_fusion_rejects_invalid_arguments():
         L.GG_ERR_INVALID
     assert lib.tsdf_view_table(src, 2, FAKE, C.byref(good), FAKE, 100, None) == L.GG_ERR_WORKSPACE
     call = lambda F=FAKE, Fp=None, nws=1 << 40: lib.tsdf_integrate_tabled(
-        src, 2, C.byref(tgt), C.byref(good), None, Fp, None, F, FAKE, None, None, FAKE, nws, None)
+        src, 2, C.byref(tgt), C.byref(good), None, Fp, None, F, FAKE, None, None, None, FAKE, nws,
+        None)
     assert call(F=None) == L.GG_ERR_INVALID
     assert call(Fp=FAKE) == L.GG_ERR_INVALID
     assert call(nws=100) == L.GG_ERR_WORKSPACE
@@ -220,7 +257,7 @@ def test_ewa_splat_rejects_invalid_arguments():
     src, tgt = _cams()
     sp = ops.splat_params(scenes.splat_params())
     args = lambda K, d=FAKE, prm=sp, lp=0.3, ws=FAKE, nws=1 << 40, o=FAKE: (
-        src, K, d, FAKE, C.byref(tgt), C.byref(prm), lp, o, FAKE, FAKE, ws, nws, None)
+        src, K, d, FAKE, C.byref(tgt), C.byref(prm), lp, 0, o, FAKE, FAKE, ws, nws, None)
     assert lib.splat_views_ewa(*args(0)) == L.GG_ERR_INVALID
     rc, msg = _err(lib.splat_views_ewa(*args(2, d=None)))
     assert rc == L.GG_ERR_INVALID and "NULL" in msg
@@ -237,20 +274,18 @@ def test_ewa_splat_rejects_invalid_arguments():
     assert rc == L.GG_ERR_WORKSPACE
 
 
-def test_launch_shape_setters_validate():
+def test_ewa_sort_limit_is_validated():
     lib = L.lib()
+    src, tgt = _cams()
+    sp = ops.splat_params(scenes.splat_params())
     for bad in (-1, 1, 63, 513, 1024):
-        assert lib.gg_set_ewa_sort_limit(bad) == L.GG_ERR_INVALID
+        rc = lib.splat_views_ewa(src, 2, FAKE, FAKE, C.byref(tgt), C.byref(sp), 0.3, bad, FAKE, FAKE,
+                                 FAKE, FAKE, 1 << 40, None)
+        assert rc == L.GG_ERR_INVALID, bad
     for ok in (64, 100, 512, 0):
-        assert lib.gg_set_ewa_sort_limit(ok) == L.GG_OK
-    for bad in (-1, 3, 5, 16):
-        assert lib.gg_set_volume_vector(bad) == L.GG_ERR_INVALID
-    for ok in (0, 1, 2, 4, 8, 0):
-        assert lib.gg_set_volume_vector(ok) == L.GG_OK
-    assert lib.gg_set_volume_tile(-1, 0) == L.GG_ERR_INVALID
-    assert lib.gg_set_volume_tile(1025, 0) == L.GG_ERR_INVALID
-    assert lib.gg_set_volume_tile(8, 65) == L.GG_ERR_INVALID
-    assert lib.gg_set_volume_tile(0, 0) == L.GG_OK
+        rc = lib.splat_views_ewa(src, 2, FAKE, FAKE, C.byref(tgt), C.byref(sp), 0.3, ok, FAKE, FAKE,
+                                 FAKE, FAKE, 16, None)
+        assert rc == L.GG_ERR_WORKSPACE, ok
 
 
 def test_workspace_sizes():
@@ -330,6 +365,6 @@ def test_noalloc_rejects_a_workspace_beyond_its_static_scratch():
     need = ops.workspace_size(3, 8, 1920, 1080, 1920, 1080, 64)
     assert need > 64 << 20
     rc = lib.tsdf_integrate_noalloc(src, 8, FAKE, C.byref(tgt), C.byref(tp), None, None, None,
-                                    FAKE, FAKE, FAKE, FAKE, None)
+                                    FAKE, FAKE, FAKE, FAKE, None, None)
     assert rc == L.GG_ERR_UNSUPPORTED
     assert "static scratch" in lib.gg_last_error().decode()

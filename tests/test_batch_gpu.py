@@ -113,16 +113,11 @@ def test_batch_bins_per_thread(vec):
     plain results, which do not depend on that choice either."""
     items = _items(n=8)
     refs = [_plain(it) for it in items]
-    lib = gg._lib.lib()
-    gg._lib.check(lib.gg_set_volume_vector(vec))
-    try:
-        plan = gg.BatchPlan(items)
-        plan.launch()
-        torch.cuda.synchronize()
-        _check(items, refs)
-        plan.close()
-    finally:
-        lib.gg_set_volume_vector(0)
+    plan = gg.BatchPlan(items, bins_per_thread=vec)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check(items, refs)
+    plan.close()
 
 
 @pytest.mark.parametrize("seed", range(4))

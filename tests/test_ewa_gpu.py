@@ -20,10 +20,10 @@ def bits(a):
     return np.ascontiguousarray(a, np.float32).view(np.uint32)
 
 
-def run(c, lowpass=0.3):
+def run(c, lowpass=0.3, sort_limit=0):
     o = gg.splat_views_ewa(c["src"], torch.from_numpy(np.ascontiguousarray(c["depth"])).to(DEV),
                            torch.from_numpy(np.ascontiguousarray(c["rgb"])).to(DEV), c["tgt"],
-                           c["splat"], lowpass=lowpass)
+                           c["splat"], lowpass=lowpass, sort_limit=sort_limit)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in o.items()}
 
@@ -75,11 +75,7 @@ def test_long_lists_take_the_merge_path():
 def test_sort_limit_invariance(limit):
     cs = [scenes.config1(), _zoomed_out(4, seed=1)]
     ref = [run(c) for c in cs]
-    gg.set_ewa_sort_limit(limit)
-    try:
-        got = [run(c) for c in cs]
-    finally:
-        gg.set_ewa_sort_limit(0)
+    got = [run(c, sort_limit=limit) for c in cs]
     for a, b in zip(ref, got):
         for key in ("rgb", "alpha", "depth"):
             assert np.array_equal(bits(a[key]), bits(b[key])), key

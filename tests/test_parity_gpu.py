@@ -271,21 +271,16 @@ def test_volume_tile_shape_does_not_change_results():
     depth, _ = to_dev(c)
     base = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
     F, W = base[0], base[1]
-    try:
-        for vec in (1, 2, 4, 8):
-            gg._lib.check(gg._lib.lib().gg_set_volume_vector(vec))
-            for ppb in ((0, 0), (1, 1), (3, 1), (8, 1), (8, 8), (40, 8), (32, 32)):
-                gg._lib.check(gg._lib.lib().gg_set_volume_tile(*ppb))
-                v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
-                e = gg.tsdf_extract_depth(c["tgt"], c["tsdf"], F, W)
-                torch.cuda.synchronize()
-                for a, b in zip(v, base):
-                    assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (vec, ppb)
-                for a, b in zip(e, base[2:]):
-                    assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (vec, ppb)
-    finally:
-        gg._lib.lib().gg_set_volume_tile(0, 0)
-        gg._lib.lib().gg_set_volume_vector(0)
+    for vec in (1, 2, 4, 8):
+        for ppb in ((0, 0), (1, 1), (3, 1), (8, 1), (8, 8), (16, 16), (40, 8), (32, 32)):
+            tun = (ppb[0], ppb[1], vec)
+            v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"], tuning=tun)
+            e = gg.tsdf_extract_depth(c["tgt"], c["tsdf"], F, W, tuning=tun)
+            torch.cuda.synchronize()
+            for a, b in zip(v, base):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), tun
+            for a, b in zip(e, base[2:]):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), tun
 
 
 # ---------------------------------------------------------------------------
@@ -435,7 +430,6 @@ def test_full_video_in_the_benchmark_launch(video_frames):
     two workspaces, two frames with the volume carried in place.  The oracle
     follows 2000 sampled pixel columns through both frames; the second
     frame's splat is compared in full."""
-    from paper_2505_18932_amd import autotune
     c, frames = video_frames
     tp, sp = c["tsdf"], c["splat"]
     K, H, W = frames[0][0].shape
@@ -451,32 +445,29 @@ def test_full_video_in_the_benchmark_launch(video_frames):
     ev_t = [torch.cuda.Event(), torch.cuda.Event()]
     ev_f = [torch.cuda.Event(), torch.cuda.Event()]
     dev_frames = [(torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)) for d, r in frames]
-    autotune.set_plain((16, 16, 8))
-    try:
-        F = Wv = None
-        outs = []
+    tun = (16, 16, 8)
+    F = Wv = None
+    outs = []
+    torch.cuda.synchronize()
+    for i, (d, r) in enumerate(dev_frames):
+        b = i % 2
+        side.wait_event(ev_f[b])
+        gg.tsdf_view_table(c["src"], d, tp, ws=wss[b], stream=side)
+        ev_t[b].record(side)
+        so = gg.splat_views(c["src"], d, r, c["tgt"], sp, ws=ws_s, stream=side)
+        main.wait_event(ev_t[b])
+        if F is None:
+            F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, ws=wss[b],
+                                               table_ready=True, tuning=tun)
+        else:
+            F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, F_prev=F,
+                                               W_prev=Wv, F=F, W=Wv, ws=wss[b],
+                                               table_ready=True, tuning=tun)
+        ev_f[b].record(main)
         torch.cuda.synchronize()
-        for i, (d, r) in enumerate(dev_frames):
-            b = i % 2
-            side.wait_event(ev_f[b])
-            gg.tsdf_view_table(c["src"], d, tp, ws=wss[b], stream=side)
-            ev_t[b].record(side)
-            so = gg.splat_views(c["src"], d, r, c["tgt"], sp, ws=ws_s, stream=side)
-            main.wait_event(ev_t[b])
-            if F is None:
-                F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, ws=wss[b],
-                                                   table_ready=True)
-            else:
-                F, Wv, dep, bb = gg.tsdf_integrate(c["src"], d, c["tgt"], tp, F_prev=F,
-                                                   W_prev=Wv, F=F, W=Wv, ws=wss[b],
-                                                   table_ready=True)
-            ev_f[b].record(main)
-            torch.cuda.synchronize()
-            outs.append((F.reshape(-1, tp["num_bins"])[pix].cpu().numpy(),
-                         Wv.reshape(-1, tp["num_bins"])[pix].cpu().numpy(),
-                         dep.reshape(-1)[pix].cpu().numpy(), bb.reshape(-1)[pix].cpu().numpy()))
-    finally:
-        autotune.set_plain((0, 0, 0))
+        outs.append((F.reshape(-1, tp["num_bins"])[pix].cpu().numpy(),
+                     Wv.reshape(-1, tp["num_bins"])[pix].cpu().numpy(),
+                     dep.reshape(-1)[pix].cpu().numpy(), bb.reshape(-1)[pix].cpu().numpy()))
     ref = None
     for (d, r), (Fg, Wg, dg, bg) in zip(frames, outs):
         Fr_prev, Wr_prev = ref if ref is not None else (None, None)
@@ -604,7 +595,6 @@ def test_fusion_stream_probe(vec):
     W = min(decay W_prev, cap), F = (W F_prev) / W (0 where W is 0), in that
     FP32 order; its fused extraction equals tsdf_extract_depth on the
     result."""
-    from paper_2505_18932_amd import autotune
     c = small(w=61, h=35, k=3, bins=32)
     depth, _ = to_dev(c)
     tp = c["tsdf"]
@@ -612,12 +602,8 @@ def test_fusion_stream_probe(vec):
     Fp, Wp = F.cpu().numpy(), W.cpu().numpy()
     od = torch.empty(F.shape[:2], device=DEV)
     ob = torch.empty(F.shape[:2], dtype=torch.int32, device=DEV)
-    autotune.set_plain((16, 16, vec))
-    try:
-        gg.ops.fusion_stream_probe(c["tgt"], tp, F, W, F, W, od, ob)
-        torch.cuda.synchronize()
-    finally:
-        autotune.set_plain((0, 0, 0))
+    gg.ops.fusion_stream_probe(c["tgt"], tp, F, W, F, W, od, ob, tuning=(16, 16, vec))
+    torch.cuda.synchronize()
     wn = np.minimum(np.float32(tp["decay"]) * Wp, np.float32(tp["weight_cap"]))
     with np.errstate(invalid="ignore", divide="ignore"):
         fn = np.where(wn > 0, (wn * Fp) / wn, np.float32(0)).astype(np.float32)
