@@ -539,6 +539,35 @@ class RingSequence:
         return np.stack(depth), np.stack(rgb)
 
 
+def _coarse_job(args):
+    cam, prims, f, seeds, noise, holes = args
+    lo = Camera(cam.fx / f, cam.fy / f, cam.cx / f, cam.cy / f, cam.R, cam.t,
+                -(-cam.width // f), -(-cam.height // f))
+    d, c = render(lo, prims, None)
+    ys = np.arange(cam.height) // f
+    xs = np.arange(cam.width) // f
+    return to_inputs(d[ys][:, xs], c[ys][:, xs], np.random.default_rng(seeds), noise, holes)
+
+
+def coarse_frame(seq, t, factor=2, procs=1):
+    """Frame t of ``seq`` ray-cast at 1/factor resolution (the same cameras
+    with scaled intrinsics) and repeated to the full maps, then rounded to
+    inputs with the sequence's noise and holes per full-resolution pixel
+    (seeded per view): full-size depth and colour with the scene's structure
+    and motion, cheaper to generate on the host (for long sequences at large
+    sizes)."""
+    prims = seq.scene.prims(t)
+    jobs = [(cam, prims, factor, [seq.cfg_id, seq.seed, t, factor, v], seq.noise, seq.holes)
+            for v, cam in enumerate(seq.src)]
+    if procs <= 1:
+        views = [_coarse_job(j) for j in jobs]
+    else:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
+            views = pool.map(_coarse_job, jobs)
+    return np.stack([d for d, _ in views]), np.stack([c for _, c in views])
+
+
 def config2(seed=0):
     """Video: K=4 of a 16-camera ring (radius 1 m, aimed inward) at
     1280x720, target between two ring cameras; 5 spheres moving
