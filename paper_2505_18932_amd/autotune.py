@@ -10,7 +10,7 @@ next to this module (``tuning_cache.json``):
   passes with each call (``tuning=`` of the volume calls, the C ABI's
   ``gg_volume_tuning``); nothing is set process-wide;
 * batched path: (threads per fusion workgroup, persistent workgroups per
-  compute unit) for a batch signature.
+  compute unit, bins per thread) for a batch signature.
 """
 from __future__ import annotations
 
@@ -28,8 +28,11 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 # (pixels per workgroup, pixels per wavefront row, bins per thread); 0 = default
 PLAIN_CANDIDATES = [(0, 0, 4), (8, 8, 4), (16, 8, 4), (16, 16, 4), (32, 8, 4), (32, 16, 4),
                     (0, 0, 8), (16, 16, 8), (32, 16, 8), (32, 32, 8), (64, 16, 8), (64, 32, 8)]
-BATCH_CANDIDATES = [(128, 4), (256, 2), (256, 4), (256, 8), (512, 2), (512, 4), (1024, 1),
-                    (1024, 2)]
+# (threads per fusion workgroup, persistent workgroups per compute unit, bins
+# per thread); 0 = default
+BATCH_CANDIDATES = [(256, 4, 4), (256, 8, 4), (512, 2, 4), (512, 4, 4), (1024, 2, 4),
+                    (256, 4, 8), (256, 8, 8), (512, 2, 8), (512, 4, 8), (1024, 1, 8),
+                    (1024, 2, 8)]
 
 
 def arch(device=None) -> str:
@@ -119,11 +122,11 @@ def batch_signature(items):
     sig = sorted((len(it["src"]), ops.tsdf_params(it["tsdf"]).num_bins,
                   ops.camera(it["tgt"]).width, ops.camera(it["tgt"]).height,
                   it.get("rgb") is not None) for it in items)
-    return "batch/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
+    return "batch-v/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
 
 
 def tune_batch(items, reps=3, use_cache=True):
-    """Best (volume_threads, blocks_per_cu) for this batch (one plan per
+    """Best (volume_threads, blocks_per_cu, bins_per_thread) for this batch (one plan per
     candidate over the same buffers, each closed before the next).
     Returns (tuning, {candidate: ms})."""
     key = batch_signature(items)
@@ -134,7 +137,7 @@ def tune_batch(items, reps=3, use_cache=True):
     times = {}
     for cand in BATCH_CANDIDATES:
         plan = ops.BatchPlan(items, *cand)
-        times["%d,%d" % cand] = _time(plan.launch, reps)
+        times[",".join(map(str, cand))] = _time(plan.launch, reps)
         plan.close()
     best = min(times, key=times.get)
     tun = tuple(int(v) for v in best.split(","))

@@ -1231,6 +1231,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
   // host descriptors, work lists and the device-memory layout
   std::vector<BatchItem> h(n);
   std::vector<WorkItem> conf, bin, raster, integ[kIntegClasses];
+  size_t integ_shm[kIntegClasses] = {};
   std::vector<uint32_t> splat_items;
   std::vector<VolumeShape> shapes(n);
   std::vector<SplatLayout> sl(n);
@@ -1248,7 +1249,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     vs.ppb = std::max(1u, (uint32_t)threads / vs.cpp);
     vs.threads = vs.ppb * vs.cpp;
     vs.nblocks = (npix + vs.ppb - 1) / vs.ppb;
-    vs.pw_shift = pick_pw_shift(vs.ppb, 8);
+    vs.pw_shift = pick_pw_shift(vs.ppb, 16);
     o_table[i] = off;
     off += up256(8 * (size_t)sw * sh * K);
     o_bins[i] = off;
@@ -1282,7 +1283,19 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     IntegrateArgs probe{};  // only for the view count class and the reciprocal's range
     make_integrate_args(probe, it.src, it.K, it.tgt, it.tsdf, vs, nullptr, nullptr, nullptr,
                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-    const int g = integ_class(vs.V, K, probe.exact_only != 0);
+    // the volume stream through LDS where the plain call would take it too
+    // and the item's tile fills the plan's workgroup exactly
+    size_t stage_bytes = 0;
+    if (vs.threads == (uint32_t)threads && vs.pw_shift == 4 && vs.cpp % 4 == 0) {
+      if (vs.V == 8) stage_bytes = integrate_lds_bytes<8>(vs.threads, vs.ppb, D, true);
+      if (vs.V == 4) stage_bytes = integrate_lds_bytes<4>(vs.threads, vs.ppb, D, true);
+      if (stage_bytes > 65536) stage_bytes = 0;
+    }
+    const int mode = stage_bytes ? (it.F_prev ? 2 : 1) : 0;
+    const int g = integ_class(vs.V, K, probe.exact_only != 0, mode);
+    // (the workgroup is the plan's: sF and sW hold one float per thread of it)
+    integ_shm[g] = std::max(integ_shm[g], stage_bytes ? stage_bytes
+                                                      : integrate_lds_head(threads, vs.ppb));
     for (uint32_t t = 0; t < vs.nblocks; ++t)
       integ[g].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
   }
@@ -1344,6 +1357,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
   for (int g = 0; g < kIntegClasses; ++g) {
     P.d_integ[g] = (WorkItem *)(dv + o_integ[g]);
     P.n_integ[g] = (uint32_t)integ[g].size();
+    P.integ_shm[g] = integ_shm[g];
   }
   P.d_splat_items = (uint32_t *)(dv + o_sitems);
   P.n_splat_items = (uint32_t)splat_items.size();

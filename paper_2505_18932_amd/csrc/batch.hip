@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__re
 // Fusion: one workgroup tile of one item per work entry, every entry of a
 // launch in the same specialisation as the plain kernel (so the same code
 // and register budget).
-template <int V, int KC, bool kExact>
+template <int V, int KC, bool kExact, int kMode>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
                                                                uint32_t n, uint32_t chunk,
@@ -142,16 +142,24 @@ __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *
   extern __shared__ float smem[];
   for_each_entry(n, chunk, ctr, [&](uint32_t w) {
     const WorkItem wi = work[w];
-    integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
+    if constexpr (kMode == 0)
+      integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
+    else
+      integrate_tile<V, KC, kExact, true, kMode == 2 ? 1 : 0>(items[wi.item].integ,
+                                                               work_tile(wi), smem);
   });
 }
 
 template <int C>
 static void launch_integ_class(const BatchPlan &P, uint32_t n, int grid, uint32_t chunk,
                                size_t shm, hipStream_t s) {
-  hipLaunchKernelGGL((batch_integrate_kernel<vec_of_class(C), views_of_class(C), exact_class(C)>),
-                     dim3(grid), dim3(P.integ_threads), shm, s, P.d_items, P.d_integ[C], n, chunk,
-                     P.d_ctr + (kLightCounters + C) * kXcds);
+  // the LDS form exists for 8 and 4 bins per thread only (the host assigns
+  // no items to the other combinations)
+  if constexpr (mode_of_class(C) == 0 || vec_of_class(C) >= 4)
+    hipLaunchKernelGGL((batch_integrate_kernel<vec_of_class(C), views_of_class(C), exact_class(C),
+                                               mode_of_class(C)>),
+                       dim3(grid), dim3(P.integ_threads), shm, s, P.d_items, P.d_integ[C], n,
+                       chunk, P.d_ctr + (kLightCounters + C) * kXcds);
 }
 
 template <int C>
@@ -232,12 +240,11 @@ int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
     hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
                        chunk_of(P.n_conf, g), P.d_ctr + 0 * kXcds);
   }
-  const size_t shm = sizeof(float) * 2 * P.integ_threads + sizeof(int) * P.integ_threads;
   for (int c = 0; c < kIntegClasses; ++c) {
     const uint32_t n = P.n_integ[c];
     if (!n) continue;
     const int g = persistent_grid(n, per, cus);
-    dispatch_integ_class<0>(c, P, n, g, chunk_of(n, g), shm, s);
+    dispatch_integ_class<0>(c, P, n, g, chunk_of(n, g), P.integ_shm[c], s);
   }
   if (branch)
     if (int rc = check_hip(hipStreamWaitEvent(s, join, 0), "batch join")) return rc;

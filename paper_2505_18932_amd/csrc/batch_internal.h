@@ -11,21 +11,33 @@ constexpr int kConfTileFloats = kConfLH * kConfLW;
 // Fusion work is split into classes that each run one specialisation of the
 // plain kernel's device function: bins per thread (8, 4, 2, 1) times view
 // count (1, 2, 3, 4, 6, 8 compile-time, other counts at run time, or every
-// sample by IEEE division).
-constexpr int kVecClasses = 4, kViewClasses = 8;
-constexpr int kIntegClasses = kVecClasses * kViewClasses;
+// sample by IEEE division) times the volume stream's form (direct with the
+// carry decided at run time; through LDS without or with a carry, for 8 or
+// 4 bins per thread).
+constexpr int kVecClasses = 4, kViewClasses = 8, kModeClasses = 3;
+constexpr int kIntegClasses = kVecClasses * kViewClasses * kModeClasses;
 constexpr int kLightCounters = 4;  // confidence, bin count, bin fill, raster
 constexpr int kXcds = 8;           // each phase keeps one counter per XCD
 constexpr int kBatchCounters = (kLightCounters + kIntegClasses) * kXcds;
 
-__host__ __device__ constexpr int vec_of_class(int c) { return 8 >> (c / kViewClasses); }
-__host__ __device__ constexpr int views_of_class(int c) {
-  return (c % kViewClasses) < 4 ? (c % kViewClasses) + 1
-                                : ((c % kViewClasses) == 4 ? 6 : ((c % kViewClasses) == 5 ? 8 : 0));
+__host__ __device__ constexpr int vec_of_class(int c) {
+  return 8 >> ((c / kModeClasses) / kViewClasses);
 }
-__host__ __device__ constexpr bool exact_class(int c) { return c % kViewClasses == 7; }
+__host__ __device__ constexpr int views_of_class(int c) {
+  return ((c / kModeClasses) % kViewClasses) < 4
+             ? ((c / kModeClasses) % kViewClasses) + 1
+             : (((c / kModeClasses) % kViewClasses) == 4
+                    ? 6
+                    : (((c / kModeClasses) % kViewClasses) == 5 ? 8 : 0));
+}
+__host__ __device__ constexpr bool exact_class(int c) {
+  return (c / kModeClasses) % kViewClasses == 7;
+}
+// 0: direct volume stream, carry at run time; 1: through LDS, no carry; 2:
+// through LDS, carried
+__host__ __device__ constexpr int mode_of_class(int c) { return c % kModeClasses; }
 
-inline int integ_class(int V, int K, bool exact_only) {
+inline int integ_class(int V, int K, bool exact_only, int mode) {
   const int vi = V == 8 ? 0 : (V == 4 ? 1 : (V == 2 ? 2 : 3));
   int kc = 6;  // runtime view count
   if (exact_only)
@@ -36,7 +48,7 @@ inline int integ_class(int V, int K, bool exact_only) {
     kc = 4;
   else if (K == 8)
     kc = 5;
-  return vi * kViewClasses + kc;
+  return (vi * kViewClasses + kc) * kModeClasses + mode;
 }
 
 // Everything one item's phases need, in device memory (read with scalar
@@ -74,6 +86,7 @@ struct BatchPlan {
   BatchItem *d_items = nullptr;
   WorkItem *d_conf = nullptr, *d_bin = nullptr, *d_raster = nullptr, *d_integ[kIntegClasses] = {};
   uint32_t n_conf = 0, n_bin = 0, n_raster = 0, n_integ[kIntegClasses] = {};
+  size_t integ_shm[kIntegClasses] = {};  // dynamic LDS of each fusion class (its items' largest)
   uint32_t *d_splat_items = nullptr;
   uint32_t n_splat_items = 0;
   uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
