@@ -371,16 +371,21 @@ def batched_speedup(gg, torch, dev, procs, tune=True, tuning=None):
                           tsdf=gg.tsdf_params(scenes.tsdf_params(num_bins=desc["d"], trunc=4.0))))
     voxels = sum(it["tgt"].width * it["tgt"].height * it["tsdf"].num_bins for it in items)
     pixels = sum(it["tgt"].width * it["tgt"].height for it in items)
+    ttimes = {}
     if tuning is None:
-        tuning, ttimes = autotune.tune_batch(items) if tune else ((0, 0), {})
+        tuning, ttimes = autotune.tune_batch(items) if tune else ((0, 0, 0), {})
     plan = gg.BatchPlan(items, *tuning)
     outs = [dict(F=it["F"], W=it["W"]) for it in items]
+    # the plain calls each at the best launch shape of its item's class (K, D, size), tuned as
+    # the main leg's is: the strongest sequence of plain calls to compare with
+    ptiles = [autotune.tune_plain(it["src"], it["depth"], it["tgt"], it["tsdf"], reps=3)[0]
+              if tune else TILE[0] for it in items]
 
     def plain():
-        for it, o in zip(items, outs):
+        for it, o, tl in zip(items, outs, ptiles):
             gg.splat_views(it["src"], it["depth"], it["rgb"], it["tgt"], it["splat"])
             gg.tsdf_integrate(it["src"], it["depth"], it["tgt"], it["tsdf"], F=o["F"], W=o["W"],
-                              tuning=TILE[0])
+                              tuning=tl)
 
     def timed(fn, reps=5):
         fn()
@@ -397,6 +402,8 @@ def batched_speedup(gg, torch, dev, procs, tune=True, tuning=None):
     return {"items": len(items), "target_mpix": round(pixels / 1e6, 3),
             "voxels_g": round(voxels / 1e9, 3), "graph_ms": round(tb, 3), "plain_ms": round(tp, 3),
             "speedup": round(tp / tb, 3), "tuning": list(tuning),
+            "plain_tunings": sorted(set(",".join(map(str, t)) for t in ptiles if t)),
+            "tuning_ms": {k: round(v, 3) for k, v in ttimes.items()},
             "batched_mpix_s": round(pixels / tb / 1e3, 1)}
 
 

@@ -107,11 +107,20 @@ typedef struct gg_mask_params {
  *                     where it divides num_bins and, for 8, where every
  *                     volume argument is 32-byte aligned, else the largest of
  *                     4, 2, 1 dividing num_bins.
+ *   band_width        order in which the fusion visits its workgroup tiles:
+ *                     vertical bands of about this many target pixels
+ *                     across, each walked row by row from the top, so that
+ *                     the view-table lines which neighbouring target rows
+ *                     share are still cached when the next row needs them;
+ *                     0..65536 (0: 256); a band as wide as the target is
+ *                     plain row-major order, which is also taken where the
+ *                     target width is not a multiple of pixels_per_block.
  * Invalid values: GG_ERR_INVALID. */
 typedef struct gg_volume_tuning {
   int32_t pixels_per_block;
   int32_t pixels_per_row;
   int32_t bins_per_thread;
+  int32_t band_width;
 } gg_volume_tuning;
 
 /* Operations for gg_workspace_size(). */
@@ -446,7 +455,9 @@ int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
 /* ---------------------------------------------------------------------------
  * Batched path: many target views of uneven resolution, view count and bin
  * count (each with its own inputs, cameras, parameters, volume and outputs)
- * fused by persistent kernels in one hipGraph launch.  Every output is
+ * fused by kernels over per-phase work lists (persistent ones for the light
+ * phases, one workgroup per tile for the fusion) in one hipGraph launch.
+ * Every output is
  * bitwise identical to the plain calls (splat_views + tsdf_integrate with
  * fused extraction) on the same item, for any tuning.
  * ------------------------------------------------------------------------- */
@@ -470,9 +481,13 @@ typedef struct gg_batch_item {
 
 /* Launch shape chosen by the autotuner (0 = default). */
 typedef struct gg_batch_tuning {
-  int32_t volume_threads;  /* threads per fusion workgroup, multiple of 64 in 64..1024 (256) */
-  int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..64 (4)              */
+  int32_t pixels_per_block; /* target pixels per fusion workgroup, 0..1024 (0: 16; fewer
+                               where the workgroup would exceed 1024 threads)             */
+  int32_t blocks_per_cu;   /* resident workgroups per compute unit of the persistent splat
+                              and confidence phases, 0..64 (0: as many as fit)             */
   int32_t bins_per_thread; /* of the fusion, as in gg_volume_tuning (0: default)            */
+  int32_t branches;        /* 0 or 2: the splat phases form a branch of the graph that runs
+                              beside the fusion; 1: every phase in one sequence          */
 } gg_batch_tuning;
 
 typedef struct gg_batch gg_batch;

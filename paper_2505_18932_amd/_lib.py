@@ -58,13 +58,13 @@ class GGBatchItem(C.Structure):
 
 
 class GGBatchTuning(C.Structure):
-    _fields_ = [("volume_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("bins_per_thread", C.c_int32)]
+    _fields_ = [("pixels_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("bins_per_thread", C.c_int32), ("branches", C.c_int32)]
 
 
 class GGVolumeTuning(C.Structure):
     _fields_ = [("pixels_per_block", C.c_int32), ("pixels_per_row", C.c_int32),
-                ("bins_per_thread", C.c_int32)]
+                ("bins_per_thread", C.c_int32), ("band_width", C.c_int32)]
 
 
 P = C.c_void_p

@@ -6,11 +6,13 @@ caches the winner per GPU architecture and workload class in a JSON file
 next to this module (``tuning_cache.json``):
 
 * plain path: bins per thread, pixels per workgroup and per wavefront row of
-  the fusion for a (K, D, width, height) class: a launch shape the caller
+  the fusion and the band width of its tile order for a (K, D, width, height)
+  class: a launch shape the caller
   passes with each call (``tuning=`` of the volume calls, the C ABI's
   ``gg_volume_tuning``); nothing is set process-wide;
-* batched path: (threads per fusion workgroup, persistent workgroups per
-  compute unit, bins per thread) for a batch signature.
+* batched path: (pixels per fusion workgroup, resident workgroups per
+  compute unit of the persistent light phases, bins per thread, graph
+  branches) for a batch signature.
 """
 from __future__ import annotations
 
@@ -25,14 +27,17 @@ from . import ops
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
-# (pixels per workgroup, pixels per wavefront row, bins per thread); 0 = default
-PLAIN_CANDIDATES = [(0, 0, 4), (8, 8, 4), (16, 8, 4), (16, 16, 4), (32, 8, 4), (32, 16, 4),
-                    (0, 0, 8), (16, 16, 8), (32, 16, 8), (32, 32, 8), (64, 16, 8), (64, 32, 8)]
-# (threads per fusion workgroup, persistent workgroups per compute unit, bins
-# per thread); 0 = default
-BATCH_CANDIDATES = [(256, 4, 4), (256, 8, 4), (512, 2, 4), (512, 4, 4), (1024, 2, 4),
-                    (256, 4, 8), (256, 8, 8), (512, 2, 8), (512, 4, 8), (1024, 1, 8),
-                    (1024, 2, 8)]
+# (pixels per workgroup, pixels per wavefront row, bins per thread, band width of the tile
+# order in pixels); 0 = default
+PLAIN_CANDIDATES = [(0, 0, 4, 0), (8, 8, 4, 0), (16, 8, 4, 0), (16, 16, 4, 0), (32, 8, 4, 0),
+                    (32, 16, 4, 0), (0, 0, 8, 0), (16, 16, 8, 0), (32, 16, 8, 0), (32, 32, 8, 0),
+                    (64, 16, 8, 0), (64, 32, 8, 0), (16, 16, 8, 128), (16, 16, 8, 512),
+                    (16, 16, 8, 65536), (32, 16, 8, 128)]
+# (target pixels per fusion workgroup, resident workgroups per compute unit of
+# the persistent splat and confidence phases, bins per thread, graph branches);
+# 0 = default
+BATCH_CANDIDATES = [(16, 0, 8, 2), (16, 0, 8, 1), (32, 0, 8, 2), (32, 0, 8, 1), (16, 2, 8, 2),
+                    (64, 0, 8, 2), (16, 0, 4, 2), (16, 0, 4, 1), (32, 0, 4, 2)]
 
 
 def arch(device=None) -> str:
@@ -70,11 +75,11 @@ def _time(fn, reps=5, warm=2):
 
 
 def plain_key(K, D, width, height):
-    return f"plain-v/K{K}/D{D}/{width}x{height}"
+    return f"plain-b/K{K}/D{D}/{width}x{height}"
 
 
 def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
-    """Best (pixels per workgroup, pixels per row, bins per thread) of
+    """Best (pixels per workgroup, pixels per row, bins per thread, band width) of
     tsdf_integrate for this class; returns (best, {candidate: ms}), best to
     be passed as ``tuning=`` to the volume calls."""
     tg, tp = ops.camera(tgt), ops.tsdf_params(params)
@@ -86,7 +91,7 @@ def tune_plain(src, depth, tgt, params, reps=5, use_cache=True):
     F, W, _, _ = ops.tsdf_integrate(src, depth, tgt, params)
     times = {}
     for cand in PLAIN_CANDIDATES:
-        times["%d,%d,%d" % cand] = _time(lambda: ops.tsdf_integrate(
+        times[",".join(map(str, cand))] = _time(lambda: ops.tsdf_integrate(
             src, depth, tgt, params, F_prev=F, W_prev=W, F=F, W=W, tuning=cand), reps)
     best = tuple(int(v) for v in min(times, key=times.get).split(","))
     cache.setdefault(a, {})[key] = {"best": list(best), "times": times, "when": time.time()}
@@ -113,7 +118,7 @@ def tune_plain_step(step, first, reps=8, warm=2):
             step(i, tuning=cand)
             i += 1
         torch.cuda.synchronize()
-        times["%d,%d,%d" % cand] = (time.perf_counter() - t0) * 1e3 / reps
+        times[",".join(map(str, cand))] = (time.perf_counter() - t0) * 1e3 / reps
     best = tuple(int(v) for v in min(times, key=times.get).split(","))
     return best, times, i
 
@@ -122,11 +127,11 @@ def batch_signature(items):
     sig = sorted((len(it["src"]), ops.tsdf_params(it["tsdf"]).num_bins,
                   ops.camera(it["tgt"]).width, ops.camera(it["tgt"]).height,
                   it.get("rgb") is not None) for it in items)
-    return "batch-v/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
+    return "batch-p/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
 
 
 def tune_batch(items, reps=3, use_cache=True):
-    """Best (volume_threads, blocks_per_cu, bins_per_thread) for this batch (one plan per
+    """Best (pixels_per_block, blocks_per_cu, bins_per_thread, branches) for this batch (one plan per
     candidate over the same buffers, each closed before the next).
     Returns (tuning, {candidate: ms})."""
     key = batch_signature(items)

@@ -323,13 +323,33 @@ static int check_tuning(const gg_volume_tuning *t, const char *what) {
   const int v = t->bins_per_thread;
   if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)
     return fail(GG_ERR_INVALID, "%s: bins_per_thread %d not in {0, 1, 2, 4, 8}", what, v);
+  if (t->band_width < 0 || t->band_width > 65536)
+    return fail(GG_ERR_INVALID, "%s: band_width %d outside 0..65536", what, t->band_width);
   return GG_OK;
 }
 
 struct VolumeShape {
   int V;
   uint32_t cpp, ppb, threads, nblocks, pw_shift;
+  uint32_t band_px;  // fusion tile order: band width in target pixels
 };
+
+constexpr uint32_t kDefaultBandPixels = 256;
+
+// The fusion's tile order (IntegrateArgs::band_*) for a target of width x
+// height pixels in tiles of ppb pixels: bands of band_px pixels across where
+// whole tiles make up each row, else row-major.
+static void set_band_order(IntegrateArgs &a, int width, int height, uint32_t ppb,
+                           uint32_t band_px) {
+  a.band_T = a.band_B = a.band_H = 0;
+  if ((uint32_t)width % ppb != 0) return;
+  const uint32_t T = (uint32_t)width / ppb;
+  const uint32_t B = std::max(1u, band_px / ppb);
+  if (B >= T) return;
+  a.band_T = T;
+  a.band_B = B;
+  a.band_H = (uint32_t)height;
+}
 
 // Largest power of two <= cap (and <= 64) dividing ppb, as a shift.
 static uint32_t pick_pw_shift(uint32_t ppb, int cap) {
@@ -360,6 +380,7 @@ static int volume_shape(int D, uint32_t npix, VolumeShape &s, const char *what,
   s.threads = ppb * s.cpp;
   s.nblocks = (npix + ppb - 1) / ppb;
   s.pw_shift = pick_pw_shift(ppb, pw_t > 0 ? pw_t : 16);
+  s.band_px = (tun && tun->band_width > 0) ? (uint32_t)tun->band_width : kDefaultBandPixels;
   return GG_OK;
 }
 
@@ -726,6 +747,7 @@ static void make_integrate_args(IntegrateArgs &a, const gg_camera *src, int32_t 
   a.ppb = vs.ppb;
   a.pw_shift = vs.pw_shift;
   a.nblocks = vs.nblocks;
+  set_band_order(a, tgt.width, tgt.height, vs.ppb, vs.band_px);
   a.decay = prm.decay;
   a.cap = prm.weight_cap;
   a.carry = F_prev != nullptr;
@@ -1169,6 +1191,10 @@ struct gg_batch {
   std::vector<char> keep;  // nothing host-side is needed after creation
 };
 
+// Target pixels per fusion workgroup of a batch item by default (as the plain
+// call's tuned launch shape takes them).
+constexpr uint32_t kBatchPixelsPerBlock = 16;
+
 // Bins per thread of a batch item (as for the plain call with that tuning).
 static int item_vec(const gg_batch_item &it, int vec) {
   const bool a32 = aligned(it.F, 32) && aligned(it.W, 32) &&
@@ -1213,16 +1239,12 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     return fail(GG_ERR_INVALID, "%s: bins_per_thread %d not in {0, 1, 2, 4, 8}", N, vec);
   for (int i = 0; i < n; ++i)
     if (int rc = check_item(items[i], i, vec)) return rc;
-  int threads = (tune && tune->volume_threads) ? tune->volume_threads : 256;
-  int per_cu = (tune && tune->blocks_per_cu) ? tune->blocks_per_cu : 4;
-  if (threads < 64 || threads > 1024 || threads % 64 || per_cu < 1 || per_cu > 64)
-    return fail(GG_ERR_INVALID, "%s: volume_threads in 64..1024 (multiple of 64), "
-                "blocks_per_cu in 1..64", N);
-  for (int i = 0; i < n; ++i) {
-    const int D = items[i].tsdf.num_bins;
-    const int V = item_vec(items[i], vec);
-    while (threads < D / V) threads += 64;
-  }
+  const int ppb_t = tune ? tune->pixels_per_block : 0;
+  const int per_cu = tune ? tune->blocks_per_cu : 0;
+  const int branches = tune ? tune->branches : 0;
+  if (ppb_t < 0 || ppb_t > 1024 || per_cu < 0 || per_cu > 64 || branches < 0 || branches > 2)
+    return fail(GG_ERR_INVALID, "%s: pixels_per_block in 0..1024, blocks_per_cu in 0..64, "
+                "branches in 0..2", N);
   int dev = 0, cus = 256;
   if (int rc = check_hip(hipGetDevice(&dev), N)) return rc;
   if (int rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), N))
@@ -1230,8 +1252,9 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
 
   // host descriptors, work lists and the device-memory layout
   std::vector<BatchItem> h(n);
-  std::vector<WorkItem> conf, bin, raster, integ[kIntegClasses];
-  size_t integ_shm[kIntegClasses] = {};
+  std::vector<WorkItem> conf, bin, raster;
+  std::vector<IntegGroup> groups;              // fusion launches: (class, workgroup size)
+  std::vector<std::vector<WorkItem>> integ;    // their work lists
   std::vector<uint32_t> splat_items;
   std::vector<VolumeShape> shapes(n);
   std::vector<SplatLayout> sl(n);
@@ -1246,10 +1269,13 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     VolumeShape &vs = shapes[i];
     vs.V = item_vec(it, vec);
     vs.cpp = (uint32_t)(D / vs.V);
-    vs.ppb = std::max(1u, (uint32_t)threads / vs.cpp);
+    // pixels per workgroup as the plain call's launch shape would give them
+    vs.ppb = ppb_t > 0 ? (uint32_t)ppb_t : kBatchPixelsPerBlock;
+    while (vs.ppb > 1 && vs.ppb * vs.cpp > 1024) --vs.ppb;
     vs.threads = vs.ppb * vs.cpp;
     vs.nblocks = (npix + vs.ppb - 1) / vs.ppb;
     vs.pw_shift = pick_pw_shift(vs.ppb, 16);
+    vs.band_px = kDefaultBandPixels;
     o_table[i] = off;
     off += up256(8 * (size_t)sw * sh * K);
     o_bins[i] = off;
@@ -1284,28 +1310,38 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     make_integrate_args(probe, it.src, it.K, it.tgt, it.tsdf, vs, nullptr, nullptr, nullptr,
                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     // the volume stream through LDS where the plain call would take it too
-    // and the item's tile fills the plan's workgroup exactly
     size_t stage_bytes = 0;
-    if (vs.threads == (uint32_t)threads && vs.pw_shift == 4 && vs.cpp % 4 == 0) {
+    if (vs.threads % 64 == 0 && vs.pw_shift == 4 && vs.cpp % 4 == 0) {
       if (vs.V == 8) stage_bytes = integrate_lds_bytes<8>(vs.threads, vs.ppb, D, true);
       if (vs.V == 4) stage_bytes = integrate_lds_bytes<4>(vs.threads, vs.ppb, D, true);
       if (stage_bytes > 65536) stage_bytes = 0;
     }
     const int mode = stage_bytes ? (it.F_prev ? 2 : 1) : 0;
-    const int g = integ_class(vs.V, K, probe.exact_only != 0, mode);
-    // (the workgroup is the plan's: sF and sW hold one float per thread of it)
-    integ_shm[g] = std::max(integ_shm[g], stage_bytes ? stage_bytes
-                                                      : integrate_lds_head(threads, vs.ppb));
-    for (uint32_t t = 0; t < vs.nblocks; ++t)
-      integ[g].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
+    const int cls = integ_class(vs.V, K, probe.exact_only != 0, mode);
+    size_t gi = 0;
+    while (gi < groups.size() && !(groups[gi].cls == cls && groups[gi].threads == vs.threads)) ++gi;
+    if (gi == groups.size()) {
+      IntegGroup g;
+      g.cls = cls;
+      g.threads = vs.threads;
+      groups.push_back(g);
+      integ.emplace_back();
+    }
+    groups[gi].shm = std::max(groups[gi].shm,
+                              stage_bytes ? stage_bytes : integrate_lds_head(vs.threads, vs.ppb));
+    // the item's tiles in the plain launch's visiting order (bands)
+    for (uint32_t s = 0; s < vs.nblocks; ++s) {
+      const uint32_t t = band_tile(probe, s);
+      integ[gi].push_back(WorkItem{(uint16_t)i, 0, (uint16_t)(t & 0xffff), (uint16_t)(t >> 16)});
+    }
   }
   const size_t o_counts = off;
   off += up256(4 * (count_words + kBatchCounters));
   auto put = [&](size_t bytes) { const size_t o = off; off += up256(bytes ? bytes : 1); return o; };
   const size_t o_conf = put(sizeof(WorkItem) * conf.size()), o_bin = put(sizeof(WorkItem) * bin.size()),
                o_raster = put(sizeof(WorkItem) * raster.size());
-  size_t o_integ[kIntegClasses];
-  for (int g = 0; g < kIntegClasses; ++g) o_integ[g] = put(sizeof(WorkItem) * integ[g].size());
+  std::vector<size_t> o_integ(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) o_integ[g] = put(sizeof(WorkItem) * integ[g].size());
   const size_t o_sitems = put(4 * splat_items.size());
 
   gg_batch *b = new gg_batch();
@@ -1313,7 +1349,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
   P.n_items = n;
   P.cus = cus;
   P.blocks_per_cu = per_cu;
-  P.integ_threads = (uint32_t)threads;
+  P.branches = branches ? branches : 2;
   P.dev_bytes = off;
   if (int rc = check_hip(hipMalloc(&P.dev, off), N)) {
     delete b;
@@ -1354,10 +1390,10 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
   P.n_bin = (uint32_t)bin.size();
   P.d_raster = (WorkItem *)(dv + o_raster);
   P.n_raster = (uint32_t)raster.size();
-  for (int g = 0; g < kIntegClasses; ++g) {
-    P.d_integ[g] = (WorkItem *)(dv + o_integ[g]);
-    P.n_integ[g] = (uint32_t)integ[g].size();
-    P.integ_shm[g] = integ_shm[g];
+  P.integ = groups;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    P.integ[g].list = (WorkItem *)(dv + o_integ[g]);
+    P.integ[g].n = (uint32_t)integ[g].size();
   }
   P.d_splat_items = (uint32_t *)(dv + o_sitems);
   P.n_splat_items = (uint32_t)splat_items.size();
@@ -1372,7 +1408,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
   cp(o_conf, conf.data(), sizeof(WorkItem) * conf.size());
   cp(o_bin, bin.data(), sizeof(WorkItem) * bin.size());
   cp(o_raster, raster.data(), sizeof(WorkItem) * raster.size());
-  for (int g = 0; g < kIntegClasses; ++g)
+  for (size_t g = 0; g < groups.size(); ++g)
     cp(o_integ[g], integ[g].data(), sizeof(WorkItem) * integ[g].size());
   if (rc == GG_OK) rc = batch_occupancy(P);
   cp(o_sitems, splat_items.data(), 4 * splat_items.size());

@@ -1,13 +1,15 @@
 // Batched path: many target views of uneven resolution, view count and bin
-// count fused by persistent kernels over per-phase work lists, the whole
-// batch captured once into a hipGraph and replayed with one launch.
+// count fused by kernels over per-phase work lists, the whole batch captured
+// once into a hipGraph and replayed with one launch.
 //
 // Each work item runs the same device function as the plain entry points
 // (conf_tile, splat_bin_block, tile_scan_block, raster_tile,
 // integrate_tile), so every output is bitwise identical to the
-// corresponding plain call.  Work lists are grouped by item and split into
-// contiguous ranges per workgroup; workgroups are numbered XCD-aware so
-// each XCD walks a contiguous part of the list.
+// corresponding plain call.  Work lists are grouped by item; the light
+// phases run persistent workgroups that take chunks of their lists, the
+// fusion one workgroup per entry; either way each XCD walks a contiguous
+// part of a list.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -133,43 +135,44 @@ __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__re
 
 // Fusion: one workgroup tile of one item per work entry, every entry of a
 // launch in the same specialisation as the plain kernel (so the same code
-// and register budget).
+// and register budget).  Not persistent: one workgroup per entry, as the
+// plain launch has one per tile -- a tile is heavy (a whole workgroup's
+// pixels over every bin), the classes have far more entries than the
+// device holds workgroups, and the dispatcher then balances them as well as
+// a work queue would, without its counter and barriers per entry.  Entries
+// go to the XCDs in contiguous parts (xcd_tile), so the tiles in flight on
+// an XCD are neighbours in the list (each item's bands) and share the
+// view-table lines in its L2.
 template <int V, int KC, bool kExact, int kMode>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
-                                                               uint32_t n, uint32_t chunk,
-                                                               uint32_t *ctr) {
+                                                               uint32_t n) {
   extern __shared__ float smem[];
-  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
-    const WorkItem wi = work[w];
-    if constexpr (kMode == 0)
-      integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
-    else
-      integrate_tile<V, KC, kExact, true, kMode == 2 ? 1 : 0>(items[wi.item].integ,
-                                                               work_tile(wi), smem);
-  });
+  const WorkItem wi = work[xcd_tile(blockIdx.x, n)];
+  if constexpr (kMode == 0)
+    integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
+  else
+    integrate_tile<V, KC, kExact, true, kMode == 2 ? 1 : 0>(items[wi.item].integ, work_tile(wi),
+                                                             smem);
 }
 
 template <int C>
-static void launch_integ_class(const BatchPlan &P, uint32_t n, int grid, uint32_t chunk,
-                               size_t shm, hipStream_t s) {
+static void launch_integ_class(const BatchPlan &P, const IntegGroup &g, hipStream_t s) {
   // the LDS form exists for 8 and 4 bins per thread only (the host assigns
   // no items to the other combinations)
   if constexpr (mode_of_class(C) == 0 || vec_of_class(C) >= 4)
     hipLaunchKernelGGL((batch_integrate_kernel<vec_of_class(C), views_of_class(C), exact_class(C),
                                                mode_of_class(C)>),
-                       dim3(grid), dim3(P.integ_threads), shm, s, P.d_items, P.d_integ[C], n,
-                       chunk, P.d_ctr + (kLightCounters + C) * kXcds);
+                       dim3(g.n), dim3(g.threads), g.shm, s, P.d_items, g.list, g.n);
 }
 
 template <int C>
-static void dispatch_integ_class(int c, const BatchPlan &P, uint32_t n, int grid, uint32_t chunk,
-                                 size_t shm, hipStream_t s) {
+static void dispatch_integ_class(const BatchPlan &P, const IntegGroup &g, hipStream_t s) {
   if constexpr (C < kIntegClasses) {
-    if (c == C)
-      launch_integ_class<C>(P, n, grid, chunk, shm, s);
+    if (g.cls == C)
+      launch_integ_class<C>(P, g, s);
     else
-      dispatch_integ_class<C + 1>(c, P, n, grid, chunk, shm, s);
+      dispatch_integ_class<C + 1>(P, g, s);
   }
 }
 
@@ -188,7 +191,8 @@ static uint32_t chunk_of(uint32_t n, int grid) {
 }
 
 // Resident workgroups per CU of the light phases: their persistent grids
-// fill the device exactly.
+// fill the device exactly, or hold at most blocks_per_cu workgroups per CU
+// (leaving the rest of each CU to the fusion of the other branch).
 int batch_occupancy(BatchPlan &P) {
   int a = 0, b = 0, c = 0;
   if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_conf_kernel, 256, 0),
@@ -200,21 +204,22 @@ int batch_occupancy(BatchPlan &P) {
   if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, batch_raster_kernel, 256,
                                                                       0), "batch occupancy"))
     return rc;
-  P.occ_conf = a > 0 ? a : 1;
-  P.occ_bin = b > 0 ? b : 1;
-  P.occ_raster = c > 0 ? c : 1;
+  const int cap = P.blocks_per_cu > 0 ? P.blocks_per_cu : 1 << 20;
+  P.occ_conf = std::max(1, std::min(a, cap));
+  P.occ_bin = std::max(1, std::min(b, cap));
+  P.occ_raster = std::max(1, std::min(c, cap));
   return GG_OK;
 }
 
 int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
                  hipEvent_t join) {
-  const int cus = P.cus, per = P.blocks_per_cu;
+  const int cus = P.cus;
   // tile counts of every item and the phases' work counters
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1024), dim3(256), 0, s, P.zero_ptr, P.zero_words);
   // The splat phases depend on the depth maps and the zeroed counts only: with a side stream
   // they form a second branch of the graph, beside the bins, weights and fusion of the main
   // branch, and the two overlap; the branches join before the graph ends.
-  const bool branch = side && P.n_bin;
+  const bool branch = side && P.n_bin && P.branches != 1;
   if (branch) {
     if (int rc = check_hip(hipEventRecord(fork, s), "batch fork")) return rc;
     if (int rc = check_hip(hipStreamWaitEvent(side, fork, 0), "batch fork")) return rc;
@@ -240,12 +245,8 @@ int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
     hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
                        chunk_of(P.n_conf, g), P.d_ctr + 0 * kXcds);
   }
-  for (int c = 0; c < kIntegClasses; ++c) {
-    const uint32_t n = P.n_integ[c];
-    if (!n) continue;
-    const int g = persistent_grid(n, per, cus);
-    dispatch_integ_class<0>(c, P, n, g, chunk_of(n, g), P.integ_shm[c], s);
-  }
+  for (const IntegGroup &g : P.integ)
+    if (g.n) dispatch_integ_class<0>(P, g, s);
   if (branch)
     if (int rc = check_hip(hipStreamWaitEvent(s, join, 0), "batch join")) return rc;
   return check_hip(hipGetLastError(), "batch phases");

@@ -1,6 +1,8 @@
 // Batched path: device-resident item descriptors, work lists and the plan.
 #pragma once
 
+#include <vector>
+
 #include "splat_device.h"
 #include "tsdf_device.h"
 
@@ -18,7 +20,7 @@ constexpr int kVecClasses = 4, kViewClasses = 8, kModeClasses = 3;
 constexpr int kIntegClasses = kVecClasses * kViewClasses * kModeClasses;
 constexpr int kLightCounters = 4;  // confidence, bin count, bin fill, raster
 constexpr int kXcds = 8;           // each phase keeps one counter per XCD
-constexpr int kBatchCounters = (kLightCounters + kIntegClasses) * kXcds;
+constexpr int kBatchCounters = kLightCounters * kXcds;
 
 __host__ __device__ constexpr int vec_of_class(int c) {
   return 8 >> ((c / kModeClasses) / kViewClasses);
@@ -75,24 +77,34 @@ __device__ __forceinline__ uint32_t work_tile(const WorkItem &w) {
   return (uint32_t)w.x | ((uint32_t)w.y << 16);
 }
 
+// One fusion launch of the batch: the tiles of every item in one
+// specialisation (class) and workgroup size.
+struct IntegGroup {
+  int cls = 0;
+  uint32_t threads = 0;
+  size_t shm = 0;              // dynamic LDS (its items' largest)
+  WorkItem *list = nullptr;    // device
+  uint32_t n = 0;
+};
+
 struct BatchPlan {
   int32_t n_items = 0;
-  int cus = 256, blocks_per_cu = 4;
-  uint32_t integ_threads = 256;
+  int cus = 256, blocks_per_cu = 0;  // 0: light phases fill each CU
+  int branches = 2;                  // 2: splat phases beside the fusion; 1: one sequence
   int occ_conf = 1, occ_bin = 1, occ_raster = 1;  // resident workgroups per CU
   // device memory owned by the plan
   void *dev = nullptr;
   size_t dev_bytes = 0;
   BatchItem *d_items = nullptr;
-  WorkItem *d_conf = nullptr, *d_bin = nullptr, *d_raster = nullptr, *d_integ[kIntegClasses] = {};
-  uint32_t n_conf = 0, n_bin = 0, n_raster = 0, n_integ[kIntegClasses] = {};
-  size_t integ_shm[kIntegClasses] = {};  // dynamic LDS of each fusion class (its items' largest)
+  WorkItem *d_conf = nullptr, *d_bin = nullptr, *d_raster = nullptr;
+  uint32_t n_conf = 0, n_bin = 0, n_raster = 0;
+  std::vector<IntegGroup> integ;
   uint32_t *d_splat_items = nullptr;
   uint32_t n_splat_items = 0;
   uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
   size_t zero_words = 0;
-  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters (zeroed per launch):
-                                 // kXcds per phase
+  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters of the light phases
+                                 // (zeroed per launch): kXcds per phase
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

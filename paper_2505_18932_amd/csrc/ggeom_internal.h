@@ -172,6 +172,9 @@ struct IntegrateArgs {
   uint32_t cpp, ppb; // chunks per pixel, pixels per workgroup
   uint32_t pw_shift; // 2^pw_shift neighbouring pixels share each wavefront row
   uint32_t nblocks;
+  // tile order: band_T tiles per target row, visited in vertical bands of
+  // band_B tiles across and band_H rows (band_T = 0: row-major)
+  uint32_t band_T, band_B, band_H;
   float decay, cap;
   int32_t carry;
   int32_t exact_only;  // 1: every sample takes IEEE division (extreme depths)

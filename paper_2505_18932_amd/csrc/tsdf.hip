@@ -55,7 +55,8 @@ int launch_conf(const ConfArgs &a, hipStream_t s) {
 template <int V, int KC, bool kExact, bool kStage, int kCarry>
 __global__ __launch_bounds__(1024) void integrate_kernel(IntegrateArgs a) {
   extern __shared__ float smem[];
-  integrate_tile<V, KC, kExact, kStage, kCarry>(a, xcd_tile(blockIdx.x, a.nblocks), smem);
+  integrate_tile<V, KC, kExact, kStage, kCarry>(a, band_tile(a, xcd_tile(blockIdx.x, a.nblocks)),
+                                                smem);
 }
 
 template <int V, int KC, bool kStage, int kCarry>

@@ -130,6 +130,26 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
   __syncthreads();  // the tile may be restaged by the caller's next iteration
 }
 
+// Fusion tile at position s of the launch's visiting order.  Far source
+// views see a target ray as a long epipolar segment spanning many source
+// rows, so one target row gathers from a large part of each view table;
+// the rows below it gather from nearly the same lines.  Visiting vertical
+// bands of band_B tiles across, each row by row from the top, keeps the
+// lines that the tiles in flight share within cache, where row-major order
+// would have walked the whole target width before returning to them.
+// Every full band comes before the narrower last one (band_T = 0:
+// row-major order).
+__host__ __device__ __forceinline__ uint32_t band_tile(const IntegrateArgs &a, uint32_t s) {
+  if (a.band_T == 0) return s;
+  const uint32_t span = a.band_B * a.band_H;  // tiles of a full band
+  const uint32_t b = s / span;
+  const uint32_t b0 = b * a.band_B;
+  const uint32_t w = a.band_T - b0 < a.band_B ? a.band_T - b0 : a.band_B;
+  const uint32_t rem = s - b * span;
+  const uint32_t r = rem / w;
+  return r * a.band_T + b0 + (rem - r * w);
+}
+
 // ---------------------------------------------------------------------------
 // vector access of V consecutive floats (V = 4, 2, 1)
 

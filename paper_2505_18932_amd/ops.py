@@ -197,14 +197,17 @@ def splat_views_ewa(src, depth: torch.Tensor, rgb: torch.Tensor, tgt, params, *,
 
 def volume_tuning(t):
     """A launch shape of the volume kernels, (pixels per workgroup, pixels per
-    wavefront row, bins per thread) with 0 for a default, as the C record (or
-    None: the defaults)."""
+    wavefront row, bins per thread[, band width in pixels of the fusion's
+    tile order]) with 0 for a default, as the C record (or None: the
+    defaults)."""
     if t is None:
         return None
     if isinstance(t, L.GGVolumeTuning):
         return t
-    ppb, pw, vec = (int(v) for v in t)
-    return L.GGVolumeTuning(ppb, pw, vec)
+    v = [int(x) for x in t]
+    if len(v) not in (3, 4):
+        raise ValueError("volume tuning: 3 or 4 integers, got %r" % (t,))
+    return L.GGVolumeTuning(*(v + [0] * (4 - len(v))))
 
 
 def _tref(t):
@@ -539,7 +542,8 @@ class BatchPlan:
     binds these buffers; write new inputs into the same tensors between
     launches."""
 
-    def __init__(self, items, volume_threads=0, blocks_per_cu=0, bins_per_thread=0):
+    def __init__(self, items, pixels_per_block=0, blocks_per_cu=0, bins_per_thread=0,
+                 branches=0):
         self.items = items
         self._keep = []
         arr = (L.GGBatchItem * len(items))()
@@ -594,7 +598,8 @@ class BatchPlan:
                 b.sp_tape = o["tape"].data_ptr()
             self._keep.append(sa)
         self._arr = arr
-        tune = L.GGBatchTuning(int(volume_threads), int(blocks_per_cu), int(bins_per_thread))
+        tune = L.GGBatchTuning(int(pixels_per_block), int(blocks_per_cu), int(bins_per_thread),
+                               int(branches))
         h = C.c_void_p()
         L.check(L.lib().gg_batch_plan(arr, len(items), C.byref(tune), C.byref(h)))
         self._h = h

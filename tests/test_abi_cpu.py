@@ -208,14 +208,15 @@ def test_volume_tuning_is_per_call_and_validated():
     tp = ops.tsdf_params(scenes.tsdf_params(num_bins=64))
     ws_small = 100  # fails the workspace check after a valid tuning
     for bad in ((-1, 0, 0), (1025, 0, 0), (8, 65, 0), (0, -1, 0), (0, 0, 3), (0, 0, 16),
-                (0, 0, -1)):
+                (0, 0, -1), (0, 0, 0, -1), (16, 16, 8, 65537)):
         t = ops.volume_tuning(bad)
         rc = lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, None, None, FAKE,
                                 FAKE, None, None, C.byref(t), FAKE, 1 << 40, None)
         assert rc == L.GG_ERR_INVALID, bad
         assert lib.tsdf_extract_depth(C.byref(tgt), C.byref(tp), FAKE, FAKE, FAKE, FAKE,
                                       C.byref(t), None) == L.GG_ERR_INVALID, bad
-    for ok in ((0, 0, 0), (16, 16, 8), (32, 8, 4), (1024, 64, 1), (3, 1, 2)):
+    for ok in ((0, 0, 0), (16, 16, 8), (32, 8, 4), (1024, 64, 1), (3, 1, 2), (16, 16, 8, 128),
+               (16, 16, 8, 65536), (8, 8, 4, 1)):
         t = ops.volume_tuning(ok)
         rc = lib.tsdf_integrate(src, 2, FAKE, C.byref(tgt), C.byref(tp), None, None, None, FAKE,
                                 FAKE, None, None, C.byref(t), FAKE, ws_small, None)

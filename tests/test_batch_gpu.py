@@ -47,7 +47,9 @@ def _check(plan_items, refs):
                 _same(it["splat_out"][key], s[key], f"item {i} splat {key}")
 
 
-@pytest.mark.parametrize("tuning", [(0, 0), (64, 1), (512, 2), (1024, 8)])
+# (pixels per fusion workgroup, light-phase workgroups per CU, bins per thread, branches)
+@pytest.mark.parametrize("tuning", [(0, 0, 0, 0), (64, 1, 0, 0), (512, 2, 8, 2), (1024, 8, 4, 1),
+                                    (16, 0, 8, 1), (3, 0, 8, 0)])
 def test_batch_equals_plain(tuning):
     items = _items()
     refs = [_plain(it) for it in items]

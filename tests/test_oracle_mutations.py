@@ -56,8 +56,8 @@ MUTANTS = [
      "(real)((double)sp->sigma_px * (double)tgt->fx / (double)src[k].fx);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    real *prgb",
      "(real)((double)sp->sigma_px);\n    const float *dk = depth + ns * k;\n    const uint8_t *ck = rgb + ns * 3 * k;\n    real *prgb",
      PINS),
-    ("grad_clamp_ignored", "if (s < tau) g_depth_in[ns * k + q] += gF[e] * w / Wn;",
-     "g_depth_in[ns * k + q] += gF[e] * w / Wn;", GRADS),
+    ("grad_clamp_ignored", "if (s < tau) {\n          g_depth_in[ns * k + q] += gF[e] * w / Wn;",
+     "if (1) {\n          g_depth_in[ns * k + q] += gF[e] * w / Wn;", GRADS),
     ("grad_neighbour_term", "g_depth_in[ns * k + n] -= gnu * (real)2 * dd;", "", GRADS),
     ("grad_alpha_term", "dLdG += g_alpha[o] * others;", "", GRADS),
     ("grad_footprint_term", "d2 * dsdD / (sig * g.s2)", "0", GRADS),

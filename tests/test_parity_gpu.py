@@ -267,13 +267,19 @@ def test_repeat_runs_bitwise():
 
 
 def test_volume_tile_shape_does_not_change_results():
-    c = small(bins=96)
+    """Launch shape and tile order (bands of 1 .. 5 tiles across a row of 6,
+    a narrower last band, several bands per row of 12, or row-major) leave
+    every output bitwise unchanged."""
+    c = small(w=96, h=29, bins=96)
     depth, _ = to_dev(c)
     base = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"])
     F, W = base[0], base[1]
+    shapes = [(0, 0, 0), (1, 1, 0), (3, 1, 0), (8, 1, 0), (8, 8, 0), (16, 16, 0), (40, 8, 0),
+              (32, 32, 0), (16, 16, 16), (16, 16, 48), (16, 16, 80), (8, 8, 24), (32, 16, 32),
+              (16, 16, 65536), (40, 8, 80)]
     for vec in (1, 2, 4, 8):
-        for ppb in ((0, 0), (1, 1), (3, 1), (8, 1), (8, 8), (16, 16), (40, 8), (32, 32)):
-            tun = (ppb[0], ppb[1], vec)
+        for ppb in shapes:
+            tun = (ppb[0], ppb[1], vec, ppb[2])
             v = gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"], tuning=tun)
             e = gg.tsdf_extract_depth(c["tgt"], c["tsdf"], F, W, tuning=tun)
             torch.cuda.synchronize()
