@@ -455,8 +455,8 @@ int tsdf_integrate_backward(const gg_camera *src, int32_t K, const float *depth,
 /* ---------------------------------------------------------------------------
  * Batched path: many target views of uneven resolution, view count and bin
  * count (each with its own inputs, cameras, parameters, volume and outputs)
- * fused by kernels over per-phase work lists (persistent ones for the light
- * phases, one workgroup per tile for the fusion) in one hipGraph launch.
+ * fused by kernels over per-phase work lists (persistent ones for the splat
+ * binning, one workgroup per tile for the others) in one hipGraph launch.
  * Every output is
  * bitwise identical to the plain calls (splat_views + tsdf_integrate with
  * fused extraction) on the same item, for any tuning.
@@ -484,7 +484,7 @@ typedef struct gg_batch_tuning {
   int32_t pixels_per_block; /* target pixels per fusion workgroup, 0..1024 (0: 16; fewer
                                where the workgroup would exceed 1024 threads)             */
   int32_t blocks_per_cu;   /* resident workgroups per compute unit of the persistent splat
-                              and confidence phases, 0..64 (0: as many as fit)             */
+                              binning phases, 0..64 (0: as many as fit)                    */
   int32_t bins_per_thread; /* of the fusion, as in gg_volume_tuning (0: default)            */
   int32_t branches;        /* 0 or 2: the splat phases form a branch of the graph that runs
                               beside the fusion; 1: every phase in one sequence          */

@@ -11,7 +11,7 @@ next to this module (``tuning_cache.json``):
   passes with each call (``tuning=`` of the volume calls, the C ABI's
   ``gg_volume_tuning``); nothing is set process-wide;
 * batched path: (pixels per fusion workgroup, resident workgroups per
-  compute unit of the persistent light phases, bins per thread, graph
+  compute unit of the persistent splat binning, bins per thread, graph
   branches) for a batch signature.
 """
 from __future__ import annotations
@@ -34,10 +34,10 @@ PLAIN_CANDIDATES = [(0, 0, 4, 0), (8, 8, 4, 0), (16, 8, 4, 0), (16, 16, 4, 0), (
                     (64, 16, 8, 0), (64, 32, 8, 0), (16, 16, 8, 128), (16, 16, 8, 512),
                     (16, 16, 8, 65536), (32, 16, 8, 128)]
 # (target pixels per fusion workgroup, resident workgroups per compute unit of
-# the persistent splat and confidence phases, bins per thread, graph branches);
+# the persistent splat binning phases, bins per thread, graph branches);
 # 0 = default
-BATCH_CANDIDATES = [(16, 0, 8, 2), (16, 0, 8, 1), (32, 0, 8, 2), (32, 0, 8, 1), (16, 2, 8, 2),
-                    (64, 0, 8, 2), (16, 0, 4, 2), (16, 0, 4, 1), (32, 0, 4, 2)]
+BATCH_CANDIDATES = [(16, 0, 8, 2), (16, 0, 8, 1), (32, 0, 8, 2), (16, 1, 8, 2), (16, 2, 8, 2),
+                    (16, 0, 4, 2), (32, 0, 4, 2)]
 
 
 def arch(device=None) -> str:

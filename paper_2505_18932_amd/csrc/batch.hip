@@ -5,10 +5,10 @@
 // Each work item runs the same device function as the plain entry points
 // (conf_tile, splat_bin_block, tile_scan_block, raster_tile,
 // integrate_tile), so every output is bitwise identical to the
-// corresponding plain call.  Work lists are grouped by item; the light
-// phases run persistent workgroups that take chunks of their lists, the
-// fusion one workgroup per entry; either way each XCD walks a contiguous
-// part of a list.
+// corresponding plain call.  Work lists are grouped by item; the splat
+// binning phases run persistent workgroups that take chunks of their lists,
+// the others one workgroup per entry; either way each XCD walks a
+// contiguous part of a list.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -93,15 +93,18 @@ __device__ __forceinline__ void for_each_entry(uint32_t n, uint32_t chunk, uint3
     for (uint32_t w = w0; w < w1; ++w) body(w);
 }
 
+// The confidence, raster and fusion phases run one workgroup per entry, as
+// their plain launches run one per tile: their lists hold far more entries
+// than the device holds workgroups, so the dispatcher balances them as well
+// as a work queue would, without a counter and barriers per grab.  Entries
+// go to the XCDs in contiguous parts (xcd_tile), so the tiles in flight on
+// an XCD are neighbours in the list and share the lines in its L2.
 __global__ __launch_bounds__(256) void batch_conf_kernel(const BatchItem *__restrict__ items,
                                                          const WorkItem *__restrict__ work,
-                                                         uint32_t n, uint32_t chunk,
-                                                         uint32_t *ctr) {
+                                                         uint32_t n) {
   __shared__ float tile[kConfTileFloats];
-  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
-    const WorkItem wi = work[w];
-    conf_tile(items[wi.item].conf, wi.k, wi.x, wi.y, tile);
-  });
+  const WorkItem wi = uniform_entry(work, xcd_tile(blockIdx.x, n));
+  conf_tile(items[wi.item].conf, wi.k, wi.x, wi.y, tile);
 }
 
 template <bool kFill>
@@ -124,31 +127,21 @@ __global__ __launch_bounds__(1024) void batch_scan_kernel(const BatchItem *__res
 
 __global__ __launch_bounds__(256) void batch_raster_kernel(const BatchItem *__restrict__ items,
                                                            const WorkItem *__restrict__ work,
-                                                           uint32_t n, uint32_t chunk,
-                                                           uint32_t *ctr) {
+                                                           uint32_t n) {
   __shared__ RasterLds lds;
-  for_each_entry(n, chunk, ctr, [&](uint32_t w) {
-    const WorkItem wi = work[w];
-    raster_tile<false>(items[wi.item].splat, wi.k, work_tile(wi), lds);
-  });
+  const WorkItem wi = uniform_entry(work, xcd_tile(blockIdx.x, n));
+  raster_tile<false>(items[wi.item].splat, wi.k, work_tile(wi), lds);
 }
 
 // Fusion: one workgroup tile of one item per work entry, every entry of a
-// launch in the same specialisation as the plain kernel (so the same code
-// and register budget).  Not persistent: one workgroup per entry, as the
-// plain launch has one per tile -- a tile is heavy (a whole workgroup's
-// pixels over every bin), the classes have far more entries than the
-// device holds workgroups, and the dispatcher then balances them as well as
-// a work queue would, without its counter and barriers per entry.  Entries
-// go to the XCDs in contiguous parts (xcd_tile), so the tiles in flight on
-// an XCD are neighbours in the list (each item's bands) and share the
-// view-table lines in its L2.
+// launch in the same specialisation as the plain kernel (so the same code);
+// each item's tiles are listed in the plain launch's band order.
 template <int V, int KC, bool kExact, int kMode>
 __global__ __launch_bounds__(1024) void batch_integrate_kernel(const BatchItem *__restrict__ items,
                                                                const WorkItem *__restrict__ work,
                                                                uint32_t n) {
   extern __shared__ float smem[];
-  const WorkItem wi = work[xcd_tile(blockIdx.x, n)];
+  const WorkItem wi = uniform_entry(work, xcd_tile(blockIdx.x, n));
   if constexpr (kMode == 0)
     integrate_tile<V, KC, kExact>(items[wi.item].integ, work_tile(wi), smem);
   else
@@ -190,24 +183,16 @@ static uint32_t chunk_of(uint32_t n, int grid) {
   return c ? (uint32_t)c : 1u;
 }
 
-// Resident workgroups per CU of the light phases: their persistent grids
+// Resident workgroups per CU of the persistent binning phases: their grids
 // fill the device exactly, or hold at most blocks_per_cu workgroups per CU
-// (leaving the rest of each CU to the fusion of the other branch).
+// (leaving the rest of each CU to the other branch).
 int batch_occupancy(BatchPlan &P) {
-  int a = 0, b = 0, c = 0;
-  if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_conf_kernel, 256, 0),
-                         "batch occupancy"))
-    return rc;
+  int b = 0;
   if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                              &b, batch_bin_kernel<true>, 256, 0), "batch occupancy"))
     return rc;
-  if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, batch_raster_kernel, 256,
-                                                                      0), "batch occupancy"))
-    return rc;
   const int cap = P.blocks_per_cu > 0 ? P.blocks_per_cu : 1 << 20;
-  P.occ_conf = std::max(1, std::min(a, cap));
   P.occ_bin = std::max(1, std::min(b, cap));
-  P.occ_raster = std::max(1, std::min(c, cap));
   return GG_OK;
 }
 
@@ -227,24 +212,22 @@ int batch_record(BatchPlan &P, hipStream_t s, hipStream_t side, hipEvent_t fork,
   const hipStream_t ss = branch ? side : s;
   if (P.n_bin) {
     const int gb = persistent_grid(P.n_bin, P.occ_bin, cus);
-    const int gr = persistent_grid(P.n_raster, P.occ_raster, cus);
     hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(gb), dim3(256), 0, ss, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1 * kXcds);
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 0 * kXcds);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(P.n_splat_items), dim3(1024), 0, ss, P.d_items,
                        P.d_splat_items);
     hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(gb), dim3(256), 0, ss, P.d_items, P.d_bin,
-                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 2 * kXcds);
-    hipLaunchKernelGGL(batch_raster_kernel, dim3(gr), dim3(256), 0, ss, P.d_items, P.d_raster,
-                       P.n_raster, chunk_of(P.n_raster, gr), P.d_ctr + 3 * kXcds);
+                       P.n_bin, chunk_of(P.n_bin, gb), P.d_ctr + 1 * kXcds);
+    if (P.n_raster)
+      hipLaunchKernelGGL(batch_raster_kernel, dim3(P.n_raster), dim3(256), 0, ss, P.d_items,
+                         P.d_raster, P.n_raster);
   }
   if (branch)
     if (int rc = check_hip(hipEventRecord(join, side), "batch join")) return rc;
   hipLaunchKernelGGL(batch_bins_kernel, dim3(P.n_items), dim3(256), 0, s, P.d_items);
-  if (P.n_conf) {
-    const int g = persistent_grid(P.n_conf, P.occ_conf, cus);
-    hipLaunchKernelGGL(batch_conf_kernel, dim3(g), dim3(256), 0, s, P.d_items, P.d_conf, P.n_conf,
-                       chunk_of(P.n_conf, g), P.d_ctr + 0 * kXcds);
-  }
+  if (P.n_conf)
+    hipLaunchKernelGGL(batch_conf_kernel, dim3(P.n_conf), dim3(256), 0, s, P.d_items, P.d_conf,
+                       P.n_conf);
   for (const IntegGroup &g : P.integ)
     if (g.n) dispatch_integ_class<0>(P, g, s);
   if (branch)

@@ -18,7 +18,7 @@ constexpr int kConfTileFloats = kConfLH * kConfLW;
 // 4 bins per thread).
 constexpr int kVecClasses = 4, kViewClasses = 8, kModeClasses = 3;
 constexpr int kIntegClasses = kVecClasses * kViewClasses * kModeClasses;
-constexpr int kLightCounters = 4;  // confidence, bin count, bin fill, raster
+constexpr int kLightCounters = 2;  // persistent phases: bin count, bin fill
 constexpr int kXcds = 8;           // each phase keeps one counter per XCD
 constexpr int kBatchCounters = kLightCounters * kXcds;
 
@@ -71,6 +71,22 @@ struct WorkItem {
   uint16_t x, y;  // conf: tile (x, y); splat bin: source block x; raster / fusion: tile x
 };
 
+// Entry e of a work list, read once and made uniform: the item index then
+// addresses its descriptor through the scalar unit (SGPRs), instead of a
+// vector register pair held for the whole tile.
+__device__ __forceinline__ WorkItem uniform_entry(const WorkItem *work, uint32_t e) {
+  static_assert(sizeof(WorkItem) == 8, "WorkItem is two dwords");
+  const uint2 raw = reinterpret_cast<const uint2 *>(work)[e];
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(raw.x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(raw.y);
+  WorkItem w;
+  w.item = (uint16_t)(lo & 0xffffu);
+  w.k = (uint16_t)(lo >> 16);
+  w.x = (uint16_t)(hi & 0xffffu);
+  w.y = (uint16_t)(hi >> 16);
+  return w;
+}
+
 // The fusion and raster phases address tiles beyond 65535: they use x as
 // the low 16 bits and y as the high 16 bits of a 32-bit tile index.
 __device__ __forceinline__ uint32_t work_tile(const WorkItem &w) {
@@ -89,9 +105,9 @@ struct IntegGroup {
 
 struct BatchPlan {
   int32_t n_items = 0;
-  int cus = 256, blocks_per_cu = 0;  // 0: light phases fill each CU
+  int cus = 256, blocks_per_cu = 0;  // 0: the binning phases fill each CU
   int branches = 2;                  // 2: splat phases beside the fusion; 1: one sequence
-  int occ_conf = 1, occ_bin = 1, occ_raster = 1;  // resident workgroups per CU
+  int occ_bin = 1;  // resident workgroups per CU of the binning phases
   // device memory owned by the plan
   void *dev = nullptr;
   size_t dev_bytes = 0;
@@ -103,7 +119,7 @@ struct BatchPlan {
   uint32_t n_splat_items = 0;
   uint32_t *zero_ptr = nullptr;  // tile counts of every item, then the counters
   size_t zero_words = 0;
-  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters of the light phases
+  uint32_t *d_ctr = nullptr;     // kBatchCounters work counters of the binning phases
                                  // (zeroed per launch): kXcds per phase
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
