@@ -109,6 +109,87 @@ def recorded_valu_instructions():
 TILE = [None]
 
 
+def _oracle_frames(oracle, c, frames, carry):
+    """Wall seconds of the oracle's forward (splat, fusion with the volume
+    carried from frame to frame when ``carry``, extraction) over ``frames``
+    ((depth, rgb) pairs, generated beforehand)."""
+    t0 = time.perf_counter()
+    F = W = None
+    for d, r in frames:
+        oracle.splat(c["src"], d, r, c["tgt"], c["splat"])
+        if carry:
+            F, W = oracle.integrate(c["src"], d, c["tgt"], c["tsdf"], F_prev=F, W_prev=W)
+        else:
+            F, W = oracle.integrate(c["src"], d, c["tgt"], c["tsdf"])
+        oracle.extract(F, W, c["tsdf"])
+    return time.perf_counter() - t0
+
+
+def cpu_plan(procs):
+    """The CPU oracle's timing plan, whole frames of the forward (splat +
+    fusion + extraction) on all host cores, scene generation excluded:
+    the two parallel-rig scenes in full, the video sequence's 30 frames with
+    the volume carried, the 24 batching items in sequence, and 3 frames of
+    the streaming sequence extrapolated to its 300 (labelled as such).  No
+    GPU work.  Returns one record per workload."""
+    import oracle
+
+    cores = oracle.num_threads()
+    out = {"cores": cores, "cpu": _cpu_model(), "kind": "oracle", "unit": "Mpix/s"}
+
+    def rec(name, c, frames, carry, note, extrapolate_to=None):
+        el = _oracle_frames(oracle, c, frames, carry)
+        npix = c["tgt"].width * c["tgt"].height * len(frames)
+        r = {"frames": len(frames), "seconds": round(el, 2),
+             "mpix_s": round(npix / el / 1e6, 4), "ms_per_frame": round(el * 1e3 / len(frames), 1),
+             "workload": note}
+        if extrapolate_to:
+            r["extrapolated_seconds_%d_frames" % extrapolate_to] = round(
+                el / len(frames) * extrapolate_to, 1)
+        out[name] = r
+        print("# cpu plan: %s %s" % (name, r), file=sys.stderr, flush=True)
+
+    for name, cfg in (("tiny_320x240_K2_D64", scenes.config1()),
+                      ("differentiation_640x360_K4_D96", scenes.config3())):
+        rec(name, cfg, [(cfg["depth"], cfg["rgb"])], False, "one frame, in full")
+    c2 = scenes.config2(seed=0)
+    f2 = make_frames(30, procs)
+    rec("video_1280x720_K4_D128", c2, list(zip(f2[0], f2[1])), True,
+        "all 30 frames of the video sequence, volume carried")
+    descs = scenes.config4_items()
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            items = pool.map(scenes.config4_item, descs)
+    else:
+        items = [scenes.config4_item(d) for d in descs]
+    t0 = time.perf_counter()
+    px = 0
+    for it in items:
+        _oracle_frames(oracle, it, [(it["depth"], it["rgb"])], False)
+        px += it["tgt"].width * it["tgt"].height
+    el = time.perf_counter() - t0
+    out["batch_24_items"] = {"frames": len(items), "seconds": round(el, 2),
+                             "mpix_s": round(px / el / 1e6, 4),
+                             "workload": "the 24 batching items in sequence, each one frame"}
+    print("# cpu plan: batch %s" % out["batch_24_items"], file=sys.stderr, flush=True)
+    c5, d5, r5 = streaming_sequence(procs, 3)
+    rec("streaming_1920x1080_K8_D256", c5, list(zip(d5, r5)), True,
+        "3 consecutive frames of the streaming sequence, volume carried; seconds for its 300 "
+        "frames extrapolated from them", extrapolate_to=300)
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def fusion_stream_probe_ms(gg, torch, dev, tgt, tp, F, W, reps=10):
     """Mean duration of the fusion kernel launched with no views on the
     volume (F, W) in place (gg_fusion_stream_probe), HIP events on the
@@ -219,7 +300,7 @@ def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3):
             fwd_ms.append(ev[0].elapsed_time(ev[1]))
             bwd_ms.append(ev[1].elapsed_time(ev[2]))
 
-    for t in range(warm):
+    for t in range(min(warm, nf)):
         frame(t, t > 0, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -626,6 +707,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="run only the CPU oracle's timing plan (no GPU work) and print it")
+    ap.add_argument("--stream-frames", type=int, default=STREAM_FRAMES,
+                    help="frames of the streaming leg (1920x1080, K=8, D=256); the leg warms up "
+                         "on min(3, frames) of them first")
     ap.add_argument("--no-temporal", action="store_true")
     ap.add_argument("--no-raymarch", action="store_true")
     ap.add_argument("--no-network", action="store_true")
@@ -644,6 +730,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.cpu_plan:
+        procs = args.procs or max(1, min(16, os.cpu_count() or 1))
+        print(json.dumps({"cpu_plan": cpu_plan(procs)}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the geometry stage on a single "
               "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -654,7 +744,7 @@ def main():
     print(f"# frames generated: {depth_h.shape}", file=sys.stderr, flush=True)
     # the large workload's first frame for its backward/forward ratio, generated (like the
     # frames above) before anything touches the GPU
-    large = None if args.no_bwd else streaming_sequence(procs)
+    large = None if args.no_bwd else streaming_sequence(procs, args.stream_frames)
     paper = None
     if not args.no_paper_shape:
         pc = scenes.paper_shape()

@@ -151,36 +151,40 @@ __host__ __device__ __forceinline__ uint32_t band_tile(const IntegrateArgs &a, u
 }
 
 // ---------------------------------------------------------------------------
-// vector access of V consecutive floats (V = 4, 2, 1)
+// Volume stream access of V consecutive floats (V = 8, 4, 2, 1).  The volume
+// is read and written once per launch: its accesses are non-temporal, so
+// that they pass through the caches without evicting the view-table lines
+// that the gathers of neighbouring tiles reuse.
 
 template <int V>
 __device__ __forceinline__ void loadv(const float *p, float (&o)[V]) {
   if constexpr (V == 8) {
-    const gg_v4f a = *(const GG_GLOBAL gg_v4f *)p, b = *(const GG_GLOBAL gg_v4f *)(p + 4);
+    const gg_v4f a = __builtin_nontemporal_load((const GG_GLOBAL gg_v4f *)p),
+                 b = __builtin_nontemporal_load((const GG_GLOBAL gg_v4f *)(p + 4));
     o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
     o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
   } else if constexpr (V == 4) {
-    const gg_v4f v = *(const GG_GLOBAL gg_v4f *)p;
+    const gg_v4f v = __builtin_nontemporal_load((const GG_GLOBAL gg_v4f *)p);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   } else if constexpr (V == 2) {
-    const gg_v2f v = *(const GG_GLOBAL gg_v2f *)p;
+    const gg_v2f v = __builtin_nontemporal_load((const GG_GLOBAL gg_v2f *)p);
     o[0] = v.x; o[1] = v.y;
   } else {
-    o[0] = *gmem(p);
+    o[0] = __builtin_nontemporal_load(gmem(p));
   }
 }
 
 template <int V>
 __device__ __forceinline__ void storev(float *p, const float (&o)[V]) {
   if constexpr (V == 8) {
-    *(GG_GLOBAL gg_v4f *)p = (gg_v4f){o[0], o[1], o[2], o[3]};
-    *(GG_GLOBAL gg_v4f *)(p + 4) = (gg_v4f){o[4], o[5], o[6], o[7]};
+    __builtin_nontemporal_store((gg_v4f){o[0], o[1], o[2], o[3]}, (GG_GLOBAL gg_v4f *)p);
+    __builtin_nontemporal_store((gg_v4f){o[4], o[5], o[6], o[7]}, (GG_GLOBAL gg_v4f *)(p + 4));
   } else if constexpr (V == 4) {
-    *(GG_GLOBAL gg_v4f *)p = (gg_v4f){o[0], o[1], o[2], o[3]};
+    __builtin_nontemporal_store((gg_v4f){o[0], o[1], o[2], o[3]}, (GG_GLOBAL gg_v4f *)p);
   } else if constexpr (V == 2) {
-    *(GG_GLOBAL gg_v2f *)p = (gg_v2f){o[0], o[1]};
+    __builtin_nontemporal_store((gg_v2f){o[0], o[1]}, (GG_GLOBAL gg_v2f *)p);
   } else {
-    *gmem(p) = o[0];
+    __builtin_nontemporal_store(o[0], gmem(p));
   }
 }
 
@@ -485,7 +489,7 @@ __device__ __forceinline__ void stage_pos(int h, uint32_t lane, uint32_t &p, uin
 // Loads of the stream, unconditional (a pixel past the image reads the last
 // pixel's run, which nothing stores back): no branch separates them from the
 // view gathers, so the compiler's in-order wait counts need not assume that
-// these long-latency loads precede every gather.
+// these long-latency loads precede every gather.  Non-temporal, as loadv.
 template <int V>
 __device__ __forceinline__ void stage_load(const float *src, uint32_t pix0, uint32_t npix,
                                            size_t run0, int D, gg_v4f (&r)[VolStage<V>::kIssues]) {
@@ -495,7 +499,7 @@ __device__ __forceinline__ void stage_load(const float *src, uint32_t pix0, uint
     uint32_t p, j;
     stage_pos<V>(h, lane, p, j);
     const uint32_t pp = min(pix0 + p, npix - 1u);
-    r[h] = *(const GG_GLOBAL gg_v4f *)(src + (size_t)pp * D + run0 + 4u * j);
+    r[h] = __builtin_nontemporal_load((const GG_GLOBAL gg_v4f *)(src + (size_t)pp * D + run0 + 4u * j));
   }
 }
 
@@ -539,7 +543,8 @@ __device__ __forceinline__ void stage_store(const float *st, float *dst, uint32_
     uint32_t p, j;
     stage_pos<V>(h, lane, p, j);
     const gg_v4f v = lds_get4(st + (p * VolStage<V>::kRowF4 + j) * 4);
-    if (pix0 + p < npix) *(GG_GLOBAL gg_v4f *)(dst + (size_t)(pix0 + p) * D + run0 + 4u * j) = v;
+    if (pix0 + p < npix)
+      __builtin_nontemporal_store(v, (GG_GLOBAL gg_v4f *)(dst + (size_t)(pix0 + p) * D + run0 + 4u * j));
   }
 }
 

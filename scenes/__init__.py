@@ -565,7 +565,9 @@ def coarse_frame(seq, t, factor=2, procs=1):
         import multiprocessing as mp
         with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
             views = pool.map(_coarse_job, jobs)
-    return np.stack([d for d, _ in views]), np.stack([c for _, c in views])
+    # C order whatever the rendering's strides (one process returns views of them)
+    return (np.ascontiguousarray(np.stack([d for d, _ in views])),
+            np.ascontiguousarray(np.stack([c for _, c in views])))
 
 
 def config2(seed=0):
