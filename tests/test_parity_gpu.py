@@ -45,8 +45,35 @@ def check_splat(c, depth, rgb):
     close(out["rgb"].cpu().numpy(), ref["rgb"], what="rgb")
     close(out["alpha"].cpu().numpy(), ref["alpha"], what="alpha")
     tape = out["tape"].cpu().numpy()
-    close(tape[:, 0], ref["tape"][:, 0], what="tape sum G")
+    check_tape(tape, ref["tape"])
     return out, ref
+
+
+def check_tape(tape, ref):
+    """Every plane of the splat tape: sum G, the sum of log(1 - G) over members with G < 1 (fixed
+    point here, FP32 in the oracle) and the count of members with G == 1.  The device's and the
+    host's expf may differ by an ulp; the paper fixes no exponential, so both are correct.  Near
+    G = 1 that ulp moves a member between the count and the log sum, and it changes log(1 - G) by
+    up to 2^-23 / (1 - G): the log sum is ill-conditioned there.  So the test checks what is
+    well-conditioned -- the transmittance prod(1 - G) = exp(log sum) (0 with a member at G = 1),
+    to n ulps absolute -- and the log sum where the counts agree, to its conditioning: at most
+    2^-23 / (1 - G) per member, which the pixel's transmittance bounds (each 1 - G is at least the
+    product) for up to 24 members."""
+    close(tape[:, 0], ref[:, 0], what="tape sum G")
+    t_gpu = np.where(tape[:, 2] == 0, np.exp(tape[:, 1].astype(np.float64)), 0.0)
+    t_ref = np.where(ref[:, 2] == 0, np.exp(ref[:, 1].astype(np.float64)), 0.0)
+    dt = np.abs(t_gpu - t_ref)
+    assert dt.max() <= 24 * 2.0 ** -24, f"transmittance differs by {dt.max():.3g}"
+    dc = ref[:, 2].astype(np.int64) - tape[:, 2].astype(np.int64)
+    covered = int((ref[:, 0] > 0).sum())
+    assert (dc != 0).sum() <= max(8, covered // 200), \
+        f"tape count of G == 1 differs at {(dc != 0).sum()} of {covered} covered pixels"
+    m = (dc == 0) & (t_ref > 1e-6)
+    g1 = tape[:, 1].astype(np.float64)[m]
+    r1 = ref[:, 1].astype(np.float64)[m]
+    bound = 1e-5 * np.abs(r1) + 24 * 2.0 ** -23 / t_ref[m]
+    bad = np.abs(g1 - r1) > bound
+    assert not bad.any(), f"tape sum log(1 - G): {bad.sum()} of {m.sum()} beyond their conditioning"
 
 
 def check_tsdf(c, depth, F_prev=None, W_prev=None, mask=None, pixels=None, ref_prev=None):
@@ -255,8 +282,8 @@ def test_standalone_extract_equals_fused():
 def test_repeat_runs_bitwise():
     c = scenes.config1()
     depth, rgb = to_dev(c)
-    outs = [gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"]) for _ in range(3)]
-    vols = [gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"]) for _ in range(3)]
+    outs = [gg.splat_views(c["src"], depth, rgb, c["tgt"], c["splat"]) for _ in range(10)]
+    vols = [gg.tsdf_integrate(c["src"], depth, c["tgt"], c["tsdf"]) for _ in range(10)]
     torch.cuda.synchronize()
     for o in outs[1:]:
         for key in ("win_idx", "depth", "rgb", "alpha", "tape"):
