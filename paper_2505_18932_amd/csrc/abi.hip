@@ -289,7 +289,7 @@ static TsdfLayout tsdf_layout(int K, int sw, int sh, int D, bool backward) {
   const size_t ns = (size_t)sw * sh;
   size_t o = 0;
   L.table = o;
-  o += up256(8 * ns * K);
+  o += up256(8 * table_view_records(sw, sh) * K);
   L.bins = o;
   o += up256(8 * (size_t)D);
   if (backward) {
@@ -752,6 +752,11 @@ static void make_integrate_args(IntegrateArgs &a, const gg_camera *src, int32_t 
   a.cap = prm.weight_cap;
   a.carry = F_prev != nullptr;
   a.exact_only = fast_reciprocal_safe(a.views, K, tgt, prm.z_far) ? 0 : 1;
+  // Structured view-table loads take three vector instructions per sample off the carried
+  // fusion, whose issue slots bound it at up to four views; at more views the texture address
+  // unit is the tighter bound and they lose, and the forms without a carry would lose a
+  // wavefront per SIMD to the extra address registers (measured; results are the same).
+  a.rows = (table_rows_ok(sw) && F_prev != nullptr && K <= 4) ? 1 : 0;
 }
 
 // The view table (per source pixel: usable depth, fusion weight) and the
@@ -1277,7 +1282,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     vs.pw_shift = pick_pw_shift(vs.ppb, 16);
     vs.band_px = kDefaultBandPixels;
     o_table[i] = off;
-    off += up256(8 * (size_t)sw * sh * K);
+    off += up256(8 * table_view_records(sw, sh) * K);
     o_bins[i] = off;
     off += up256(8 * (size_t)D);
     if (it.rgb) {

@@ -91,6 +91,37 @@ __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off)
   return make_float2(v.x, v.y);
 }
 
+// The view table: per view Hs rows of Ws + 1 records, the last record of each
+// row (0, 0) -- no usable depth, no weight -- so that a sample whose column
+// falls outside the image may read that record instead of being tested.
+__host__ __device__ constexpr uint32_t table_pitch(int32_t Ws) { return (uint32_t)Ws + 1u; }
+__host__ __device__ constexpr size_t table_view_records(int32_t Ws, int32_t Hs) {
+  return (size_t)Hs * table_pitch(Ws);
+}
+// A structured buffer resource holds its stride (the row pitch, bytes) in a
+// 14-bit field: rows of at most 2047 records.
+__host__ __device__ constexpr bool table_rows_ok(int32_t Ws) { return table_pitch(Ws) * 8u <= 16383u; }
+
+// Structured buffer load (row index and byte offset within the row; the
+// hardware multiplies the index by the stride).  A row index at or past the
+// resource's row count reads zeros and touches no memory; the offset is not
+// checked against the stride, so the caller keeps it inside the row.
+extern "C" __device__ gg_v2f gg_struct_buffer_load_v2f32(__amdgpu_buffer_rsrc_t rsrc,
+                                                          int32_t vindex, int32_t voffset,
+                                                          int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v2f32");
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_of(const void *p, uint32_t pitch_bytes,
+                                                          uint32_t rows) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)pitch_bytes, (int)rows,
+                                           0x00020000);
+}
+
+__device__ __forceinline__ float2 rload2(__amdgpu_buffer_rsrc_t r, uint32_t row, uint32_t off) {
+  const gg_v2f v = gg_struct_buffer_load_v2f32(r, (int32_t)row, (int32_t)off, 0, 0);
+  return make_float2(v.x, v.y);
+}
+
 __device__ __forceinline__ uint32_t gatomic_add(uint32_t *p, uint32_t v) {
   return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -145,7 +176,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t wg, uint32_t n) {
 
 struct ConfArgs {
   const float *depth;  // K x Hs x Ws
-  float2 *table;       // K x Hs x Ws: (usable depth or +inf, omega)
+  float2 *table;       // K x Hs x (Ws + 1): (usable depth or +inf, omega), rows closed by (0, 0)
   int32_t Ws, Hs, K;
   int32_t radius;      // (w - 1) / 2
   float tw2;           // conf_tau^2
@@ -155,7 +186,7 @@ struct ConfArgs {
 
 struct IntegrateArgs {
   Proj views[GG_MAX_VIEWS];  // target -> view k
-  const float2 *table;       // K x Ns view table
+  const float2 *table;       // K x Hs x (Ws + 1) view table (table_pitch)
   const float2 *bins;        // D x (z_d, tau_d)
   const float *mask;         // Ht x Wt or null
   const float *F_prev;       // may alias F
@@ -178,6 +209,7 @@ struct IntegrateArgs {
   float decay, cap;
   int32_t carry;
   int32_t exact_only;  // 1: every sample takes IEEE division (extreme depths)
+  int32_t rows;        // 1: the launch reads the view tables with structured loads
 };
 
 struct ExtractArgs {
@@ -197,7 +229,7 @@ struct ExtractArgs {
 
 struct TsdfBackArgs {
   Proj views[GG_MAX_VIEWS];
-  const float2 *table;   // recomputed view table
+  const float2 *table;   // recomputed view table, K x Hs x (Ws + 1)
   const float2 *bins;
   const float *depth;
   const float *F;
@@ -219,7 +251,7 @@ struct TsdfBackArgs {
 // Volume-free raymarch (raymarch.hip).
 struct RaymarchArgs {
   Proj views[GG_MAX_VIEWS];  // target -> view k
-  const float2 *table;       // K x Ns view table
+  const float2 *table;       // K x Hs x (Ws + 1) view table (table_pitch)
   int32_t K, Ws, Hs;
   uint32_t ns, npix;
   FastDiv wt_div;            // by Wt

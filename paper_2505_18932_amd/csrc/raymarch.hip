@@ -29,11 +29,13 @@ __device__ __forceinline__ float2 march_sample(const RaymarchArgs &a, int k, flo
   const float fWs = (float)a.Ws, fHs = (float)a.Hs;
   uint32_t off;
   // recip_rn unless a lane's depth lies in (0, 2^-100] (wave-uniform choice)
+  const uint32_t pitch = table_pitch(a.Ws);
   if (kExact || __any(Z > 0.0f && !(Z > kRecipLo)))
-    off = sample_offset<kDivide>(X0, X1, Z, (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs);
+    off = sample_offset<kDivide>(X0, X1, Z, (uint32_t)a.Ws, (uint32_t)a.Hs, pitch, fWs, fHs);
   else
-    off = sample_offset<kChecked>(X0, X1, Z, (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs);
-  return bload2(buffer_of(a.table + (size_t)k * a.ns, a.ns * 8u), off);
+    off = sample_offset<kChecked>(X0, X1, Z, (uint32_t)a.Ws, (uint32_t)a.Hs, pitch, fWs, fHs);
+  const size_t rec = table_view_records(a.Ws, a.Hs);
+  return bload2(buffer_of(a.table + (size_t)k * rec, (uint32_t)(rec * 8u)), off);
 }
 
 __device__ __forceinline__ void march_accumulate(float Z, float2 e, float tau, float &S,

@@ -52,16 +52,25 @@ int launch_conf(const ConfArgs &a, hipStream_t s) {
   return check_hip(hipGetLastError(), "conf_kernel");
 }
 
-template <int V, int KC, bool kExact, bool kStage, int kCarry>
+template <int V, int KC, bool kExact, bool kStage, int kCarry, bool kRows = false>
 __global__ __launch_bounds__(1024) void integrate_kernel(IntegrateArgs a) {
   extern __shared__ float smem[];
-  integrate_tile<V, KC, kExact, kStage, kCarry>(a, band_tile(a, xcd_tile(blockIdx.x, a.nblocks)),
-                                                smem);
+  integrate_tile<V, KC, kExact, kStage, kCarry, kRows>(
+      a, band_tile(a, xcd_tile(blockIdx.x, a.nblocks)), smem);
 }
 
 template <int V, int KC, bool kStage, int kCarry>
 static void launch_integrate_vk(const IntegrateArgs &a, uint32_t threads, size_t shm,
                                 hipStream_t s) {
+  // structured view-table loads: only in the staged, carried forms with up to four views
+  // (the host sets a.rows where they pay; elsewhere the specialisation does not exist)
+  if constexpr (kStage && kCarry == 1 && KC >= 1 && KC <= 4) {
+    if (a.rows && !a.exact_only) {
+      hipLaunchKernelGGL((integrate_kernel<V, KC, false, kStage, kCarry, true>), dim3(a.nblocks),
+                         dim3(threads), shm, s, a);
+      return;
+    }
+  }
   if (a.exact_only)
     hipLaunchKernelGGL((integrate_kernel<V, KC, true, kStage, kCarry>), dim3(a.nblocks),
                        dim3(threads), shm, s, a);
@@ -226,7 +235,8 @@ __device__ __forceinline__ void voxel_adjoint(const TsdfBackArgs &a, uint32_t pi
     const float u = X0 * inv, w = X1 * inv;
     if (!(u >= 0.0f && u < fWs && w >= 0.0f && w < fHs)) continue;
     const uint32_t q = (uint32_t)w * (uint32_t)a.Ws + (uint32_t)u;
-    const float2 e = a.table[(size_t)k * a.ns + q];
+    const float2 e = a.table[(size_t)k * table_view_records(a.Ws, a.Hs) +
+                             (size_t)(uint32_t)w * table_pitch(a.Ws) + (uint32_t)u];
     const float s = e.x - Z;
     if (s < -tau) continue;
     const float c = fminf(s, tau);

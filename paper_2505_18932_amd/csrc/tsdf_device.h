@@ -125,7 +125,9 @@ __device__ __forceinline__ void conf_tile(const ConfArgs &a, int k, int bx, int 
       const float om = (nu == 0.0f) ? 1.0f : fminf(a.scale / sqrtf(nu / a.n2), 1.0f);
       rec = make_float2(dq, om);
     }
-    gstore2(a.table + (size_t)k * a.Ws * a.Hs + (size_t)j * a.Ws + i, rec);
+    float2 *row = a.table + (size_t)k * table_view_records(a.Ws, a.Hs) + (size_t)j * table_pitch(a.Ws);
+    gstore2(row + i, rec);
+    if (i == a.Ws - 1) gstore2(row + a.Ws, make_float2(0.0f, 0.0f));  // the row's closing record
   }
   __syncthreads();  // the tile may be restaged by the caller's next iteration
 }
@@ -279,17 +281,19 @@ enum : int {
   kDivide = 2,   // IEEE division
 };
 
-// Byte offset of the sample's view-table record, kOutOfRange if none.
+// Byte offset of the sample's view-table record within the view's table
+// (rows of `pitch` records), kOutOfRange if none.
 template <int kMode>
 __device__ __forceinline__ uint32_t sample_offset(float X0, float X1, float Z, uint32_t Ws,
-                                                  uint32_t Hs, float fWs, float fHs) {
+                                                  uint32_t Hs, uint32_t pitch, float fWs,
+                                                  float fHs) {
   if constexpr (kMode == kDivide) {
     uint32_t off = kOutOfRange;
     if (Z > 0.0f) {
       const float iv = 1.0f / Z;
       const float u = X0 * iv, w = X1 * iv;
       if (u >= 0.0f && u < fWs && w >= 0.0f && w < fHs)
-        off = ((uint32_t)w * Ws + (uint32_t)u) << 3;
+        off = ((uint32_t)w * pitch + (uint32_t)u) << 3;
     }
     return off;
   } else {
@@ -297,8 +301,37 @@ __device__ __forceinline__ uint32_t sample_offset(float X0, float X1, float Z, u
     const uint32_t i = (uint32_t)floor_i32(X0 * inv), j = (uint32_t)floor_i32(X1 * inv);
     bool ok = i < Ws && j < Hs;
     if constexpr (kMode == kChecked) ok = ok && (Z > kRecipLo);
-    // sizes are at most 16384 (host check): Ws * 8 < 2^24, the offset < 2^31
-    return ok ? __umul24(j, Ws << 3) + (i << 3) : kOutOfRange;
+    // sizes are at most 16384 (host check): pitch * 8 < 2^24, the offset < 2^31
+    return ok ? __umul24(j, pitch << 3) + (i << 3) : kOutOfRange;
+  }
+}
+
+// The sample's record as (row, byte offset in the row) for a structured
+// load: a row outside [0, Hs) -- a negative floor is a huge unsigned row --
+// is dropped by the load's range check, and a column outside [0, Ws) is
+// clamped to Ws, the row's closing record (0, 0).  Either way the sample
+// reads (0, 0), exactly what the range-checked raw load gives it, with no
+// test of its own.
+template <int kMode>
+__device__ __forceinline__ void sample_row(float X0, float X1, float Z, uint32_t Ws, float fWs,
+                                           float fHs, uint32_t &row, uint32_t &off) {
+  if constexpr (kMode == kDivide) {
+    row = 0xffffffffu;
+    off = 0u;
+    if (Z > 0.0f) {
+      const float iv = 1.0f / Z;
+      const float u = X0 * iv, w = X1 * iv;
+      if (u >= 0.0f && u < fWs && w >= 0.0f && w < fHs) {
+        row = (uint32_t)w;
+        off = (uint32_t)u << 3;
+      }
+    }
+  } else {
+    const float inv = recip_rn(Z);
+    const uint32_t i = (uint32_t)floor_i32(X0 * inv), j = (uint32_t)floor_i32(X1 * inv);
+    row = j;
+    if constexpr (kMode == kChecked) row = (Z > kRecipLo) ? j : 0xffffffffu;
+    off = min(i, Ws) << 3;
   }
 }
 
@@ -327,25 +360,45 @@ __device__ __forceinline__ int view_mode(const Proj &P, float px, float py, cons
 // One view's samples of the V voxels: depths and table gathers (left in
 // flight for the caller).  A sample with no pixel reads the record (0, 0)
 // from the range-checked load, whose zero weight drops it.
-template <int V, int kMode>
+// kRows: the view's table read with structured loads (rows of at most 2047
+// records), else with range-checked raw loads.
+template <int V, int kMode, bool kRows>
 __device__ __forceinline__ void view_samples(const IntegrateArgs &a, int k, float px, float py,
                                              const float (&z)[V], float (&Z)[V],
                                              float2 (&e)[V]) {
   const Proj &P = a.views[k];
   float h0, h1, h2;
   ray_of(P, px, py, h0, h1, h2);
-  const __amdgpu_buffer_rsrc_t tab = buffer_of(a.table + (size_t)k * a.ns, a.ns * 8u);
+  const uint32_t pitch = table_pitch(a.Ws);
+  const float2 *view = a.table + (size_t)k * table_view_records(a.Ws, a.Hs);
   const float fWs = (float)a.Ws, fHs = (float)a.Hs;
-  uint32_t off[V];
+  if constexpr (kRows) {
+    const __amdgpu_buffer_rsrc_t tab = rows_of(view, pitch * 8u, (uint32_t)a.Hs);
+    uint32_t row[V], off[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const float X0 = fmaf(z[v], h0, P.c[0]);
-    const float X1 = fmaf(z[v], h1, P.c[1]);
-    Z[v] = fmaf(z[v], h2, P.c[2]);
-    off[v] = sample_offset<kMode>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, fWs, fHs);
+    for (int v = 0; v < V; ++v) {
+      const float X0 = fmaf(z[v], h0, P.c[0]);
+      const float X1 = fmaf(z[v], h1, P.c[1]);
+      Z[v] = fmaf(z[v], h2, P.c[2]);
+      sample_row<kMode>(X0, X1, Z[v], (uint32_t)a.Ws, fWs, fHs, row[v], off[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) e[v] = rload2(tab, row[v], off[v]);
+  } else {
+    const __amdgpu_buffer_rsrc_t tab =
+        buffer_of(view, (uint32_t)(table_view_records(a.Ws, a.Hs) * 8u));
+    uint32_t off[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const float X0 = fmaf(z[v], h0, P.c[0]);
+      const float X1 = fmaf(z[v], h1, P.c[1]);
+      Z[v] = fmaf(z[v], h2, P.c[2]);
+      off[v] = sample_offset<kMode>(X0, X1, Z[v], (uint32_t)a.Ws, (uint32_t)a.Hs, pitch, fWs,
+                                    fHs);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) e[v] = bload2(tab, off[v]);
   }
-#pragma unroll
-  for (int v = 0; v < V; ++v) e[v] = bload2(tab, off[v]);
 }
 
 // Accumulate one view's samples: s = D_k - z_k, occlusion cut (s < -tau:
@@ -371,7 +424,7 @@ __device__ __forceinline__ void view_accumulate(const float (&Z)[V], const float
 // after_issue() (the caller's own loads, so that in-order load completion
 // lets the gathers be consumed while those are still in flight), then the
 // samples are accumulated in view order.
-template <int V, int G, int kMode, typename AfterIssue>
+template <int V, int G, int kMode, bool kRows, typename AfterIssue>
 __device__ __forceinline__ void fuse_group(const IntegrateArgs &a, int k0, float px, float py,
                                            const float (&z)[V], const float (&tau)[V],
                                            float (&S)[V], float (&Wo)[V],
@@ -379,7 +432,7 @@ __device__ __forceinline__ void fuse_group(const IntegrateArgs &a, int k0, float
   float Z[G][V];
   float2 e[G][V];
 #pragma unroll
-  for (int g = 0; g < G; ++g) view_samples<V, kMode>(a, k0 + g, px, py, z, Z[g], e[g]);
+  for (int g = 0; g < G; ++g) view_samples<V, kMode, kRows>(a, k0 + g, px, py, z, Z[g], e[g]);
   after_issue();
 #pragma unroll
   for (int g = 0; g < G; ++g) view_accumulate<V>(Z[g], e[g], tau, S, Wo);
@@ -398,23 +451,29 @@ constexpr int view_group() {
 // View count KC > 0 known at compile time, every sample in front of its
 // view: views in unrolled groups, the caller's loads issued after the first
 // group's gathers.
-template <int V, int KC, typename AfterIssue>
+template <int V, int KC, bool kRows, typename AfterIssue>
 __device__ __forceinline__ void fuse_views_in_front(const IntegrateArgs &a, float px, float py,
                                                     const float (&z)[V], const float (&tau)[V],
                                                     float (&S)[V], float (&Wo)[V],
                                                     AfterIssue &&after_issue) {
   constexpr int G = view_group<KC, V>();
-  fuse_group<V, G, kInFront>(a, 0, px, py, z, tau, S, Wo, after_issue);
+  fuse_group<V, G, kInFront, kRows>(a, 0, px, py, z, tau, S, Wo, after_issue);
 #pragma unroll
   for (int k0 = G; k0 < KC; k0 += G)
-    fuse_group<V, G, kInFront>(a, k0, px, py, z, tau, S, Wo, [] {});
+    fuse_group<V, G, kInFront, kRows>(a, k0, px, py, z, tau, S, Wo, [] {});
 }
 
 // KC > 0 and every sample of the wave in front of every view (one
 // wave-uniform test): the unrolled straight-line variant.  Otherwise (and
 // for a runtime view count, KC == 0, or under kExact) one view at a time in
 // a loop, each in its own wave-uniform mode, the caller's loads first.
-template <int V, int KC, bool kExact, typename AfterIssue>
+//
+// kRows: every view table read with structured loads (rows_of / rload2),
+// which replace the per-sample bounds tests with the row index's range check
+// and a clamp of the column onto the row's closing record: three vector
+// instructions fewer per sample, for two registers per address in flight and
+// more work at the texture address unit (the host picks it where that pays).
+template <int V, int KC, bool kExact, bool kRows, typename AfterIssue>
 __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, float py,
                                             const float (&z)[V], const float (&tau)[V],
                                             float (&S)[V], float (&Wo)[V],
@@ -428,7 +487,7 @@ __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, fl
       front = front && lo > kRecipLo;
     }
     if (__builtin_expect(__all(front), 1)) {
-      fuse_views_in_front<V, KC>(a, px, py, z, tau, S, Wo, after_issue);
+      fuse_views_in_front<V, KC, kRows>(a, px, py, z, tau, S, Wo, after_issue);
       return;
     }
   }
@@ -438,13 +497,14 @@ __device__ __forceinline__ void fuse_voxels(const IntegrateArgs &a, float px, fl
   for (int k = 0; k < K; ++k) {
     const int mode = kExact ? kDivide : view_mode<V>(a.views[k], px, py, z);
     if (mode == kInFront)
-      fuse_group<V, 1, kInFront>(a, k, px, py, z, tau, S, Wo, [] {});
+      fuse_group<V, 1, kInFront, kRows>(a, k, px, py, z, tau, S, Wo, [] {});
     else if (mode == kChecked)
-      fuse_group<V, 1, kChecked>(a, k, px, py, z, tau, S, Wo, [] {});
+      fuse_group<V, 1, kChecked, kRows>(a, k, px, py, z, tau, S, Wo, [] {});
     else
-      fuse_group<V, 1, kDivide>(a, k, px, py, z, tau, S, Wo, [] {});
+      fuse_group<V, 1, kDivide, kRows>(a, k, px, py, z, tau, S, Wo, [] {});
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // The volume stream through LDS.  In the compute layout a wavefront holds 16
@@ -563,11 +623,13 @@ __host__ __device__ constexpr size_t integrate_lds_bytes(uint32_t threads, uint3
 }
 
 // kCarry: 1 the previous volume is carried, 0 it is not, -1 a.carry decides
-// at run time (the staged form takes it at compile time).
-template <int V, int KC, bool kExact, bool kStage = false, int kCarry = -1>
+// at run time (the staged form takes it at compile time).  kRows: structured
+// view-table loads (see fuse_voxels; rows of at most 2047 records).
+template <int V, int KC, bool kExact, bool kStage = false, int kCarry = -1, bool kRows = false>
 __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t tile, float *smem) {
   static_assert(!kStage || V == 4 || V == 8, "staged volume stream needs V = 4 or 8");
   static_assert(!kStage || kCarry >= 0, "the staged form takes the carry at compile time");
+  static_assert(!kRows || KC > 0, "structured loads in the compile-time view-count forms only");
   float *sF = smem;
   float *sW = smem + blockDim.x;
   int *sBest = reinterpret_cast<int *>(smem + 2 * blockDim.x);
@@ -657,7 +719,8 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
     // stores nothing) and takes part in the wavefront's exchanges
     const uint32_t y = fdiv(pix, a.wt_div);
     const uint32_t x = pix - y * a.wt_div.d;
-    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
+    fuse_voxels<V, KC, kExact, kRows>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo,
+                                        load_volume);
     if constexpr (kCarry == 1) {
       stage_put_stream<V>(sVol, rF);
       stage_put_stream<V>(sVol + VolStage<V>::kArray, rW);
@@ -682,7 +745,8 @@ __device__ __forceinline__ void integrate_tile(const IntegrateArgs &a, uint32_t 
   } else if (active) {
     const uint32_t y = fdiv(pix, a.wt_div);
     const uint32_t x = pix - y * a.wt_div.d;
-    fuse_voxels<V, KC, kExact>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo, load_volume);
+    fuse_voxels<V, KC, kExact, kRows>(a, (float)x + 0.5f, (float)y + 0.5f, z, tau, S, Wo,
+                                        load_volume);
     const float m = a.mask ? fmaxf(1.0f - mraw, 0.0f) : 1.0f;
 #pragma unroll
     for (int v = 0; v < V; ++v) {

@@ -219,6 +219,18 @@ def test_library_maxima():
     check_tsdf(c, depth)
 
 
+def test_carried_fusion_both_table_forms():
+    """The carried fusion with up to four views reads the view tables with structured loads
+    where a table row (the image width plus its closing record) fits the resource's stride
+    field, 2047 records, and with range-checked raw loads beyond; widths straddle the limit,
+    a carried second frame included, and both forms give the oracle's volume bitwise."""
+    for w in (2046, 2047, 4100):
+        c = small(w=w, h=3, k=2, bins=32)
+        depth, _ = to_dev(c)
+        (F, W, _, _), ref = check_tsdf(c, depth)
+        check_tsdf(c, depth, F_prev=F, W_prev=W, ref_prev=ref)
+
+
 def test_single_view_and_many_views():
     for k in (1, 8):
         c = small(k=k)
