@@ -260,11 +260,13 @@ def streaming_sequence(procs, frames=STREAM_FRAMES):
     return c, np.stack([d for d, _ in fr]), np.stack([r for _, r in fr])
 
 
-def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3):
+def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3, tile=None):
     """The streaming workload as a sequence: every frame runs the forward
     (splat, fusion with the volume carried in place, fused extraction) and
     the backward (the three adjoints for fixed random upstream gradients),
-    on one stream, HIP events around each half.  Returns per-frame means."""
+    on one stream, HIP events around each half.  The fusion takes ``tile``,
+    else the launch shape the autotuner picks for this workload.  Returns
+    per-frame means."""
     src, tgt, sp, tp = c["src"], c["tgt"], c["splat"], c["tsdf"]
     nf = depth_h.shape[0]
     depth = torch.from_numpy(depth_h).to(dev)
@@ -277,6 +279,9 @@ def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3):
     ws_b = torch.empty(gg.workspace_size(4, K, Ws, Hs, Wd, H, D), dtype=torch.uint8, device=dev)
     ws_s = torch.empty(gg.workspace_size(1, K, Ws, Hs, Wd, H, 2, gg.splat_params(sp)),
                        dtype=torch.uint8, device=dev)
+    if tile is None:
+        from paper_2505_18932_amd import autotune
+        tile = autotune.tune_plain(src, depth[0], tgt, tp, reps=3, use_cache=False)[0]
     so = gg.splat_views(src, depth[0], rgb[0], tgt, sp, ws=ws_s)
     g_rgb, g_z, g_a = (torch.randn_like(so["rgb"]), torch.randn_like(so["depth"]),
                        torch.randn_like(so["alpha"]))
@@ -289,7 +294,7 @@ def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3):
         gg.splat_views(src, depth[t], rgb[t], tgt, sp, out=so, ws=ws_s)
         kw = dict(F_prev=F, W_prev=Wv) if carry else {}
         _, _, d, b = gg.tsdf_integrate(src, depth[t], tgt, tp, F=F, W=Wv, ws=ws_t,
-                                       tuning=TILE[0], **kw)
+                                       tuning=tile, **kw)
         ev[1].record()
         gg.splat_views_backward(src, depth[t], rgb[t], tgt, sp, so, g_rgb, g_z, g_a)
         g2 = gg.tsdf_extract_depth_backward(tgt, tp, F, Wv, b, gdep)
@@ -313,6 +318,7 @@ def streaming_leg(gg, torch, dev, c, depth_h, rgb_h, warm=3):
             "ms_per_frame": round(tf + tb, 3), "wall_ms_per_frame": round(wall, 3),
             "frames": nf, "fwd_ms_range": [round(min(fwd_ms), 3), round(max(fwd_ms), 3)],
             "bwd_ms_range": [round(min(bwd_ms), 3), round(max(bwd_ms), 3)],
+            "fusion_tile": list(tile),
             "workload": "streaming 1920x1080 K=8 D=256, %d consecutive frames, volume carried, "
                         "forward + backward every frame (views rendered at half resolution and "
                         "repeated to full size)" % nf}
@@ -934,7 +940,9 @@ def main():
         r, tf, tb = bwd_fwd_ratio(gg, torch, dev)
         out["bwd_fwd"] = {"ratio": round(r, 3), "fwd_ms": round(tf, 3), "bwd_ms": round(tb, 3),
                           "workload": "differentiation 640x360 K=4 D=96"}
-        out["bwd_fwd_large"] = streaming_leg(gg, torch, dev, *large)
+        # the streaming workload's own tuned launch shape, unless the command pins one
+        out["bwd_fwd_large"] = streaming_leg(gg, torch, dev, *large,
+                                             tile=TILE[0] if args.tile else None)
         del large
         torch.cuda.empty_cache()
     del F, Wv, sout

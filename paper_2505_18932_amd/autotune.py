@@ -31,8 +31,8 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 # order in pixels); 0 = default
 PLAIN_CANDIDATES = [(0, 0, 4, 0), (8, 8, 4, 0), (16, 8, 4, 0), (16, 16, 4, 0), (32, 8, 4, 0),
                     (32, 16, 4, 0), (0, 0, 8, 0), (16, 16, 8, 0), (32, 16, 8, 0), (32, 32, 8, 0),
-                    (64, 16, 8, 0), (64, 32, 8, 0), (16, 16, 8, 128), (16, 16, 8, 512),
-                    (16, 16, 8, 65536), (32, 16, 8, 128)]
+                    (64, 16, 8, 0), (64, 32, 8, 0), (16, 16, 8, 128), (16, 16, 8, 192),
+                    (16, 16, 8, 512), (16, 16, 8, 65536), (32, 16, 8, 128)]
 # (target pixels per fusion workgroup, resident workgroups per compute unit of
 # the persistent splat binning phases, bins per thread, graph branches);
 # 0 = default
