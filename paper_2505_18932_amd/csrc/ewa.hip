@@ -187,6 +187,7 @@ struct EwaLds {
   unsigned long long key[kEwaSortCap];
   float4 rec[2][64];
   float z[64];
+  uint8_t idx[4][64];  // per quadrant of the tile: the staged entries that may reach it, in order
 };
 
 // Ascending bitonic sort of L.key[0 .. N) (N a power of two, 64 <= N <=
@@ -264,13 +265,42 @@ __device__ const unsigned long long *global_sort(EwaLds &L, unsigned long long *
   return src;
 }
 
+// Whether the Gaussian of a staged record may take a term at a pixel of the
+// 4 x 4 quadrant whose first pixel is (qx, qy): a term needs alpha >= 1/255,
+// so d^T S^-1 d <= 2 ln 255 < 11.1 and |dx| <= sqrt(11.1 S_xx), and it needs
+// |dx| <= rmax.  S_xx = M_yy / det M of the conic M = S^-1, whose entries the
+// record holds as Ah = -M_xx / 2, Ch = -M_yy / 2, Bn = -M_xy; the extent
+// takes 2% and a quarter pixel of margin for the rounding of this
+// reconstruction and of the tests (a conic so ill-conditioned that S_xx
+// comes out negative or NaN falls back to rmax: fminf drops the NaN).  The
+// test is a superset, so it never decides a term: skipping a record it
+// rejects leaves every pixel of the quadrant exactly as taking it would.
+__device__ __forceinline__ bool ewa_reaches(float4 A, float4 B, float rmax, float qx, float qy) {
+  const float det = 4.0f * (A.z * B.x) - A.w * A.w;
+  const float sxx = (-2.0f * B.x) / det, syy = (-2.0f * A.z) / det;
+  const float hx = fminf(sqrtf(11.32f * sxx), rmax) + 0.25f;
+  const float hy = fminf(sqrtf(11.32f * syy), rmax) + 0.25f;
+  // pixel centres qx + 0.5 .. qx + 3.5 against u +- hx, likewise in y
+  return (qx + 0.5f) - A.x <= hx && A.x - (qx + 3.5f) <= hx && (qy + 0.5f) - A.y <= hy &&
+         A.y - (qy + 3.5f) <= hy;
+}
+
+// One wavefront per (view, tile); its 64 lanes are the tile's four 4 x 4
+// quadrants (lanes 16 q .. 16 q + 15, row-major in each).  Each batch of 64
+// staged records is culled per quadrant (ewa_reaches) into an ordered list,
+// and each quadrant's 16 lanes composite only their own list: the wavefront
+// takes as many steps as the longest of the four instead of all 64, and
+// every pixel still sees, front to back, every record that can touch it.
 __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
   __shared__ EwaLds L;
   const int k = blockIdx.y;
   const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles);
   const uint32_t lane = threadIdx.x;
   const uint32_t ty = tile / (uint32_t)a.ntx, tx = tile - ty * (uint32_t)a.ntx;
-  const int x = (int)tx * kEwaTile + (int)(lane & 7u), y = (int)ty * kEwaTile + (int)(lane >> 3);
+  const uint32_t quad = lane >> 4, ql = lane & 15u;
+  const int qx0 = (int)tx * kEwaTile + 4 * (int)(quad & 1u);
+  const int qy0 = (int)ty * kEwaTile + 4 * (int)(quad >> 1);
+  const int x = qx0 + (int)(ql & 3u), y = qy0 + (int)(ql >> 2);
   const size_t seg = (size_t)k * a.ntiles + tile;
   const uint32_t off = min(gmem(a.tile_offset)[seg], a.cap);
   const uint32_t m = min(gmem(a.tile_count)[seg], a.cap - off);
@@ -293,20 +323,38 @@ __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
   float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, zs = 0.0f;
   bool done = x >= a.Wt || y >= a.Ht;
   const float4 *rec = a.rec + 2 * (size_t)k * a.ns;
+  const float tx0 = (float)((int)tx * kEwaTile), ty0 = (float)((int)ty * kEwaTile);
   for (uint32_t base = 0; base < m; base += 64) {
     if (__all(done)) break;
-    const uint32_t e = base + lane, nb = min(64u, m - base);
+    const uint32_t e = base + lane;
+    uint32_t reach = 0;  // bit q: the record may reach quadrant q
     if (e < m) {
       const unsigned long long key = in_lds ? L.key[e] : gmem(list)[e];
       const uint32_t q = (uint32_t)key;
       const gg_v4f r0 = *(const GG_GLOBAL gg_v4f *)(rec + 2 * (size_t)q);
       const gg_v4f r1 = *(const GG_GLOBAL gg_v4f *)(rec + 2 * (size_t)q + 1);
-      L.rec[0][lane] = make_float4(r0.x, r0.y, r0.z, r0.w);
-      L.rec[1][lane] = make_float4(r1.x, r1.y, r1.z, r1.w);
+      const float4 A = make_float4(r0.x, r0.y, r0.z, r0.w), B = make_float4(r1.x, r1.y, r1.z, r1.w);
+      L.rec[0][lane] = A;
+      L.rec[1][lane] = B;
       L.z[lane] = __uint_as_float((uint32_t)(key >> 32));
+#pragma unroll
+      for (uint32_t qd = 0; qd < 4; ++qd)
+        if (ewa_reaches(A, B, rmax, tx0 + 4.0f * (float)(qd & 1u), ty0 + 4.0f * (float)(qd >> 1)))
+          reach |= 1u << qd;
+    }
+    // each quadrant's list: the records that reach it, in staging (= front to back) order
+    uint32_t nq = 0;
+#pragma unroll
+    for (uint32_t qd = 0; qd < 4; ++qd) {
+      const unsigned long long b = __ballot((reach >> qd) & 1u);
+      if ((reach >> qd) & 1u)
+        L.idx[qd][__popcll(b & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+      if (qd == quad) nq = (uint32_t)__popcll(b);
     }
     __syncthreads();
-    for (uint32_t t = 0; t < nb; ++t) {
+    // each quadrant walks its own list; the wavefront runs as long as the longest
+    for (uint32_t s = 0; s < nq; ++s) {
+      const uint32_t t = L.idx[quad][s];
       const float4 A = L.rec[0][t], B = L.rec[1][t];
       const float dx = px - A.x, dy = py - A.y;
       const bool in = fabsf(dx) <= rmax && fabsf(dy) <= rmax;
