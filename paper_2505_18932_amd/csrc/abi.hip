@@ -1303,7 +1303,7 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
           conf.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)x, (uint16_t)y});
     if (it.rgb) {
       splat_items.push_back((uint32_t)i);
-      const uint32_t nb = ((uint32_t)(sw * sh) + 255u) / 256u;
+      const uint32_t nb = splat_bin_blocks((uint32_t)sw, (uint32_t)sh);
       for (int k = 0; k < K; ++k) {
         for (uint32_t b = 0; b < nb; ++b)
           bin.push_back(WorkItem{(uint16_t)i, (uint16_t)k, (uint16_t)(b & 0xffff), (uint16_t)(b >> 16)});

@@ -50,7 +50,7 @@ uint32_t splat_tiles_per_splat(float r_max) {
 
 int launch_splat_forward(SplatArgs &a, hipStream_t s) {
   const uint32_t n = (uint32_t)a.K * a.ntiles;
-  const dim3 gsrc((a.ns + 255) / 256, a.K);
+  const dim3 gsrc(splat_bin_blocks((uint32_t)a.Ws, (uint32_t)a.Hs), a.K);
   {
     KernelTimer t("splat_zero", s);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(min((n + 255) / 256, 1024u)), dim3(256), 0, s,

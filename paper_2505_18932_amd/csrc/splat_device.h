@@ -93,14 +93,35 @@ __device__ __forceinline__ uint32_t aggregated_slot(uint32_t *counters, uint32_t
   return base + rank;
 }
 
+// Source pixels of one binning workgroup (256 threads): four wavefronts of
+// kBinWave x kBinWave pixels side by side.  A square of neighbouring source
+// pixels lands on a compact target region, which touches fewer distinct
+// tiles than a run of 64 pixels along a row: fewer rounds of the
+// wavefront's per-tile grouping (aggregated_slot).  The order in which a
+// tile's list receives its entries changes nothing downstream: the z-test
+// keeps the minimum key and the blend sums integers.
+constexpr uint32_t kBinWave = 8;
+constexpr uint32_t kBinBlockW = 4 * kBinWave, kBinBlockH = kBinWave;
+
+__host__ __device__ constexpr uint32_t splat_bin_blocks_x(uint32_t Ws) {
+  return (Ws + kBinBlockW - 1) / kBinBlockW;
+}
+__host__ __device__ constexpr uint32_t splat_bin_blocks(uint32_t Ws, uint32_t Hs) {
+  return splat_bin_blocks_x(Ws) * ((Hs + kBinBlockH - 1) / kBinBlockH);
+}
+
 // Count (kFill = false) or list (kFill = true) the target tiles touched by
-// the footprints of source pixels blk * blockDim .. of view k.
+// the footprints of the source pixels of binning block blk of view k.
 template <bool kFill>
 __device__ __forceinline__ void splat_bin_block(const SplatArgs &a, int k, uint32_t blk) {
-  const uint32_t q = blk * blockDim.x + threadIdx.x;
+  const uint32_t nbx = splat_bin_blocks_x((uint32_t)a.Ws);
+  const uint32_t by = blk / nbx, bx = blk - by * nbx;  // wave-uniform
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t i = bx * kBinBlockW + wv * kBinWave + (lane % kBinWave);
+  const uint32_t j = by * kBinBlockH + lane / kBinWave;
+  const uint32_t q = j * (uint32_t)a.Ws + i;
   int tx0 = 0, ty0 = 0, nx = 0, n = 0;
-  if (q < a.ns) {
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
+  if (i < (uint32_t)a.Ws && j < (uint32_t)a.Hs) {
     const SplatGeom g = splat_geom(a.views[k], gmem(a.depth)[(size_t)k * a.ns + q], i, j, a);
     if (g.ok) {
       tx0 = g.a0 / kTile;
@@ -236,11 +257,15 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
   const size_t p = (size_t)py * a.Wt + px;
   const size_t o = (size_t)k * a.nt + p;
   const unsigned long long wk = zkey[t];
+  // The weighted means divide the fixed-point sums in FP32: each sum is
+  // rounded to FP32 (through FP64, whose conversion of a 64-bit integer is
+  // short), and 1 / (sum of G) multiplies the numerators.  Each result is
+  // within a few ulps of the exact quotient.
+  const float inv_g = wk == ~0ull ? 0.0f : 1.0f / (float)(double)(long long)sG[t];
   if (a.mask_in) {
     // the mask channel, like the colours; its maximum over the views as
     // float bits (non-negative floats order as unsigned integers)
-    const float m = wk == ~0ull ? 0.0f : (float)((double)(long long)lds.sM[t] /
-                                                 (double)(long long)lds.sG[t]);
+    const float m = wk == ~0ull ? 0.0f : (float)(double)(long long)lds.sM[t] * inv_g;
     if (a.out_mask) gmem(a.out_mask)[o] = m;
     if (a.out_mask_max)
       __hip_atomic_fetch_max(reinterpret_cast<GG_GLOBAL uint32_t *>(gmem(a.out_mask_max) + p),
@@ -262,15 +287,15 @@ __device__ __forceinline__ void raster_output(const SplatArgs &a, int k, int px,
   }
   win[o] = (int32_t)(uint32_t)(wk & 0xffffffffull);
   dep[o] = __uint_as_float((uint32_t)(wk >> 32));
-  const double sg = (double)(long long)sG[t];
-  rgb[p] = (float)((double)(long long)sR[t] / sg);
-  rgb[a.nt + p] = (float)((double)(long long)sGr[t] / sg);
-  rgb[2 * a.nt + p] = (float)((double)(long long)sB[t] / sg);
-  const double L = (double)(long long)sL[t] / kFixL;
-  alp[o] = sOnes[t] ? 1.0f : (float)(1.0 - exp(L));
+  rgb[p] = (float)(double)(long long)sR[t] * inv_g;
+  rgb[a.nt + p] = (float)(double)(long long)sGr[t] * inv_g;
+  rgb[2 * a.nt + p] = (float)(double)(long long)sB[t] * inv_g;
+  const double L = (double)(long long)sL[t] / kFixL;  // power-of-two scalings: exact
+  // alpha = 1 - prod(1 - G) = -(exp(L) - 1), with expm1 accurate where alpha is small
+  alp[o] = sOnes[t] ? 1.0f : -expm1f((float)L);
   if (a.out_tape) {
     GG_GLOBAL float *tp = gmem(a.out_tape + (size_t)k * 3 * a.nt);
-    tp[p] = (float)(sg / kFixG);
+    tp[p] = (float)((double)(long long)sG[t] / kFixG);
     tp[a.nt + p] = (float)L;
     tp[2 * a.nt + p] = (float)sOnes[t];
   }
