@@ -105,16 +105,21 @@ __device__ __forceinline__ EwaGauss ewa_gauss(const EwaArgs &a, int k, float D, 
 }
 
 // Count (kFill = false: also writes the records) or list (kFill = true) the
-// tiles touched by the Gaussians of source pixels blockIdx.x * 256 .. of
-// view blockIdx.y.
+// tiles touched by the Gaussians of the source pixels of binning block
+// blockIdx.x of view blockIdx.y: 8 x 8 squares of source pixels per
+// wavefront, as the splat's binning (the sort fixes the list order).
 template <bool kFill>
 __global__ __launch_bounds__(256) void ewa_bin_kernel(EwaArgs a) {
   const int k = blockIdx.y;
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nbx = splat_bin_blocks_x((uint32_t)a.Ws);
+  const uint32_t by = blockIdx.x / nbx, bx = blockIdx.x - by * nbx;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t i = bx * kBinBlockW + wv * kBinWave + (lane % kBinWave);
+  const uint32_t j = by * kBinBlockH + lane / kBinWave;
+  const uint32_t q = j * (uint32_t)a.Ws + i;
   int tx0 = 0, ty0 = 0, nx = 0, n = 0;
   unsigned long long key = 0;
-  if (q < a.ns) {
-    const uint32_t j = fdiv(q, a.ws_div), i = q - j * (uint32_t)a.Ws;
+  if (i < (uint32_t)a.Ws && j < (uint32_t)a.Hs) {
     const size_t o = (size_t)k * a.ns + q;
     const EwaGauss g = ewa_gauss(a, k, gmem(a.depth)[o], i, j);
     if (g.ok) {
@@ -183,11 +188,25 @@ __global__ void ewa_zero_kernel(uint32_t *p, uint32_t n) {
     gmem(p)[i] = 0u;
 }
 
+// v_writelane: `old` with lane `lane` set to the wave-uniform `value`.
+extern "C" __device__ int gg_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// The raster's cull unit: the tile's pixels in blocks of kEwaBlock x
+// kEwaBlock, each block's lanes walking their own list (2 x 2: sixteen
+// blocks of four lanes; measured faster than four 4 x 4 quadrants, whose
+// lists are longer, at the cost of 16 ballots per batch of records).
+constexpr int kEwaBlock = 2;
+constexpr int kEwaBlocksX = kEwaTile / kEwaBlock;
+constexpr int kEwaBlocks = kEwaBlocksX * kEwaBlocksX;
+constexpr int kEwaBlockLanes = kEwaBlock * kEwaBlock;
+
 struct EwaLds {
   unsigned long long key[kEwaSortCap];
   float4 rec[2][64];
   float z[64];
-  uint8_t idx[4][64];  // per quadrant of the tile: the staged entries that may reach it, in order
+  // per block of the tile: the staged entries that may reach it, in order;
+  // slot 64 takes the writes of the lanes whose entry does not
+  uint8_t idx[kEwaBlocks][65];
 };
 
 // Ascending bitonic sort of L.key[0 .. N) (N a power of two, 64 <= N <=
@@ -265,42 +284,59 @@ __device__ const unsigned long long *global_sort(EwaLds &L, unsigned long long *
   return src;
 }
 
-// Whether the Gaussian of a staged record may take a term at a pixel of the
-// 4 x 4 quadrant whose first pixel is (qx, qy): a term needs alpha >= 1/255,
-// so d^T S^-1 d <= 2 ln 255 < 11.1 and |dx| <= sqrt(11.1 S_xx), and it needs
-// |dx| <= rmax.  S_xx = M_yy / det M of the conic M = S^-1, whose entries the
-// record holds as Ah = -M_xx / 2, Ch = -M_yy / 2, Bn = -M_xy; the extent
-// takes 2% and a quarter pixel of margin for the rounding of this
-// reconstruction and of the tests (a conic so ill-conditioned that S_xx
-// comes out negative or NaN falls back to rmax: fminf drops the NaN).  The
-// test is a superset, so it never decides a term: skipping a record it
-// rejects leaves every pixel of the quadrant exactly as taking it would.
-__device__ __forceinline__ bool ewa_reaches(float4 A, float4 B, float rmax, float qx, float qy) {
+// The blocks of the tile (origin (tx0, ty0)) at whose pixels the Gaussian of
+// a staged record may take a term, as a bit mask (bit b: block b).  A term
+// needs alpha >= 1/255, so d^T S^-1 d <= 2 ln 255 < 11.1 and |dx| <=
+// sqrt(11.1 S_xx), and it needs |dx| <= rmax.  S_xx = M_yy / det M of the
+// conic M = S^-1, whose entries the record holds as Ah = -M_xx / 2, Ch =
+// -M_yy / 2, Bn = -M_xy; the extent takes 2% and a quarter pixel of margin
+// for the rounding of this reconstruction (the hardware's reciprocal and
+// square root, within an ulp or two, are well inside it) and of the tests
+// (a conic so ill-conditioned that S_xx comes out negative, infinite or NaN
+// falls back to rmax: fminf drops the NaN).  The test is a superset, so it
+// never decides a term: skipping a record it rejects leaves every pixel of
+// the block exactly as taking it would.  It is separable: a block's column
+// decides the x half, its row the y half.
+__device__ __forceinline__ uint32_t ewa_reach(float4 A, float4 B, float rmax, float tx0,
+                                              float ty0) {
   const float det = 4.0f * (A.z * B.x) - A.w * A.w;
-  const float sxx = (-2.0f * B.x) / det, syy = (-2.0f * A.z) / det;
-  const float hx = fminf(sqrtf(11.32f * sxx), rmax) + 0.25f;
-  const float hy = fminf(sqrtf(11.32f * syy), rmax) + 0.25f;
-  // pixel centres qx + 0.5 .. qx + 3.5 against u +- hx, likewise in y
-  return (qx + 0.5f) - A.x <= hx && A.x - (qx + 3.5f) <= hx && (qy + 0.5f) - A.y <= hy &&
-         A.y - (qy + 3.5f) <= hy;
+  const float rdet = __builtin_amdgcn_rcpf(det);
+  const float sxx = (-2.0f * B.x) * rdet, syy = (-2.0f * A.z) * rdet;
+  const float hx = fminf(__builtin_amdgcn_sqrtf(11.32f * sxx), rmax) + 0.25f;
+  const float hy = fminf(__builtin_amdgcn_sqrtf(11.32f * syy), rmax) + 0.25f;
+  // pixel centres q + 0.5 .. q + kEwaBlock - 0.5 against u +- h
+  constexpr float kLast = (float)kEwaBlock - 0.5f;
+  uint32_t cols = 0, rows = 0;
+#pragma unroll
+  for (int c = 0; c < kEwaBlocksX; ++c) {
+    const float qx = tx0 + (float)(kEwaBlock * c), qy = ty0 + (float)(kEwaBlock * c);
+    if ((qx + 0.5f) - A.x <= hx && A.x - (qx + kLast) <= hx) cols |= 1u << c;
+    if ((qy + 0.5f) - A.y <= hy && A.y - (qy + kLast) <= hy) rows |= 1u << c;
+  }
+  uint32_t reach = 0;
+#pragma unroll
+  for (int r = 0; r < kEwaBlocksX; ++r)
+    if ((rows >> r) & 1u) reach |= cols << (kEwaBlocksX * r);
+  return reach;
 }
 
-// One wavefront per (view, tile); its 64 lanes are the tile's four 4 x 4
-// quadrants (lanes 16 q .. 16 q + 15, row-major in each).  Each batch of 64
-// staged records is culled per quadrant (ewa_reaches) into an ordered list,
-// and each quadrant's 16 lanes composite only their own list: the wavefront
-// takes as many steps as the longest of the four instead of all 64, and
-// every pixel still sees, front to back, every record that can touch it.
+// One wavefront per (view, tile); its 64 lanes are the tile's blocks of
+// kEwaBlock x kEwaBlock pixels (the lanes of block b consecutive, row-major
+// in the block; blocks row-major in the tile).  Each batch of 64 staged
+// records is culled per block (ewa_reaches) into an ordered list, and each
+// block's lanes composite only their own list: the wavefront takes as many
+// steps as the longest list instead of all 64, and every pixel still sees,
+// front to back, every record that can touch it.
 __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
   __shared__ EwaLds L;
   const int k = blockIdx.y;
   const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles);
   const uint32_t lane = threadIdx.x;
   const uint32_t ty = tile / (uint32_t)a.ntx, tx = tile - ty * (uint32_t)a.ntx;
-  const uint32_t quad = lane >> 4, ql = lane & 15u;
-  const int qx0 = (int)tx * kEwaTile + 4 * (int)(quad & 1u);
-  const int qy0 = (int)ty * kEwaTile + 4 * (int)(quad >> 1);
-  const int x = qx0 + (int)(ql & 3u), y = qy0 + (int)(ql >> 2);
+  const uint32_t blk = lane / kEwaBlockLanes, ql = lane % kEwaBlockLanes;
+  const int qx0 = (int)tx * kEwaTile + kEwaBlock * (int)(blk % kEwaBlocksX);
+  const int qy0 = (int)ty * kEwaTile + kEwaBlock * (int)(blk / kEwaBlocksX);
+  const int x = qx0 + (int)(ql % kEwaBlock), y = qy0 + (int)(ql / kEwaBlock);
   const size_t seg = (size_t)k * a.ntiles + tile;
   const uint32_t off = min(gmem(a.tile_offset)[seg], a.cap);
   const uint32_t m = min(gmem(a.tile_count)[seg], a.cap - off);
@@ -327,7 +363,7 @@ __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
   for (uint32_t base = 0; base < m; base += 64) {
     if (__all(done)) break;
     const uint32_t e = base + lane;
-    uint32_t reach = 0;  // bit q: the record may reach quadrant q
+    uint32_t reach = 0;  // bit b: the record may reach block b
     if (e < m) {
       const unsigned long long key = in_lds ? L.key[e] : gmem(list)[e];
       const uint32_t q = (uint32_t)key;
@@ -337,24 +373,29 @@ __global__ __launch_bounds__(64) void ewa_raster_kernel(EwaArgs a) {
       L.rec[0][lane] = A;
       L.rec[1][lane] = B;
       L.z[lane] = __uint_as_float((uint32_t)(key >> 32));
-#pragma unroll
-      for (uint32_t qd = 0; qd < 4; ++qd)
-        if (ewa_reaches(A, B, rmax, tx0 + 4.0f * (float)(qd & 1u), ty0 + 4.0f * (float)(qd >> 1)))
-          reach |= 1u << qd;
+      reach = ewa_reach(A, B, rmax, tx0, ty0);
     }
-    // each quadrant's list: the records that reach it, in staging (= front to back) order
-    uint32_t nq = 0;
+    // each block's list: the records that reach it, in staging (= front to back) order
+    int counts = 0;  // lane b (< kEwaBlocks): the length of block b's list
 #pragma unroll
-    for (uint32_t qd = 0; qd < 4; ++qd) {
-      const unsigned long long b = __ballot((reach >> qd) & 1u);
-      if ((reach >> qd) & 1u)
-        L.idx[qd][__popcll(b & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-      if (qd == quad) nq = (uint32_t)__popcll(b);
+    for (uint32_t qd = 0; qd < (uint32_t)kEwaBlocks; ++qd) {
+      const bool hit = (reach & (1u << qd)) != 0u;
+      const unsigned long long b = __builtin_amdgcn_ballot_w64(hit);
+      // the lane's rank among the hits: set bits of b below the lane
+      const uint32_t rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      // every lane stores (no branch): a hit at its rank, the others into the
+      // row's spare slot, which nothing reads (relaxed atomic stores, as
+      // several lanes store to it at once)
+      __hip_atomic_store(&L.idx[qd][hit ? rank : 64u], (uint8_t)lane, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+      counts = gg_writelane(__popcll(b), (int)qd, counts);
     }
+    const uint32_t nq = (uint32_t)__shfl(counts, (int)blk);
     __syncthreads();
-    // each quadrant walks its own list; the wavefront runs as long as the longest
+    // each block walks its own list; the wavefront runs as long as the longest
     for (uint32_t s = 0; s < nq; ++s) {
-      const uint32_t t = L.idx[quad][s];
+      const uint32_t t = L.idx[blk][s];
       const float4 A = L.rec[0][t], B = L.rec[1][t];
       const float dx = px - A.x, dy = py - A.y;
       const bool in = fabsf(dx) <= rmax && fabsf(dy) <= rmax;
@@ -395,7 +436,7 @@ uint32_t ewa_tiles_per_splat(float r_max) {
 
 int launch_splat_ewa(const EwaArgs &a, hipStream_t s) {
   const uint32_t n = (uint32_t)a.K * a.ntiles;
-  const dim3 gsrc((a.ns + 255) / 256, a.K);
+  const dim3 gsrc(splat_bin_blocks((uint32_t)a.Ws, (uint32_t)a.Hs), a.K);
   {
     KernelTimer t("ewa_zero", s);
     hipLaunchKernelGGL(ewa_zero_kernel, dim3(min((n + 256) / 256, 1024u)), dim3(256), 0, s,
