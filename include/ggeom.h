@@ -164,8 +164,9 @@ size_t gg_workspace_size(int op, int32_t K, int32_t src_w, int32_t src_h, int32_
  *   log(1 - G) over band members with G < 1, and the count of G == 1 (what
  *   splat_views_backward needs).
  * Colour and opacity are accumulated in 64-bit fixed point, so they are
- * independent of the order splats arrive in; they equal the sequential FP32
- * sums to ~1e-7 relative.
+ * independent of the order splats arrive in; the means and the opacity are
+ * then formed in FP32 and equal the sequential FP32 results to a few 1e-7
+ * relative.
  * ------------------------------------------------------------------------- */
 int splat_views(const gg_camera *src, int32_t K, const float *depth, const uint8_t *rgb,
                 const gg_camera *tgt, const gg_splat_params *prm, int32_t *win_idx,

@@ -323,7 +323,7 @@ __device__ __forceinline__ uint32_t ewa_reach(float4 A, float4 B, float rmax, fl
 // One wavefront per (view, tile); its 64 lanes are the tile's blocks of
 // kEwaBlock x kEwaBlock pixels (the lanes of block b consecutive, row-major
 // in the block; blocks row-major in the tile).  Each batch of 64 staged
-// records is culled per block (ewa_reaches) into an ordered list, and each
+// records is culled per block (ewa_reach) into an ordered list, and each
 // block's lanes composite only their own list: the wavefront takes as many
 // steps as the longest list instead of all 64, and every pixel still sees,
 // front to back, every record that can touch it.
