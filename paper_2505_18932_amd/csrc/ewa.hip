@@ -131,8 +131,7 @@ __global__ __launch_bounds__(256) void ewa_bin_kernel(EwaArgs a) {
       if (!kFill) {
         const GG_GLOBAL uint8_t *c = gmem(a.rgb) + 3 * o;
         const float4 r0 = make_float4(g.u, g.v, g.Ah, g.Bn);
-        const float4 r1 = make_float4(g.Ch, (float)c[0] / 255.0f, (float)c[1] / 255.0f,
-                                      (float)c[2] / 255.0f);
+        const float4 r1 = make_float4(g.Ch, unorm8(c[0]), unorm8(c[1]), unorm8(c[2]));
         *(GG_GLOBAL gg_v4f *)(a.rec + 2 * o) = (gg_v4f){r0.x, r0.y, r0.z, r0.w};
         *(GG_GLOBAL gg_v4f *)(a.rec + 2 * o + 1) = (gg_v4f){r1.x, r1.y, r1.z, r1.w};
       }

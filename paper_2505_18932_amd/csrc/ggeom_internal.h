@@ -147,6 +147,19 @@ __device__ __forceinline__ float recip_pos(float z) {
   return 1.0f / z;
 }
 
+// A colour channel c = u / 255, correctly rounded, for u = 0..255, in three
+// FP32 operations instead of an IEEE division: q = u r with r = RN(1/255),
+// then one correction with the remainder u - 255 q, which the fused
+// multiply-add forms exactly (Markstein's step).  The result equals the
+// IEEE quotient for every u (tests/test_unorm8_cpu.py checks all 256 in
+// exact rational arithmetic).
+__device__ __forceinline__ float unorm8(uint32_t u) {
+  constexpr float r = 1.0f / 255.0f;
+  const float x = (float)u;
+  const float q = x * r;
+  return fmaf(fmaf(-q, 255.0f, x), r, q);
+}
+
 // floor(x) converted to int32 in one instruction (saturating; x finite).
 __device__ __forceinline__ int32_t floor_i32(float x) {
   int32_t r;

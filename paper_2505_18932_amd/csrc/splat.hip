@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void splat_backward_kernel(SplatArgs a) {
     // per source pixel: the Gaussian's footprint terms of dG/dD as products
     const float inv_s2 = 1.0f / g.s2, ks = dsdD / (sig * g.s2);
     const uint8_t *cq = a.rgb + ((size_t)k * a.ns + q) * 3;
-    const float c[3] = {(float)cq[0] / 255.0f, (float)cq[1] / 255.0f, (float)cq[2] / 255.0f};
+    const float c[3] = {unorm8(cq[0]), unorm8(cq[1]), unorm8(cq[2])};
     const size_t kt = (size_t)k * a.nt;
     const float *grgb = a.g_rgb ? a.g_rgb + 3 * kt : nullptr;
     const float *frgb = a.fw_rgb + 3 * kt;

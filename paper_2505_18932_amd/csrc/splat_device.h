@@ -360,9 +360,9 @@ __device__ __forceinline__ void raster_tile(const SplatArgs &a, int k, uint32_t 
     }
     if (!g.ok) continue;
     // the entry's colour (c = u8 / 255) and mask, once for all its pixels
-    const float c0 = (float)gmem(ck)[3 * (size_t)q + 0] / 255.0f;
-    const float c1 = (float)gmem(ck)[3 * (size_t)q + 1] / 255.0f;
-    const float c2 = (float)gmem(ck)[3 * (size_t)q + 2] / 255.0f;
+    const float c0 = unorm8(gmem(ck)[3 * (size_t)q + 0]);
+    const float c1 = unorm8(gmem(ck)[3 * (size_t)q + 1]);
+    const float c2 = unorm8(gmem(ck)[3 * (size_t)q + 2]);
     const float m = a.mask_in ? gmem(a.mask_in)[(size_t)k * a.ns + q] : 0.0f;
     const int a0 = max(g.a0, ax0), a1 = min(g.a1, ax0 + kTile - 1);
     const int b0 = max(g.b0, by0), b1 = min(g.b1, by0 + kTile - 1);

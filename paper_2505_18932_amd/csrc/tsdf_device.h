@@ -86,21 +86,30 @@ __device__ __forceinline__ float window_nu_fast(const float *tile, int li, int l
 // The window's tile staged in LDS; pixels without a usable depth are staged
 // as NaN (both window forms treat NaN as a hole), pixels outside the image
 // as 0 (only the bounds-checked form can reach them, and it skips them).
+// A staged row is at most 46 floats: one wavefront's lanes take its columns
+// and the workgroup's wavefronts (blockDim a multiple of 64) step down the
+// rows, so no lane divides by the row width.
 __device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
                                            const ConfArgs &a) {
+  static_assert(kConfTX + 2 * kMaxR <= 64, "a staged row fits one wavefront");
   const int r = a.radius;
   const int tw = kConfTX + 2 * r, th = kConfTY + 2 * r;
-  for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
-    const int ly = e / tw, lx = e - ly * tw;
-    const int gi = i0 - r + lx, gj = j0 - r + ly;
-    float v = 0.0f;
-    if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) {
-      v = gmem(dk)[(size_t)gj * a.Ws + gi];
-      if (!depth_ok(v)) v = __builtin_nanf("");
+  const int lx = (int)(threadIdx.x & 63u), waves = (int)(blockDim.x >> 6);
+  const int gi = i0 - r + lx;
+  const bool in_col = gi >= 0 && gi < a.Ws;
+  // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
+  // relative to the fixed centre origin
+  float *dst = tile + (kMaxR - r) * kConfLW + (lx + kMaxR - r);
+  if (lx < tw) {
+    for (int ly = (int)(threadIdx.x >> 6); ly < th; ly += waves) {
+      const int gj = j0 - r + ly;
+      float v = 0.0f;
+      if (in_col && gj >= 0 && gj < a.Hs) {
+        v = gmem(dk)[(size_t)gj * a.Ws + gi];
+        if (!depth_ok(v)) v = __builtin_nanf("");
+      }
+      dst[ly * kConfLW] = v;
     }
-    // stored at (ly + kMaxR - r, lx + kMaxR - r) so that window offsets are
-    // relative to the fixed centre origin
-    tile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
   }
 }
 
