@@ -32,9 +32,11 @@ __device__ __forceinline__ SplatGeom splat_geom(const SplatView &V, float D, uin
   g.s2 = sig * sig;
   g.R2 = fminf(2.0f * g.s2, a.rmax2);
   // candidate window: covered pixels have |a + 0.5 - x| <= r (1 + 2^-21)
-  // (the rounded d2 is at least the rounded dx^2); the float bounds below
-  // carry at most 3 ulps of |x| + r < 2^-9 of error, inside the margin
-  const float r = sqrtf(g.R2) + 0x1p-6f;
+  // (the rounded d2 is at least the rounded dx^2); the hardware square root
+  // (within an ulp) and the float bounds below carry at most 4 ulps of
+  // |x| + r, which is below 2^15 wherever a pixel is covered (images of at
+  // most 16384 pixels, r_max at most 64): at most 2^-7, inside the margin
+  const float r = __builtin_amdgcn_sqrtf(g.R2) + 0x1p-6f;
   float ax0 = ceilf(g.x - 0.5f - r), ax1 = floorf(g.x - 0.5f + r);
   float by0 = ceilf(g.y - 0.5f - r), by1 = floorf(g.y - 0.5f + r);
   ax0 = fmaxf(ax0, 0.0f);

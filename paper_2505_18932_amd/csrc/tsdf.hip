@@ -435,17 +435,7 @@ __global__ __launch_bounds__(256) void tsdf_bwd_finish_kernel(TsdfBackArgs a) {
   const ConfArgs c = conf_of(a);
   const int k = blockIdx.z, i0 = blockIdx.x * kConfTX, j0 = blockIdx.y * kConfTY;
   stage_tile(tile, a.depth + (size_t)k * a.ns, i0, j0, c);
-  {
-    const int r = a.radius, tw = kConfTX + 2 * r, th = kConfTY + 2 * r;
-    const float *gn = a.gnu + (size_t)k * a.ns;
-    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
-      const int ly = e / tw, lx = e - ly * tw;
-      const int gi = i0 - r + lx, gj = j0 - r + ly;
-      float v = 0.0f;
-      if (gi >= 0 && gi < a.Ws && gj >= 0 && gj < a.Hs) v = gmem(gn)[(size_t)gj * a.Ws + gi];
-      gtile[(ly + kMaxR - r) * kConfLW + (lx + kMaxR - r)] = v;
-    }
-  }
+  stage_rows<false>(gtile, a.gnu + (size_t)k * a.ns, i0, j0, c);
   __syncthreads();
   const int lx = threadIdx.x & (kConfTX - 1), ly = threadIdx.x / kConfTX;
   const int i = i0 + lx, j = j0 + ly;

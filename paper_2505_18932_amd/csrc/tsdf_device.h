@@ -88,8 +88,10 @@ __device__ __forceinline__ float window_nu_fast(const float *tile, int li, int l
 // as 0 (only the bounds-checked form can reach them, and it skips them).
 // A staged row is at most 46 floats: one wavefront's lanes take its columns
 // and the workgroup's wavefronts (blockDim a multiple of 64) step down the
-// rows, so no lane divides by the row width.
-__device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
+// rows, so no lane divides by the row width.  kDepth: the source is a depth
+// map, whose holes are staged as NaN; otherwise values are staged as read.
+template <bool kDepth>
+__device__ __forceinline__ void stage_rows(float *tile, const float *src, int i0, int j0,
                                            const ConfArgs &a) {
   static_assert(kConfTX + 2 * kMaxR <= 64, "a staged row fits one wavefront");
   const int r = a.radius;
@@ -105,12 +107,17 @@ __device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0,
       const int gj = j0 - r + ly;
       float v = 0.0f;
       if (in_col && gj >= 0 && gj < a.Hs) {
-        v = gmem(dk)[(size_t)gj * a.Ws + gi];
-        if (!depth_ok(v)) v = __builtin_nanf("");
+        v = gmem(src)[(size_t)gj * a.Ws + gi];
+        if (kDepth && !depth_ok(v)) v = __builtin_nanf("");
       }
       dst[ly * kConfLW] = v;
     }
   }
+}
+
+__device__ __forceinline__ void stage_tile(float *tile, const float *dk, int i0, int j0,
+                                           const ConfArgs &a) {
+  stage_rows<true>(tile, dk, i0, j0, a);
 }
 
 // One 32 x 8 tile (bx, by) of view k; tile: LDS of kConfLH x kConfLW floats.
