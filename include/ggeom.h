@@ -478,6 +478,10 @@ typedef struct gg_batch_item {
   int32_t *win_idx;             /* splat outputs, as splat_views (required with rgb) */
   float *sp_depth, *sp_rgb, *sp_alpha;
   float *sp_tape;               /* or NULL                                           */
+  gg_volume_tuning volume;      /* this item's fusion launch shape, as tsdf_integrate
+                                   takes it (all 0: the plan's pixels_per_block and
+                                   bins_per_thread, bands of 256 pixels); invalid
+                                   values fail the plan with GG_ERR_INVALID         */
 } gg_batch_item;
 
 /* Launch shape chosen by the autotuner (0 = default). */

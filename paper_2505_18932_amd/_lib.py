@@ -47,6 +47,11 @@ class GGMaskParams(C.Structure):
     _fields_ = [("beta", C.c_float), ("lambda_t", C.c_float), ("factor", C.c_int32)]
 
 
+class GGVolumeTuning(C.Structure):
+    _fields_ = [("pixels_per_block", C.c_int32), ("pixels_per_row", C.c_int32),
+                ("bins_per_thread", C.c_int32), ("band_width", C.c_int32)]
+
+
 class GGBatchItem(C.Structure):
     _fields_ = [("src", C.POINTER(GGCamera)), ("K", C.c_int32), ("depth", C.c_void_p),
                 ("rgb", C.c_void_p), ("tgt", GGCamera), ("splat", GGSplatParams),
@@ -54,17 +59,12 @@ class GGBatchItem(C.Structure):
                 ("W_prev", C.c_void_p), ("F", C.c_void_p), ("W", C.c_void_p),
                 ("out_depth", C.c_void_p), ("out_bin", C.c_void_p), ("win_idx", C.c_void_p),
                 ("sp_depth", C.c_void_p), ("sp_rgb", C.c_void_p), ("sp_alpha", C.c_void_p),
-                ("sp_tape", C.c_void_p)]
+                ("sp_tape", C.c_void_p), ("volume", GGVolumeTuning)]
 
 
 class GGBatchTuning(C.Structure):
     _fields_ = [("pixels_per_block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("bins_per_thread", C.c_int32), ("branches", C.c_int32)]
-
-
-class GGVolumeTuning(C.Structure):
-    _fields_ = [("pixels_per_block", C.c_int32), ("pixels_per_row", C.c_int32),
-                ("bins_per_thread", C.c_int32), ("band_width", C.c_int32)]
 
 
 P = C.c_void_p

@@ -124,10 +124,16 @@ def tune_plain_step(step, first, reps=8, warm=2):
 
 
 def batch_signature(items):
+    """The batch's items by view count, bins, target size, splat and their own fusion launch
+    shapes (an item's ``volume``, if any)."""
+    def own(it):
+        v = ops.volume_tuning(it.get("volume"))
+        return "" if v is None else "/v%d,%d,%d,%d" % (v.pixels_per_block, v.pixels_per_row,
+                                                        v.bins_per_thread, v.band_width)
     sig = sorted((len(it["src"]), ops.tsdf_params(it["tsdf"]).num_bins,
                   ops.camera(it["tgt"]).width, ops.camera(it["tgt"]).height,
-                  it.get("rgb") is not None) for it in items)
-    return "batch-p/" + ";".join("K%dD%d/%dx%d/%d" % s for s in sig)
+                  it.get("rgb") is not None, own(it)) for it in items)
+    return "batch-v/" + ";".join("K%dD%d/%dx%d/%d%s" % s for s in sig)
 
 
 def tune_batch(items, reps=3, use_cache=True):

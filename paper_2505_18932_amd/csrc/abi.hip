@@ -1201,10 +1201,22 @@ struct gg_batch {
 constexpr uint32_t kBatchPixelsPerBlock = 16;
 
 // Bins per thread of a batch item (as for the plain call with that tuning).
+static bool item_aligned32(const gg_batch_item &it) {
+  return aligned(it.F, 32) && aligned(it.W, 32) &&
+         (!it.F_prev || (aligned(it.F_prev, 32) && aligned(it.W_prev, 32)));
+}
+
+// Whether the item brings its own fusion launch shape.
+static bool item_tuned(const gg_batch_item &it) {
+  const gg_volume_tuning &t = it.volume;
+  return t.pixels_per_block || t.pixels_per_row || t.bins_per_thread || t.band_width;
+}
+
+// Bins per thread of the item's fusion: as its own launch shape gives them
+// (volume_shape), else as the plan's.
 static int item_vec(const gg_batch_item &it, int vec) {
-  const bool a32 = aligned(it.F, 32) && aligned(it.W, 32) &&
-                   (!it.F_prev || (aligned(it.F_prev, 32) && aligned(it.W_prev, 32)));
-  return volume_v(it.tsdf.num_bins, a32, vec);
+  return volume_v(it.tsdf.num_bins, item_aligned32(it),
+                  item_tuned(it) ? it.volume.bins_per_thread : vec);
 }
 
 static int check_item(const gg_batch_item &it, int i, int vec) {
@@ -1223,6 +1235,7 @@ static int check_item(const gg_batch_item &it, int i, int vec) {
     if (!it.win_idx || !it.sp_depth || !it.sp_rgb || !it.sp_alpha)
       return fail(GG_ERR_INVALID, "%s: splat outputs required with rgb", what);
   }
+  if (int rc = check_tuning(&it.volume, what)) return rc;
   const int D = it.tsdf.num_bins;
   const int V = item_vec(it, vec);
   if (D / V > 1024) return fail(GG_ERR_UNSUPPORTED, "%s: D = %d too large", what, D);
@@ -1272,15 +1285,22 @@ extern "C" int gg_batch_plan(const gg_batch_item *items, int32_t n, const gg_bat
     const int sw = it.src[0].width, sh = it.src[0].height, K = it.K, D = it.tsdf.num_bins;
     const uint32_t npix = (uint32_t)(it.tgt.width * it.tgt.height);
     VolumeShape &vs = shapes[i];
-    vs.V = item_vec(it, vec);
-    vs.cpp = (uint32_t)(D / vs.V);
-    // pixels per workgroup as the plain call's launch shape would give them
-    vs.ppb = ppb_t > 0 ? (uint32_t)ppb_t : kBatchPixelsPerBlock;
-    while (vs.ppb > 1 && vs.ppb * vs.cpp > 1024) --vs.ppb;
-    vs.threads = vs.ppb * vs.cpp;
-    vs.nblocks = (npix + vs.ppb - 1) / vs.ppb;
-    vs.pw_shift = pick_pw_shift(vs.ppb, 16);
-    vs.band_px = kDefaultBandPixels;
+    if (item_tuned(it)) {
+      // the item's own launch shape, exactly as tsdf_integrate would take it
+      char what[64];
+      snprintf(what, sizeof what, "%s: item %d", N, i);
+      if (int rc = volume_shape(D, npix, vs, what, item_aligned32(it), &it.volume)) return rc;
+    } else {
+      vs.V = item_vec(it, vec);
+      vs.cpp = (uint32_t)(D / vs.V);
+      // pixels per workgroup as the plain call's launch shape would give them
+      vs.ppb = ppb_t > 0 ? (uint32_t)ppb_t : kBatchPixelsPerBlock;
+      while (vs.ppb > 1 && vs.ppb * vs.cpp > 1024) --vs.ppb;
+      vs.threads = vs.ppb * vs.cpp;
+      vs.nblocks = (npix + vs.ppb - 1) / vs.ppb;
+      vs.pw_shift = pick_pw_shift(vs.ppb, 16);
+      vs.band_px = kDefaultBandPixels;
+    }
     o_table[i] = off;
     off += up256(8 * table_view_records(sw, sh) * K);
     o_bins[i] = off;

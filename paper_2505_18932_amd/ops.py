@@ -536,7 +536,9 @@ class BatchPlan:
     """Many target views fused by one graph launch (see include/ggeom.h).
 
     ``items``: dicts with keys src, depth, tgt, tsdf and optionally rgb,
-    splat, mask, F_prev, W_prev, F, W (allocated if absent), extract (True).
+    splat, mask, F_prev, W_prev, F, W (allocated if absent), extract (True),
+    volume (the item's own fusion launch shape, as ``volume_tuning`` takes it;
+    absent: the plan's).
     Outputs live in each item dict after creation: F, W, depth_out, bin_out
     and, with rgb, splat = dict(win_idx, depth, rgb, alpha, tape).  The plan
     binds these buffers; write new inputs into the same tensors between
@@ -596,6 +598,8 @@ class BatchPlan:
                 b.sp_rgb = o["rgb"].data_ptr()
                 b.sp_alpha = o["alpha"].data_ptr()
                 b.sp_tape = o["tape"].data_ptr()
+            if it.get("volume") is not None:
+                b.volume = volume_tuning(it["volume"])
             self._keep.append(sa)
         self._arr = arr
         tune = L.GGBatchTuning(int(pixels_per_block), int(blocks_per_cu), int(bins_per_thread),

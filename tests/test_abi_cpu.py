@@ -369,3 +369,51 @@ def test_noalloc_rejects_a_workspace_beyond_its_static_scratch():
                                     FAKE, FAKE, FAKE, FAKE, None, None)
     assert rc == L.GG_ERR_UNSUPPORTED
     assert "static scratch" in lib.gg_last_error().decode()
+
+
+def test_batch_rejects_an_invalid_item_launch_shape():
+    """An item's own fusion launch shape is validated with the item, before any GPU call."""
+    lib = L.lib()
+    src, tgt = _cams()
+    arr = (L.GGBatchItem * 1)()
+    b = arr[0]
+    b.src, b.K, b.depth, b.tgt = src, 2, FAKE.value, tgt
+    b.tsdf = ops.tsdf_params(scenes.tsdf_params(num_bins=64))
+    b.F = b.W = FAKE.value
+    tune = L.GGBatchTuning(0, 0, 0, 0)
+    h = C.c_void_p()
+    for bad in [(-1, 0, 0, 0), (0, 65, 0, 0), (0, 0, 3, 0), (0, 0, 8, -1), (0, 0, 8, 65537)]:
+        b.volume = ops.volume_tuning(bad)
+        rc, msg = _err(lib.gg_batch_plan(arr, 1, C.byref(tune), C.byref(h)))
+        assert rc == L.GG_ERR_INVALID and "item 0" in msg, (bad, msg)
+
+
+def test_binding_structs_match_the_header():
+    """Every record the binding marshals has the size and field offsets the C compiler gives
+    the header's struct (a small C program built with the host compiler prints them)."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"gg_camera": L.GGCamera, "gg_splat_params": L.GGSplatParams,
+               "gg_tsdf_params": L.GGTsdfParams, "gg_mask_params": L.GGMaskParams,
+               "gg_volume_tuning": L.GGVolumeTuning,
+               "gg_batch_item": L.GGBatchItem, "gg_batch_tuning": L.GGBatchTuning}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ggeom.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src_c, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src_c, "w").write("\n".join(lines) + "\n")
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src_c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f in cls._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{cname}.{f[0]}"

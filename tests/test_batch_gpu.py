@@ -60,6 +60,29 @@ def test_batch_equals_plain(tuning):
     plan.close()
 
 
+# each item's own fusion launch shape (gg_batch_item.volume): pixels per workgroup, per
+# wavefront row, bins per thread and band width, cycled over the items
+ITEM_SHAPES = [(16, 16, 8, 0), (32, 16, 8, 128), (64, 16, 8, 0), (16, 16, 8, 192),
+               (0, 0, 4, 0), (32, 8, 4, 0), (8, 8, 2, 0), (16, 16, 8, 65536), None]
+
+
+@pytest.mark.parametrize("plan_tuning", [(0, 0, 0, 0), (32, 1, 4, 1)])
+def test_batch_items_with_their_own_launch_shapes(plan_tuning):
+    """Items that bring their own fusion launch shape (several items sharing one, some none)
+    give the plain calls' results bitwise, whatever the plan's own tuning."""
+    items = _items(n=18)
+    refs = [_plain(it) for it in items]
+    for i, it in enumerate(items):
+        shape = ITEM_SHAPES[i % len(ITEM_SHAPES)]
+        if shape is not None:
+            it["volume"] = shape
+    plan = gg.BatchPlan(items, *plan_tuning)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check(items, refs)
+    plan.close()
+
+
 def test_batch_shuffled_order_and_replays():
     items = _items(n=10)
     refs = [_plain(it) for it in items]
