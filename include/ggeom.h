@@ -520,8 +520,10 @@ const char *gg_last_error(void);
 /* The relative projection a -> b [host, no GPU work]: a pixel centre
  * (px, py) of camera a at camera-a depth z maps to
  * (x_b, y_b, z_b) = z * H (px, py, 1)^T + c  (exact in real arithmetic),
- * H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a), formed in FP64
- * and rounded to FP32 once.  H [host] 9 floats row-major, c [host] 3. */
+ * H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a): the FP32
+ * rounding (to nearest, ties to even) of the exact products, formed in
+ * binary128; an entry below 2^-50 of its terms' summed magnitudes is 0.
+ * H [host] 9 floats row-major, c [host] 3. */
 int gg_relative_projection(const gg_camera *a, const gg_camera *b, float *H, float *c);
 
 /* Measurement utility: the fusion kernel of tsdf_integrate launched in the

@@ -160,8 +160,9 @@ static quad qabs(quad x) { return x < 0 ? -x : x; }
 
 /* H = K_b R_b R_a^T K_a^{-1} and c = K_b (t_b - R_b R_a^T t_a) from the
  * factors M1 .. M4 (row-major), and with every factor replaced by its
- * entrywise magnitude, the sums of the monomials' magnitudes. */
-static void relproj_q(const orc_camera *a, const orc_camera *b, quad H[9], quad c[3]) {
+ * entrywise magnitude, the sums of the monomials' magnitudes (Hm, cm). */
+static void relproj_q(const orc_camera *a, const orc_camera *b, quad H[9], quad c[3], quad Hm[9],
+                      quad cm[3]) {
   const quad fxa = a->fx, fya = a->fy;
   const quad Kb[9] = {b->fx, 0, b->cx, 0, b->fy, b->cy, 0, 0, 1};
   const quad Kai[9] = {1 / fxa, 0, -(quad)a->cx / fxa, 0, 1 / fya, -(quad)a->cy / fya, 0, 0, 1};
@@ -173,7 +174,6 @@ static void relproj_q(const orc_camera *a, const orc_camera *b, quad H[9], quad 
     }
   const quad ta[3] = {a->t[0], a->t[1], a->t[2]};
   const quad tb[3] = {b->t[0], b->t[1], b->t[2]};
-  quad Hm[9], cm[3];
   for (int pass = 0; pass < 2; ++pass) {
     /* pass 0: the values; pass 1: the same products over magnitudes */
     quad kb[9], kai[9], rb[9], rat[9], xa[3], xb[3];
@@ -206,26 +206,56 @@ static void relproj_q(const orc_camera *a, const orc_camera *b, quad H[9], quad 
 
 /* FP64 rounding (the FP64 oracle and the tests' world-space check). */
 void orc_relproj_d(const orc_camera *a, const orc_camera *b, double H[9], double c[3]) {
-  quad Hq[9], cq[3];
-  relproj_q(a, b, Hq, cq);
+  quad Hq[9], cq[3], Hm[9], cm[3];
+  relproj_q(a, b, Hq, cq, Hm, cm);
   for (int i = 0; i < 9; ++i) H[i] = (double)Hq[i];
   for (int i = 0; i < 3; ++i) c[i] = (double)cq[i];
 }
 
+/* Round to FP32 a binary128 value x that stands for an exact product whose
+ * monomials' magnitudes sum to m.  The binary128 evaluation is off by far
+ * less than 2^-100 m, so x rounds as the exact value does -- except at an
+ * exact tie (the exact value halfway between two floats, which rigs aligned
+ * with the axes produce), where that error alone would pick the side.  So a
+ * point within 2^-100 m of the halfway point between the floats below and
+ * above x counts as the tie, which goes to the float whose last significand
+ * bit is 0. */
+static float to_f32(quad x, quad m) {
+  float f = (float)x, below, above;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  /* the float on the other side of x: one step of the bit pattern (the
+   * pattern grows with |f|) */
+  const int up = ((quad)f <= x) == (f >= 0);
+  uint32_t w = up ? u + 1u : u - 1u;
+  if (f == 0) w = ((quad)f <= x) ? 1u : 0x80000001u;
+  float g;
+  memcpy(&g, &w, 4);
+  below = f < g ? f : g;
+  above = f < g ? g : f;
+  const quad half = ((quad)below + (quad)above) / 2;
+  if (qabs(x - half) <= 0x1p-100Q * m) {
+    uint32_t lb;
+    memcpy(&lb, &below, 4);
+    return (lb & 1u) == 0 ? below : above;
+  }
+  return f;
+}
+
 /* The relative projection in the oracle's working precision. */
 static void relproj(const orc_camera *a, const orc_camera *b, real H[9], real c[3]) {
-  quad Hq[9], cq[3];
-  relproj_q(a, b, Hq, cq);
-  for (int i = 0; i < 9; ++i) H[i] = (real)Hq[i];
-  for (int i = 0; i < 3; ++i) c[i] = (real)cq[i];
+  quad Hq[9], cq[3], Hm[9], cm[3];
+  relproj_q(a, b, Hq, cq, Hm, cm);
+  for (int i = 0; i < 9; ++i) H[i] = sizeof(real) == 4 ? (real)to_f32(Hq[i], Hm[i]) : (real)Hq[i];
+  for (int i = 0; i < 3; ++i) c[i] = sizeof(real) == 4 ? (real)to_f32(cq[i], cm[i]) : (real)cq[i];
 }
 
 /* Exported FP32 rounding of the relative projection (for tests). */
 void orc_relproj(const orc_camera *a, const orc_camera *b, float H[9], float c[3]) {
-  quad Hq[9], cq[3];
-  relproj_q(a, b, Hq, cq);
-  for (int i = 0; i < 9; ++i) H[i] = (float)Hq[i];
-  for (int i = 0; i < 3; ++i) c[i] = (float)cq[i];
+  quad Hq[9], cq[3], Hm[9], cm[3];
+  relproj_q(a, b, Hq, cq, Hm, cm);
+  for (int i = 0; i < 9; ++i) H[i] = to_f32(Hq[i], Hm[i]);
+  for (int i = 0; i < 3; ++i) c[i] = to_f32(cq[i], cm[i]);
 }
 
 /* The ray of pixel centre (px, py): h = H (px, py, 1)^T, fused per row. */

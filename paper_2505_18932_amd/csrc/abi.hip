@@ -92,12 +92,32 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
+// The FP32 value nearest v, a binary128 evaluation whose error lies far
+// below 2^-100 m (m: the summed magnitudes of the terms it adds).  A v
+// within 2^-100 m of the midpoint of the two floats around it is taken to
+// be that midpoint, an exact tie, and rounds to the float with the even
+// significand: cameras aligned with the axes make exact ties common, and
+// the last binary128 bits of a tie are noise of the evaluation order.
+static float nearest_f32(__float128 v, __float128 m) {
+  const float f = (float)v;
+  const float g = std::nextafter(f, (__float128)f <= v ? INFINITY : -INFINITY);
+  const float lo = std::min(f, g), hi = std::max(f, g);
+  const __float128 d = v - ((__float128)lo + (__float128)hi) * 0.5Q;
+  if ((d < 0 ? -d : d) <= 0x1p-100Q * m) {
+    uint32_t bits;
+    std::memcpy(&bits, &lo, sizeof bits);
+    return (bits & 1u) ? hi : lo;
+  }
+  return f;
+}
+
 // H = K_b R_b R_a^T K_a^{-1}, c = K_b (t_b - R_b R_a^T t_a): M = R_b R_a^T
 // and e = t_b - M t_a first, then the intrinsics of b on the left and those
 // of a on the right, in binary128 (113-bit significand), rounded once to
-// FP32.  binary128 keeps every entry far below an FP32 rounding step of its
-// exact value, also entries that are small differences of large terms, so
-// the rounding is that of the exact product whatever the evaluation order.
+// FP32 (nearest_f32).  binary128 keeps every entry far below an FP32
+// rounding step of its exact value, also entries that are small differences
+// of large terms, so the rounding is that of the exact product whatever the
+// evaluation order, exact ties included.
 // An entry below 2^-50 of the summed magnitudes of its monomials (the same
 // formulas over magnitudes, carried beside the values) is cancellation
 // residue and becomes 0, so that it is not left to the evaluation order.
@@ -144,8 +164,8 @@ void relproj(const gg_camera &a, const gg_camera &b, Proj &out) {
     Hm[3 * r + 2] = (Am[r][2] + m0 * qa(acx)) + m1 * qa(acy);
   }
   const q tiny = 0x1p-50Q;
-  for (int i = 0; i < 9; ++i) out.H[i] = qa(H[i]) < tiny * Hm[i] ? 0.0f : (float)H[i];
-  for (int i = 0; i < 3; ++i) out.c[i] = qa(c[i]) < tiny * cm[i] ? 0.0f : (float)c[i];
+  for (int i = 0; i < 9; ++i) out.H[i] = qa(H[i]) < tiny * Hm[i] ? 0.0f : nearest_f32(H[i], Hm[i]);
+  for (int i = 0; i < 3; ++i) out.c[i] = qa(c[i]) < tiny * cm[i] ? 0.0f : nearest_f32(c[i], cm[i]);
 }
 
 static bool finite_f(float v) { return std::isfinite(v); }
