@@ -2,6 +2,8 @@
 plain calls, item by item, bitwise, for several launch tunings, item orders
 and graph replays; and against the oracle directly, in full at half size and
 on sampled pixel columns at full size."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -145,13 +147,19 @@ def test_batch_bins_per_thread(vec):
     plan.close()
 
 
-@pytest.mark.parametrize("seed", range(4))
+# GG_BATCH_CASES widens the random mixes (the default keeps the suite quick)
+BATCH_CASES = int(os.environ.get("GG_BATCH_CASES", "4"))
+
+
+@pytest.mark.parametrize("seed", range(BATCH_CASES))
 def test_batch_random_mix(seed):
     """Seeded random mixes of 3 to 12 small ring items: view counts 1 to 8,
     ragged sizes, 2 to 199 bins, any confidence window, some items without
-    colour (no splat) or with a temporal mask; the one graph launch equals
-    the plain calls bitwise, on two replays."""
+    colour (no splat) or with a temporal mask, some with their own fusion
+    launch shape; the one graph launch equals the plain calls bitwise, on two
+    replays."""
     rng = np.random.default_rng(2000 + seed)
+    shapes = np.random.default_rng(3000 + seed)
     items = []
     for n in range(int(rng.integers(3, 13))):
         k = int(rng.integers(1, 9))
@@ -167,6 +175,10 @@ def test_batch_random_mix(seed):
         if rng.uniform() < 0.3:
             it["mask"] = torch.from_numpy(
                 rng.uniform(0, 1.2, (c["tgt"].height, c["tgt"].width)).astype(np.float32)).to(DEV)
+        if shapes.uniform() < 0.4:
+            it["volume"] = (int(shapes.choice([0, 1, 3, 8, 16, 32, 64])),
+                            int(shapes.choice([0, 4, 8, 16])), int(shapes.choice([0, 1, 2, 4, 8])),
+                            int(shapes.choice([0, 64, 128, 65536])))
         items.append(it)
     refs = [_plain(it) for it in items]
     plan = gg.BatchPlan(items)
