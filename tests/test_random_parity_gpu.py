@@ -20,8 +20,10 @@ from tests.test_parity_gpu import (DEV, bits, check_splat, check_tsdf, grad_clos
 
 pytestmark = pytest.mark.gpu
 
-# GG_RANDOM_CASES widens the sweep (the default keeps the suite quick)
+# GG_RANDOM_CASES widens the sweep (the default keeps the suite quick); GG_RANDOM_FIRST starts it
+# at a later seed
 CASES = int(os.environ.get("GG_RANDOM_CASES", "24"))
+FIRST = int(os.environ.get("GG_RANDOM_FIRST", "0"))
 
 
 def case(seed):
@@ -37,7 +39,7 @@ def case(seed):
     return c, rng
 
 
-@pytest.mark.parametrize("seed", range(CASES))
+@pytest.mark.parametrize("seed", range(FIRST, FIRST + CASES))
 def test_random_case(seed):
     c, rng = case(seed)
     print(f"seed {seed}: K={c['depth'].shape[0]} {c['tgt'].width}x{c['tgt'].height} "
