@@ -21,7 +21,10 @@ TEMPORAL = "tests/test_oracle_temporal.py"
 MARCH = "tests/test_oracle_raymarch.py"
 NET = "tests/test_oracle_netinputs.py"
 EWA = "tests/test_oracle_ewa.py"
+EXACT = "tests/test_relproj_exact_cpu.py"
 MUTANTS = [
+    ("tie_not_to_even", "return (lb & 1u) == 0 ? below : above;", "return above;", EXACT),
+    ("tie_rule_dropped", "if (qabs(x - half) <= 0x1p-100Q * m) {", "if (0) {", EXACT),
     ("sign_of_s", "const real s = (real)Dk - X[2];\n        if (s < -tau) continue; /* occluded",
      "const real s = X[2] - (real)Dk;\n        if (s < -tau) continue; /* occluded", PINS),
     ("no_occlusion_cut", "if (s < -tau) continue; /* occluded in view k */", "", PINS),

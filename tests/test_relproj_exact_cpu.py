@@ -1,11 +1,12 @@
-"""The relative projection (H, c) of camera pairs, from the library and from the
-oracle, against its exact value: H = K_b R_b R_a^T K_a^-1 and
+"""The relative projection (H, c) of camera pairs, from the oracle and from the
+library, against its exact value: H = K_b R_b R_a^T K_a^-1 and
 c = K_b (t_b - R_b R_a^T t_a), in rational arithmetic from the FP32 camera
 parameters, rounded to the nearest FP32 with ties to even.  An entry below
 2^-50 of its monomials' summed magnitudes is 0 on both sides (exactly zero
 here).  Rigs aligned with the axes make exact ties: the first view of the
 random sweep's seed 1348 has one in H[1][0], which binary128 rounding alone
 had sent different ways on the two sides."""
+import math
 from fractions import Fraction as Fr
 
 import numpy as np
@@ -13,13 +14,11 @@ import pytest
 
 import oracle
 import scenes
-from paper_2505_18932_amd import ops
-from tests.test_random_parity_gpu import case
 from tests.test_unorm8_cpu import rn32
 
 
 def _params(cam):
-    g = ops.camera(cam)
+    g = oracle.cam(cam)
     F = lambda v: Fr(float(np.float32(v)))  # noqa: E731
     return (F(g.fx), F(g.fy), F(g.cx), F(g.cy), [F(v) for v in g.R], [F(v) for v in g.t])
 
@@ -56,11 +55,22 @@ def expected_f32(val, mag):
     return np.float32(float(rn32(val)))
 
 
+def sweep_rig(seed):
+    """The cameras of the GPU random sweep's case ``seed`` (its rig draws, without rendering)."""
+    rng = np.random.default_rng(1000 + seed)
+    k = int(rng.integers(1, 9))
+    w, h = int(rng.integers(1, 90)), int(rng.integers(1, 60))
+    n_ring = max(8, k + 2)
+    seq = scenes.RingSequence(7, seed, n_ring, 1.0, w, h, k, scenes.MovingSpheres(seed, 3),
+                              target_angle=2 * math.pi * 0.37 / n_ring)
+    return seq.src, seq.tgt
+
+
 def _pairs():
     for seed in list(range(300)) + [1348]:
-        c, _ = case(seed)
-        for s in c["src"]:
-            yield f"sweep seed {seed}", s, c["tgt"]
+        src, tgt = sweep_rig(seed)
+        for s in src:
+            yield f"sweep seed {seed}", s, tgt
     ring = scenes.ring_rig(16, 1.0, 1280, 720)
     tgt = scenes.ring_target(0.5, 1.0, 1280, 720)
     for k in range(0, 16, 3):
@@ -68,28 +78,34 @@ def _pairs():
         yield f"ring view {k} from the target", tgt, ring[k]
 
 
-def test_library_and_oracle_round_the_exact_projection():
+def _expected(a, b):
+    (H, c), (Hm, cm) = exact_relproj(a, b)
+    return np.array([expected_f32(v, m) for v, m in zip(H + c, Hm + cm)], np.float32)
+
+
+def test_oracle_rounds_the_exact_projection():
     for what, a, b in _pairs():
-        (H, c), (Hm, cm) = exact_relproj(a, b)
-        want = np.array([expected_f32(v, m) for v, m in zip(H + c, Hm + cm)], np.float32)
-        Hl, cl = ops.relative_projection(a, b)
-        got_l = np.concatenate([np.array(Hl, np.float32).ravel(), np.array(cl, np.float32)])
         Ho, co = oracle.relproj(a, b)
-        got_o = np.concatenate([Ho.astype(np.float32).ravel(), co.astype(np.float32)])
-        assert got_l.tobytes() == want.tobytes(), (what, got_l, want)
-        assert got_o.tobytes() == want.tobytes(), (what, got_o, want)
+        got = np.concatenate([Ho.astype(np.float32).ravel(), co.astype(np.float32)])
+        want = _expected(a, b)
+        assert got.tobytes() == want.tobytes(), (what, got, want)
 
 
-@pytest.mark.parametrize("seed", [1348])
-def test_the_tie_of_seed_1348(seed):
-    c, _ = case(seed)
-    (H, _), _ = exact_relproj(c["src"][0], c["tgt"])
-    v = H[3]
+def test_library_rounds_the_exact_projection():
+    ops = pytest.importorskip("paper_2505_18932_amd.ops")
+    for what, a, b in _pairs():
+        H, c = ops.relative_projection(a, b)
+        got = np.concatenate([np.array(H, np.float32).ravel(), np.array(c, np.float32)])
+        want = _expected(a, b)
+        assert got.tobytes() == want.tobytes(), (what, got, want)
+
+
+def test_the_tie_of_seed_1348():
+    src, tgt = sweep_rig(1348)
+    (H, _), _ = exact_relproj(src[0], tgt)
     lo = np.float32(0.17127085)
     hi = np.nextafter(lo, np.float32(1))
-    assert v == (Fr(float(lo)) + Fr(float(hi))) / 2  # exactly halfway
-    Hl, _ = ops.relative_projection(c["src"][0], c["tgt"])
-    Ho, _ = oracle.relproj(c["src"][0], c["tgt"])
+    assert H[3] == (Fr(float(lo)) + Fr(float(hi))) / 2  # exactly halfway
     even = lo if (lo.view(np.uint32) & 1) == 0 else hi
-    assert np.array(Hl, np.float32).ravel()[3] == even
+    Ho, _ = oracle.relproj(src[0], tgt)
     assert Ho.astype(np.float32).ravel()[3] == even
